@@ -1,0 +1,166 @@
+"""Benchmark of the Lloyd K-means hot path on one MI355X.
+
+One step = one complete kmeans_fit of the HBM-scale workload (N=2e8 points,
+d=3, K=64 isotropic Gaussian mixture, float32 structure-of-arrays, 2.4 GB),
+from a seeded sample of K data points, exactly 50 updates (tol = 0), then the
+final labels against the last centres.  The points are resident in HBM
+before the timed region.  Prints one JSON line with point-iterations/s, the
+roofline position of the dominant kernel (the per-iteration kernel) and the
+CPU oracle's rate on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Published MI355X peaks used for the roofline.
+PEAK_FP32_TFLOPS = 157.3   # FP32 vector (packed FMA = 2 flop per lane)
+PEAK_HBM_GBS = 8000.0
+
+
+def alg_flops_per_point(d: int, K: int) -> int:
+    """FP32 work of one point in one update: per centre d subtractions, d
+    multiplies, d-1 adds and one compare; plus d+1 accumulation adds."""
+    return 3 * d * K + (d + 1)
+
+
+def alg_bytes_per_point(d: int) -> int:
+    """One float32 read per coordinate; labels are written only after the
+    last update and the centres and partials are < 0.1 %."""
+    return 4 * d
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    p = os.path.join(ROOT, "paper_2405_12052_amd", "csrc", "lloyd_kernels.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def traffic_from_profile(name: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source; None otherwise."""
+    p = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(p):
+        return None
+    try:
+        rec = json.load(open(p))
+    except ValueError:
+        return None
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(X, mu0, n_sample: int, target_s: float = 12.0):
+    """The FP64 oracle on the host cores over the first n_sample points of the
+    same data and initial centres; as many updates as fit in ~target_s."""
+    import oracle
+    cores = oracle.threads()
+    Xs = X[:, :n_sample].copy()
+    t = time.perf_counter()
+    oracle.fit(Xs, mu0, tol=0.0, max_iter=1, labels=False)
+    one = time.perf_counter() - t               # one update + one final pass
+    iters = max(1, min(20, int(target_s / max(one / 1.5, 1e-3))))
+    t = time.perf_counter()
+    r = oracle.fit(Xs, mu0, tol=0.0, max_iter=iters, labels=False)
+    el = time.perf_counter() - t
+    assert r["T"] == iters
+    return {"value": n_sample * iters / el, "unit": "point-iters/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"first {n_sample} of the {X.shape[1]} points, same K=64 initial "
+                      f"centres, {iters} float64 updates + final labels, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--iters", type=int, default=50)
+    ap.add_argument("--N", type=int, default=None, help="override N (testing only)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=20_000_000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU data-parallel design is described, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import datagen
+    from paper_2405_12052_amd import KM_OPT_TIMING, KMeans
+
+    s = datagen.spec("C3") if args.N is None else datagen.spec("C3", N=args.N)
+    t0 = time.time()
+    X, _ = datagen.generate(s)
+    mu0 = datagen.init_sample(X, s.N, s.K, s.init_seed)
+    log(f"generated N={s.N} d={s.d} K={s.K} in {time.time() - t0:.1f}s")
+    Xd = torch.from_numpy(X).cuda()
+    torch.cuda.synchronize()
+
+    km = KMeans(0)
+    km.set_option(KM_OPT_TIMING, 1)
+    for i in range(args.warmup):
+        r = km.fit(Xd, mu0, tol=0.0, max_iter=args.iters)
+        log(f"warmup {i}: T={r.iters} J={r.objective:.6e}")
+    torch.cuda.synchronize()
+    kern_ms, kern_n = 0.0, 0
+    t = time.perf_counter()
+    for i in range(args.steps):
+        r = km.fit(Xd, mu0, tol=0.0, max_iter=args.iters)
+        ms, n = km.timing()
+        kern_ms += ms
+        kern_n += n
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    assert r.iters == args.iters
+    log(f"timed {args.steps} fits in {el:.3f}s; iteration kernel {kern_ms / kern_n * 1e3:.1f} us")
+
+    pt_iters = s.N * args.iters * args.steps
+    value = pt_iters / el
+    avg_kernel_s = kern_ms / kern_n / 1e3
+    flops = alg_flops_per_point(s.d, s.K) * s.N
+    achieved = flops / avg_kernel_s / 1e12
+    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS,
+            "traffic": traffic_from_profile("lloyd_iter_C3_traffic.json"),
+            "kernel": "lloyd_iter<3,true>", "avg_launch_us": avg_kernel_s * 1e6,
+            "alg_flops_per_launch": flops,
+            "alg_bytes_per_launch": alg_bytes_per_point(s.d) * s.N,
+            "hbm_gbs_alg": alg_bytes_per_point(s.d) * s.N / avg_kernel_s / 1e9}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        cpu = cpu_baseline(X, mu0, min(args.cpu_sample, s.N))
+        log(f"cpu baseline {cpu['value']:.3e} pt-it/s on {cpu['cores']} threads")
+    out = {
+        "metric": "Lloyd point-iters/s", "value": value, "unit": "point-iters/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"plain Lloyd, HBM scale: N={s.N}, d={s.d}, K={s.K} isotropic "
+                               f"Gaussian mixture, float32 SoA, seeded-sample init, "
+                               f"{args.iters} updates (tol=0) + final labels",
+                   "N": s.N, "d": s.d, "K": s.K, "iterations": args.iters,
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    km.close()
+
+
+if __name__ == "__main__":
+    main()

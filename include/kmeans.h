@@ -1,0 +1,166 @@
+/*
+ * kmeans.h -- C ABI of the MI355X (gfx950) Lloyd K-means library
+ * (libkmeans_mi355x.so).
+ *
+ * The operation is Lloyd's algorithm as defined in the paper's section "The
+ * Lloyd's Algorithm": starting from K initial centres, repeat
+ *   reassignment   z_i = argmin_k ||x_i - mu_k||_2^2            (every point)
+ *   mean           mu_k' = sum_{z_i=k} x_i / #{i : z_i = k}      (every cluster)
+ * and, as in the section "Serial Lloyd's Algorithm", after every update form
+ *   E = sum_k ||mu_k' - mu_k||_2^2
+ * and stop once E is below a tolerance (of the order of 1e-6 in the paper).
+ * The inputs are the data set, the number of clusters and the number of
+ * points; the outputs are the final cluster indicators and means (problem
+ * statement and serial-algorithm sections).
+ *
+ * Conventions shared by every entry point
+ *   - X is caller-owned DEVICE memory: d rows of N float32, row j starting at
+ *     X + j*ld (structure of arrays; the paper's X in R^{d x N}).  ld >= N.
+ *     When X is 16-byte aligned and ld is a multiple of 4 the kernels use
+ *     128-bit loads; otherwise they fall back to 32-bit loads (same results).
+ *   - Centres passed in or out are caller-owned HOST arrays of K*d float64,
+ *     row-major (centre k at [k*d, k*d+d)).  float64 centres make resuming a
+ *     fit from its output exact.
+ *   - Labels are caller-owned DEVICE int32 arrays of N, 0-based (the paper
+ *     numbers clusters 1..K).
+ *   - Distances are evaluated in float32 as (x0-m0)^2 + (x1-m1)^2 [+ (x2-m2)^2]
+ *     against the centres rounded to float32; ties go to the lowest index.
+ *     Per-cluster sums are exact integer sums of the points on a 2^-G grid,
+ *     G chosen from max|x| so that every |x|*2^G < 2^30; the divide, E and the
+ *     tolerance test are float64.  Results do not depend on the launch
+ *     configuration and repeat bit for bit from run to run.
+ *   - An empty cluster keeps its previous centre and is counted.
+ *   - Supported shapes: d in {2, 3}; 1 <= K <= 64; K <= N <= 2^31 - 1.
+ *   - Every call is synchronous with respect to the host: it returns after
+ *     its device work on the context's stream has completed.  There is no
+ *     host synchronisation between iterations of a fit.
+ *   - A context is bound to one device and one HIP stream and is not
+ *     thread-safe; use one context per host thread.
+ *
+ * Errors: every int-returning call returns KM_OK (0) or a negative code.  All
+ * argument validation happens before any device work; on error nothing on
+ * the device has been modified and kmeans_last_error() describes the cause.
+ * Not converging within max_iter is not an error (km_result.converged = 0).
+ */
+#ifndef KMEANS_MI355X_H
+#define KMEANS_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KMEANS_ABI_VERSION 1
+
+typedef struct kmeans_ctx kmeans_ctx;
+
+enum km_status {
+    KM_OK = 0,
+    KM_EINVAL = -1,       /* invalid argument (null pointer, bad size, NaN)   */
+    KM_ENODEV = -2,       /* no usable GPU, or device index out of range      */
+    KM_EHIP = -3,         /* a HIP runtime call failed                        */
+    KM_ENOMEM = -4,       /* device or pinned-host allocation failed          */
+    KM_EUNSUPPORTED = -5  /* d or K outside what the kernels implement        */
+};
+
+/* Outcome of a fit. */
+typedef struct km_result {
+    int32_t iters;        /* T: updates performed (1 <= T <= max_iter)        */
+    int32_t converged;    /* 1 when the last update had E < tol               */
+    double E;             /* E of the last update                             */
+    double shift_l2;      /* sqrt(E): Frobenius norm of the last centre shift */
+    double objective;     /* sum_i min_k ||x_i - mu_k||^2 at the final centres
+                             (float32 distances, summed in float64)           */
+    int64_t empty_events; /* sum over the updates of clusters left empty     */
+} km_result;
+
+/* Options for kmeans_set_option. */
+enum km_option {
+    KM_OPT_GRAPH = 1,     /* 1 (default): replay iterations from a hipGraph;
+                             0: launch each iteration kernel directly          */
+    KM_OPT_UNROLL = 2,    /* iterations per graph launch (0 = automatic)       */
+    KM_OPT_BLOCKS = 3,    /* grid size of the iteration kernel (0 = automatic) */
+    KM_OPT_TIMING = 4     /* 1: time the iteration launches with HIP events
+                             (see kmeans_get_timing)                           */
+};
+
+/*
+ * Create a context on HIP device `device` that enqueues all work on
+ * `hip_stream` (a hipStream_t; NULL = the device's null stream).  `flags` is
+ * reserved and must be 0.  On success *out owns its device workspace, pinned
+ * host staging and graph cache until kmeans_destroy.
+ * Returns KM_ENODEV when no GPU is present or `device` is out of range.
+ */
+int kmeans_create(kmeans_ctx **out, int device, void *hip_stream, uint32_t flags);
+
+/* Release everything the context owns.  NULL is accepted. */
+void kmeans_destroy(kmeans_ctx *ctx);
+
+/* Message describing the last error on `ctx` ("" if none).  Valid until the
+ * next call on the same context.  With ctx == NULL: the last error of a
+ * failed kmeans_create in this thread. */
+const char *kmeans_last_error(const kmeans_ctx *ctx);
+
+/* Static name of a status code. */
+const char *kmeans_status_string(int status);
+
+/* ABI version this library implements (KMEANS_ABI_VERSION). */
+int kmeans_abi_version(void);
+
+/*
+ * Host-only argument check of a fit of N points of dimension d (row stride
+ * ld) into K clusters: the same rules kmeans_fit applies before any device
+ * work.  Needs no GPU.  Returns KM_OK, KM_EINVAL or KM_EUNSUPPORTED.
+ */
+int kmeans_validate(int64_t N, int64_t ld, int32_t d, int32_t K, double tol,
+                    int32_t max_iter);
+
+/*
+ * Reassignment step alone (the paper's step 2) for the given centres:
+ * writes labels[i] = argmin_k ||x_i - mu_k||^2 (if labels != NULL, device)
+ * and *objective = sum_i min_k ||x_i - mu_k||^2 (if objective != NULL, host).
+ * `centroids` is a host array of K*d float64.
+ */
+int kmeans_assign(kmeans_ctx *ctx, const float *X, int64_t N, int64_t ld,
+                  int32_t d, int32_t K, const double *centroids,
+                  int32_t *labels, double *objective);
+
+/*
+ * Lloyd's algorithm (the paper's steps 1-3 with its error test) from the
+ * host centres `init` (K*d float64) until E < tol or max_iter updates.
+ * Writes the final centres to centroids_out (host, K*d float64), the labels
+ * against those final centres to labels_out (device, may be NULL) and the
+ * outcome to *res (may be NULL).
+ * tol must be finite and >= 0 (tol = 0 runs exactly max_iter updates);
+ * max_iter >= 1.  Returns KM_EINVAL (after the run) if X holds a NaN or an
+ * infinity.
+ */
+int kmeans_fit(kmeans_ctx *ctx, const float *X, int64_t N, int64_t ld,
+               int32_t d, int32_t K, const double *init, double tol,
+               int32_t max_iter, double *centroids_out, int32_t *labels_out,
+               km_result *res);
+
+/* Set a km_option on the context.  Returns KM_EINVAL for an unknown option
+ * or a value out of range. */
+int kmeans_set_option(kmeans_ctx *ctx, int32_t option, int64_t value);
+
+/*
+ * Per-update history of the last kmeans_fit on `ctx`: E_t and the objective
+ * J_t of the centres each update started from.  Copies min(cap, T) entries
+ * into E and J (host, either may be NULL) and returns that count (or a
+ * negative status).
+ */
+int kmeans_get_history(kmeans_ctx *ctx, double *E, double *J, int32_t cap);
+
+/*
+ * With KM_OPT_TIMING on: total device time (ms, HIP events on the context's
+ * stream) of the iteration launches of the last kmeans_fit, and the number of
+ * iteration kernels those launches contained.
+ */
+int kmeans_get_timing(kmeans_ctx *ctx, double *iter_ms, int64_t *iter_kernels);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KMEANS_MI355X_H */

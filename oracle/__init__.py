@@ -53,10 +53,12 @@ def _load():
         lib.oracle_step.argtypes = [f32p, C.c_int64, C.c_int64, C.c_int, C.c_int,
                                     f64p, C.c_int, i32p, i64p, f64p, f64p, f64p,
                                     f64p, i64p]
+        lib.oracle_update.argtypes = [f32p, C.c_int64, C.c_int64, C.c_int, C.c_int, i32p,
+                                      f64p, i64p, f64p, f64p, f64p, i64p]
         lib.oracle_fit.argtypes = [f32p, C.c_int64, C.c_int64, C.c_int, C.c_int,
                                    f64p, C.c_double, C.c_int, C.c_int, f64p, i32p,
                                    ip, f64p, f64p, ip, f64p, f64p, i64p]
-        for f in (lib.oracle_assign, lib.oracle_step, lib.oracle_fit):
+        for f in (lib.oracle_assign, lib.oracle_step, lib.oracle_update, lib.oracle_fit):
             f.restype = C.c_int
         _lib = lib
     return _lib
@@ -123,6 +125,28 @@ def step(X, mu, N=None, assign_f32=True):
         raise ValueError(f"oracle_step failed ({rc})")
     return {"labels": labels, "counts": counts, "sums": sums, "mu": nxt,
             "E": E.value, "J": J.value, "empty": emp.value}
+
+
+def update(X, labels, mu, N=None):
+    """Mean step for given labels (0..K-1) from centres mu; returns a dict."""
+    lib = _load()
+    X, N, d, ld = _prep(X, N)
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    K = mu.shape[0]
+    labels = np.ascontiguousarray(labels, dtype=np.int32)
+    assert labels.shape == (N,)
+    counts = np.empty(K, np.int64)
+    sums = np.empty((K, d), np.float64)
+    nxt = np.empty((K, d), np.float64)
+    E = C.c_double()
+    emp = C.c_int64()
+    rc = lib.oracle_update(_ptr(X, C.c_float), N, ld, d, K, _ptr(labels, C.c_int32),
+                           _ptr(mu, C.c_double), _ptr(counts, C.c_int64),
+                           _ptr(sums, C.c_double), _ptr(nxt, C.c_double), C.byref(E),
+                           C.byref(emp))
+    if rc:
+        raise ValueError(f"oracle_update failed ({rc})")
+    return {"counts": counts, "sums": sums, "mu": nxt, "E": E.value, "empty": emp.value}
 
 
 def fit(X, mu0, tol=1e-6, max_iter=100, N=None, assign_f32=True, labels=True):

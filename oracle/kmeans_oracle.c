@@ -119,33 +119,30 @@ int oracle_assign(const float *X, int64_t N, int64_t ld, int d, int K,
 }
 
 /*
- * One Lloyd update from centres mu_t: reassignment, per-cluster counts and
- * sums, the new centres, E_t and the objective J_t = sum_i min_k D_ik of mu_t.
- * Outputs (each may be NULL except mu_next): labels[N], counts[K], sums[K*d],
- * mu_next[K*d], E, J, empty (number of clusters with no point).
+ * Mean-calculation step for given labels: per-cluster counts and sums of the
+ * points, the new centres (an empty cluster keeps mu_t), and
+ * E = sum_k ||mu_next_k - mu_t_k||^2.  counts, sums, E, empty may be NULL.
  */
-int oracle_step(const float *X, int64_t N, int64_t ld, int d, int K,
-                const double *mu_t, int assign_f32, int32_t *labels,
-                int64_t *counts, double *sums, double *mu_next, double *E,
-                double *J, int64_t *empty) {
+int oracle_update(const float *X, int64_t N, int64_t ld, int d, int K,
+                  const int32_t *labels, const double *mu_t, int64_t *counts,
+                  double *sums, double *mu_next, double *E, int64_t *empty) {
     int rc = check_args(X, N, ld, d, K, mu_t);
     if (rc) return rc;
-    if (!mu_next) return OR_EINVAL;
-    int32_t *z = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
-    double *dm = (double *)malloc(sizeof(double) * (size_t)N);
+    if (!labels || !mu_next) return OR_EINVAL;
     nsum *S = (nsum *)calloc((size_t)K * d, sizeof(nsum));
     int64_t *n = (int64_t *)calloc((size_t)K, sizeof(int64_t));
-    if (!z || !dm || !S || !n) {
-        free(z); free(dm); free(S); free(n);
+    if (!S || !n) {
+        free(S); free(n);
         return OR_ENOMEM;
     }
-    oracle_assign(X, N, ld, d, K, mu_t, assign_f32, z, dm, NULL);
-    nsum Jacc = {0.0, 0.0};
     for (int64_t i = 0; i < N; ++i) {
-        int k = z[i];
+        int k = labels[i];
+        if (k < 0 || k >= K) {
+            free(S); free(n);
+            return OR_EINVAL;
+        }
         n[k] += 1;
         for (int j = 0; j < d; ++j) nadd(&S[k * d + j], (double)X[(int64_t)j * ld + i]);
-        nadd(&Jacc, dm[i]);
     }
     int64_t n_empty = 0;
     double Eacc = 0.0;
@@ -161,12 +158,41 @@ int oracle_step(const float *X, int64_t N, int64_t ld, int d, int K,
         if (n[k] == 0) n_empty++;
         if (counts) counts[k] = n[k];
     }
-    if (labels) memcpy(labels, z, sizeof(int32_t) * (size_t)N);
     if (E) *E = Eacc;
-    if (J) *J = nval(&Jacc);
     if (empty) *empty = n_empty;
-    free(z); free(dm); free(S); free(n);
+    free(S); free(n);
     return OR_OK;
+}
+
+/*
+ * One Lloyd update from centres mu_t: the reassignment step, then the mean
+ * step on its labels, and the objective J_t = sum_i min_k D_ik of mu_t.
+ * Outputs (each may be NULL except mu_next): labels[N], counts[K], sums[K*d],
+ * mu_next[K*d], E, J, empty (number of clusters with no point).
+ */
+int oracle_step(const float *X, int64_t N, int64_t ld, int d, int K,
+                const double *mu_t, int assign_f32, int32_t *labels,
+                int64_t *counts, double *sums, double *mu_next, double *E,
+                double *J, int64_t *empty) {
+    int rc = check_args(X, N, ld, d, K, mu_t);
+    if (rc) return rc;
+    if (!mu_next) return OR_EINVAL;
+    int32_t *z = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+    double *dm = (double *)malloc(sizeof(double) * (size_t)N);
+    if (!z || !dm) {
+        free(z); free(dm);
+        return OR_ENOMEM;
+    }
+    oracle_assign(X, N, ld, d, K, mu_t, assign_f32, z, dm, NULL);
+    rc = oracle_update(X, N, ld, d, K, z, mu_t, counts, sums, mu_next, E, empty);
+    if (!rc) {
+        nsum Jacc = {0.0, 0.0};
+        for (int64_t i = 0; i < N; ++i) nadd(&Jacc, dm[i]);
+        if (J) *J = nval(&Jacc);
+        if (labels) memcpy(labels, z, sizeof(int32_t) * (size_t)N);
+    }
+    free(z); free(dm);
+    return rc;
 }
 
 /*

@@ -1,0 +1,67 @@
+// km_internal.h -- device-resident state and launcher declarations shared by
+// the kernels (lloyd_kernels.hip) and the host runtime (kmeans_api.hip).
+// Internal to libkmeans_mi355x.so; the public interface is include/kmeans.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace km {
+
+constexpr int KMAX = 64;          // largest K of a single fit
+constexpr int DMAX = 3;           // points are 2-D or 3-D (problem statement)
+constexpr int BLOCK = 256;        // threads per block of the point kernels
+constexpr int MAX_BLOCKS = 8192;  // grid cap (size of the per-block partials)
+
+// Status flags written by the device.
+enum : int32_t { FLAG_NONFINITE = 1 };
+
+// One fit (or one reassignment pass) lives in this struct in device memory.
+// The host writes the problem fields and the initial centres before the
+// first kernel; afterwards only kernels write it, and the host reads back
+// the progress block with one small copy per batch of iterations.
+struct alignas(16) State {
+    // ---- problem (host-written) ----
+    const float* X;        // d rows of N float32, row j at X + j*ld
+    int64_t N;
+    int64_t ld;
+    int32_t d;
+    int32_t K;
+    double tol;            // stop once E < tol
+    int32_t max_iter;
+    int32_t hist_cap;      // entries of E_hist / J_hist
+    double* jpart;         // [MAX_BLOCKS] per-block objective partials
+    double* E_hist;        // [hist_cap]
+    double* J_hist;        // [hist_cap]
+    // ---- progress (device-written; read back by the host) ----
+    int32_t t;             // updates performed
+    int32_t done;          // 1: no further update runs
+    int32_t flags;         // FLAG_*
+    int32_t G;             // fixed-point exponent of the per-cluster sums
+    double E;              // E of the last update
+    double J;              // objective of the last reassignment-only pass
+    int64_t empty_events;  // clusters left empty, summed over updates
+    // ---- device scratch ----
+    uint32_t absmax_bits;  // max |x| over the data, as float bits
+    uint32_t ticket;       // blocks finished in the current kernel
+    uint32_t scan_ticket;  // blocks finished in the scan kernel
+    uint32_t pad0;
+    // ---- centres ----
+    double mu64[KMAX * DMAX];          // float64 centres, row-major K x d
+    float4 mu32[KMAX];                 // the same rounded to float32, padded
+    unsigned long long acc[KMAX * (DMAX + 1)];  // per-cluster sums | count
+};
+
+// Bytes of State the host uploads (problem, progress and centres) and the
+// progress block it reads back.
+constexpr size_t kUploadBytes = offsetof(State, acc);
+constexpr size_t kProgressOffset = offsetof(State, t);
+constexpr size_t kProgressBytes = offsetof(State, absmax_bits) - offsetof(State, t);
+
+// Launchers (lloyd_kernels.hip).  `vec`: X is 16-byte aligned with ld % 4 == 0.
+hipError_t launch_scan(State* st, int d, bool vec, int grid, hipStream_t s);
+hipError_t launch_iter(State* st, int d, bool vec, int grid, hipStream_t s);
+hipError_t launch_label(State* st, int32_t* labels, int d, bool vec, int grid,
+                        hipStream_t s);
+
+}  // namespace km

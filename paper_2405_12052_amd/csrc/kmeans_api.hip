@@ -1,0 +1,458 @@
+// kmeans_api.hip -- host runtime behind include/kmeans.h: contexts, argument
+// validation, device workspace, the iteration loop (hipGraph replays with one
+// status read-back per batch of iterations) and result read-back.
+#include "../../include/kmeans.h"
+#include "km_internal.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+using km::State;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct GraphKey {
+    int d, vec, grid, unroll;
+    bool operator<(const GraphKey& o) const {
+        return std::tie(d, vec, grid, unroll) < std::tie(o.d, o.vec, o.grid, o.unroll);
+    }
+};
+
+}  // namespace
+
+struct kmeans_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;      // caller's stream: all work goes here
+    hipStream_t cap_stream = nullptr;  // private stream used only for capture
+    int n_cu = 256;
+    State* st = nullptr;               // device state
+    State* st_h = nullptr;             // pinned host staging of the state
+    double* jpart = nullptr;           // [MAX_BLOCKS]
+    double* hist = nullptr;            // [2 * hist_cap]: E then J
+    int hist_cap = 0;
+    double* hist_h = nullptr;          // pinned copy of the history
+    std::string err;
+    // options
+    int use_graph = 1;
+    int unroll = 0;
+    int blocks = 0;
+    int timing = 0;
+    // graph cache
+    std::map<GraphKey, hipGraphExec_t> graphs;
+    // timing of the last fit: one event pair per batch of iterations
+    std::vector<hipEvent_t> ev;
+    double iter_ms = 0.0;
+    int64_t iter_kernels = 0;
+    int last_T = 0;
+};
+
+namespace {
+
+int fail(kmeans_ctx* c, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(kmeans_ctx* c, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    else g_create_error = buf;
+    return code;
+}
+
+#define KM_HIP(ctx, call)                                                               \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(ctx, KM_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));  \
+    } while (0)
+
+int validate(kmeans_ctx* c, int64_t N, int64_t ld, int32_t d, int32_t K, double tol,
+             int32_t max_iter) {
+    if (N < 1 || N > 2147483647LL) return fail(c, KM_EINVAL, "N=%lld out of [1, 2^31-1]", (long long)N);
+    if (ld < N) return fail(c, KM_EINVAL, "ld=%lld < N=%lld", (long long)ld, (long long)N);
+    if (d != 2 && d != 3) return fail(c, KM_EUNSUPPORTED, "d=%d: only 2-D and 3-D points are implemented", d);
+    if (K < 1) return fail(c, KM_EINVAL, "K=%d < 1", K);
+    if (K > km::KMAX) return fail(c, KM_EUNSUPPORTED, "K=%d > %d", K, km::KMAX);
+    if (K > N) return fail(c, KM_EINVAL, "K=%d > N=%lld", K, (long long)N);
+    if (!(tol >= 0.0) || !isfinite(tol)) return fail(c, KM_EINVAL, "tol must be finite and >= 0");
+    if (max_iter < 1) return fail(c, KM_EINVAL, "max_iter=%d < 1", max_iter);
+    return KM_OK;
+}
+
+int check_device_ptr(kmeans_ctx* c, const void* p, const char* what) {
+    if (!p) return fail(c, KM_EINVAL, "%s is NULL", what);
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, KM_EINVAL, "%s is not a HIP device pointer", what);
+    }
+    if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged)
+        return fail(c, KM_EINVAL, "%s must be device memory", what);
+    return KM_OK;
+}
+
+int check_centres(kmeans_ctx* c, const double* m, int K, int d, const char* what) {
+    if (!m) return fail(c, KM_EINVAL, "%s is NULL", what);
+    for (int i = 0; i < K * d; ++i)
+        if (!isfinite(m[i])) return fail(c, KM_EINVAL, "%s[%d] is not finite", what, i);
+    return KM_OK;
+}
+
+int ensure_hist(kmeans_ctx* c, int cap) {
+    if (cap <= c->hist_cap) return KM_OK;
+    int n = c->hist_cap ? c->hist_cap : 256;
+    while (n < cap) n *= 2;
+    double* dv = nullptr;
+    double* hv = nullptr;
+    if (hipMalloc(&dv, sizeof(double) * 2 * (size_t)n) != hipSuccess)
+        return fail(c, KM_ENOMEM, "hipMalloc of the history (%d entries) failed", n);
+    if (hipHostMalloc(&hv, sizeof(double) * 2 * (size_t)n, 0) != hipSuccess) {
+        (void)hipFree(dv);
+        return fail(c, KM_ENOMEM, "hipHostMalloc of the history failed");
+    }
+    if (c->hist) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(c->hist);
+        (void)hipHostFree(c->hist_h);
+    }
+    c->hist = dv;
+    c->hist_h = hv;
+    c->hist_cap = n;
+    return KM_OK;
+}
+
+int ensure_events(kmeans_ctx* c, size_t n) {
+    while (c->ev.size() < n) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return fail(c, KM_EHIP, "hipEventCreate failed");
+        c->ev.push_back(e);
+    }
+    return KM_OK;
+}
+
+bool vec_ok(const float* X, int64_t ld) {
+    return (reinterpret_cast<uintptr_t>(X) & 15u) == 0 && (ld & 3) == 0;
+}
+
+int grid_for(kmeans_ctx* c, int64_t N) {
+    const int64_t groups = (N + 3) / 4;
+    const int64_t need = (groups + km::BLOCK - 1) / km::BLOCK;
+    int64_t cap = c->blocks > 0 ? c->blocks : (int64_t)c->n_cu * 8;
+    if (cap > km::MAX_BLOCKS) cap = km::MAX_BLOCKS;
+    int64_t g = need < cap ? need : cap;
+    return (int)(g < 1 ? 1 : g);
+}
+
+// Fill the host staging copy of the state for a problem and its centres.
+void stage(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, int K,
+           const double* mu, double tol, int max_iter) {
+    State* h = c->st_h;
+    memset(h, 0, km::kUploadBytes);
+    h->X = X;
+    h->N = N;
+    h->ld = ld;
+    h->d = d;
+    h->K = K;
+    h->tol = tol;
+    h->max_iter = max_iter;
+    h->hist_cap = c->hist_cap;
+    h->jpart = c->jpart;
+    h->E_hist = c->hist;
+    h->J_hist = c->hist + c->hist_cap;
+    h->E = INFINITY;
+    for (int k = 0; k < K; ++k) {
+        float m[3] = {0.f, 0.f, 0.f};
+        for (int j = 0; j < d; ++j) {
+            h->mu64[k * d + j] = mu[k * d + j];
+            m[j] = (float)mu[k * d + j];  // round to nearest even
+        }
+        h->mu32[k] = make_float4(m[0], m[1], m[2], 0.f);
+    }
+}
+
+int get_graph(kmeans_ctx* c, int d, bool vec, int grid, int unroll, hipGraphExec_t* out) {
+    GraphKey key{d, vec ? 1 : 0, grid, unroll};
+    auto it = c->graphs.find(key);
+    if (it != c->graphs.end()) {
+        *out = it->second;
+        return KM_OK;
+    }
+    hipGraph_t g = nullptr;
+    KM_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < unroll; ++i) {
+        hipError_t e = km::launch_iter(c->st, d, vec, grid, c->cap_stream);
+        if (e != hipSuccess) {
+            hipGraph_t junk = nullptr;
+            (void)hipStreamEndCapture(c->cap_stream, &junk);
+            if (junk) (void)hipGraphDestroy(junk);
+            return fail(c, KM_EHIP, "capture of the iteration kernel failed: %s", hipGetErrorString(e));
+        }
+    }
+    KM_HIP(c, hipStreamEndCapture(c->cap_stream, &g));
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(c, KM_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    c->graphs[key] = ex;
+    *out = ex;
+    return KM_OK;
+}
+
+int run_iterations(kmeans_ctx* c, int d, bool vec, int grid, int n_iter) {
+    if (c->use_graph) {
+        hipGraphExec_t ex;
+        int rc = get_graph(c, d, vec, grid, n_iter, &ex);
+        if (rc) return rc;
+        KM_HIP(c, hipGraphLaunch(ex, c->stream));
+    } else {
+        for (int i = 0; i < n_iter; ++i) KM_HIP(c, km::launch_iter(c->st, d, vec, grid, c->stream));
+    }
+    return KM_OK;
+}
+
+int auto_unroll(int64_t N, int max_iter) {
+    int u = N >= (1 << 24) ? 10 : (N >= (1 << 20) ? 16 : 32);
+    return u < max_iter ? u : max_iter;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kmeans_abi_version(void) { return KMEANS_ABI_VERSION; }
+
+const char* kmeans_status_string(int s) {
+    switch (s) {
+        case KM_OK: return "KM_OK";
+        case KM_EINVAL: return "KM_EINVAL";
+        case KM_ENODEV: return "KM_ENODEV";
+        case KM_EHIP: return "KM_EHIP";
+        case KM_ENOMEM: return "KM_ENOMEM";
+        case KM_EUNSUPPORTED: return "KM_EUNSUPPORTED";
+        default: return "KM_UNKNOWN";
+    }
+}
+
+int kmeans_validate(int64_t N, int64_t ld, int32_t d, int32_t K, double tol, int32_t max_iter) {
+    kmeans_ctx tmp;
+    return validate(&tmp, N, ld, d, K, tol, max_iter);
+}
+
+const char* kmeans_last_error(const kmeans_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+int kmeans_create(kmeans_ctx** out, int device, void* hip_stream, uint32_t flags) {
+    if (!out) return fail(nullptr, KM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (flags != 0) return fail(nullptr, KM_EINVAL, "flags must be 0");
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n < 1) {
+        (void)hipGetLastError();
+        return fail(nullptr, KM_ENODEV, "no HIP device available (%s)", hipGetErrorString(e));
+    }
+    if (device < 0 || device >= n) return fail(nullptr, KM_ENODEV, "device %d out of range [0, %d)", device, n);
+    if (hipSetDevice(device) != hipSuccess) return fail(nullptr, KM_ENODEV, "hipSetDevice(%d) failed", device);
+    kmeans_ctx* c = new kmeans_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    int rc = KM_OK;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->n_cu = prop.multiProcessorCount;
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        rc = fail(nullptr, KM_EHIP, "stream/event creation failed");
+    } else if (hipMalloc(&c->st, sizeof(State)) != hipSuccess ||
+               hipMalloc(&c->jpart, sizeof(double) * km::MAX_BLOCKS) != hipSuccess) {
+        rc = fail(nullptr, KM_ENOMEM, "hipMalloc of the workspace failed");
+    } else if (hipHostMalloc(&c->st_h, sizeof(State), 0) != hipSuccess) {
+        rc = fail(nullptr, KM_ENOMEM, "hipHostMalloc of the staging buffer failed");
+    } else if (ensure_hist(c, 256) != KM_OK) {
+        rc = fail(nullptr, KM_ENOMEM, "%s", c->err.c_str());
+    }
+    if (rc != KM_OK) {
+        kmeans_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return KM_OK;
+}
+
+void kmeans_destroy(kmeans_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (c->st) (void)hipFree(c->st);
+    if (c->jpart) (void)hipFree(c->jpart);
+    if (c->hist) (void)hipFree(c->hist);
+    if (c->st_h) (void)hipHostFree(c->st_h);
+    if (c->hist_h) (void)hipHostFree(c->hist_h);
+    for (auto& e : c->ev) (void)hipEventDestroy(e);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    delete c;
+}
+
+int kmeans_set_option(kmeans_ctx* c, int32_t option, int64_t value) {
+    if (!c) return KM_EINVAL;
+    switch (option) {
+        case KM_OPT_GRAPH:
+            if (value != 0 && value != 1) return fail(c, KM_EINVAL, "KM_OPT_GRAPH takes 0 or 1");
+            c->use_graph = (int)value;
+            return KM_OK;
+        case KM_OPT_UNROLL:
+            if (value < 0 || value > 1024) return fail(c, KM_EINVAL, "KM_OPT_UNROLL out of [0, 1024]");
+            c->unroll = (int)value;
+            return KM_OK;
+        case KM_OPT_BLOCKS:
+            if (value < 0 || value > km::MAX_BLOCKS) return fail(c, KM_EINVAL, "KM_OPT_BLOCKS out of [0, %d]", km::MAX_BLOCKS);
+            c->blocks = (int)value;
+            return KM_OK;
+        case KM_OPT_TIMING:
+            if (value != 0 && value != 1) return fail(c, KM_EINVAL, "KM_OPT_TIMING takes 0 or 1");
+            c->timing = (int)value;
+            return KM_OK;
+        default:
+            return fail(c, KM_EINVAL, "unknown option %d", option);
+    }
+}
+
+int kmeans_assign(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int32_t d, int32_t K,
+                  const double* centroids, int32_t* labels, double* objective) {
+    if (!c) return KM_EINVAL;
+    c->err.clear();
+    int rc = validate(c, N, ld, d, K, 0.0, 1);
+    if (!rc) rc = check_device_ptr(c, X, "X");
+    if (!rc && labels) rc = check_device_ptr(c, labels, "labels");
+    if (!rc) rc = check_centres(c, centroids, K, d, "centroids");
+    if (rc) return rc;
+    KM_HIP(c, hipSetDevice(c->device));
+    const bool vec = vec_ok(X, ld);
+    const int grid = grid_for(c, N);
+    stage(c, X, N, ld, d, K, centroids, 0.0, 1);
+    KM_HIP(c, hipMemcpyAsync(c->st, c->st_h, km::kUploadBytes, hipMemcpyHostToDevice, c->stream));
+    KM_HIP(c, km::launch_scan(c->st, d, vec, grid, c->stream));
+    KM_HIP(c, km::launch_label(c->st, labels, d, vec, grid, c->stream));
+    KM_HIP(c, hipMemcpyAsync(reinterpret_cast<char*>(c->st_h) + km::kProgressOffset,
+                             reinterpret_cast<char*>(c->st) + km::kProgressOffset,
+                             km::kProgressBytes, hipMemcpyDeviceToHost, c->stream));
+    KM_HIP(c, hipStreamSynchronize(c->stream));
+    if (c->st_h->flags & km::FLAG_NONFINITE) return fail(c, KM_EINVAL, "X holds a NaN or an infinity");
+    if (objective) *objective = c->st_h->J;
+    return KM_OK;
+}
+
+int kmeans_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int32_t d, int32_t K,
+               const double* init, double tol, int32_t max_iter, double* centroids_out,
+               int32_t* labels_out, km_result* res) {
+    if (!c) return KM_EINVAL;
+    c->err.clear();
+    int rc = validate(c, N, ld, d, K, tol, max_iter);
+    if (!rc) rc = check_device_ptr(c, X, "X");
+    if (!rc && labels_out) rc = check_device_ptr(c, labels_out, "labels_out");
+    if (!rc) rc = check_centres(c, init, K, d, "init");
+    if (!rc && !centroids_out) rc = fail(c, KM_EINVAL, "centroids_out is NULL");
+    if (rc) return rc;
+    KM_HIP(c, hipSetDevice(c->device));
+    rc = ensure_hist(c, max_iter);
+    if (rc) return rc;
+    const bool vec = vec_ok(X, ld);
+    const int grid = grid_for(c, N);
+    const int U = c->unroll > 0 ? (c->unroll < max_iter ? c->unroll : max_iter) : auto_unroll(N, max_iter);
+
+    stage(c, X, N, ld, d, K, init, tol, max_iter);
+    KM_HIP(c, hipMemcpyAsync(c->st, c->st_h, km::kUploadBytes, hipMemcpyHostToDevice, c->stream));
+    KM_HIP(c, km::launch_scan(c->st, d, vec, grid, c->stream));
+
+    // Batches of U iterations; the device decides when to stop (kernels after
+    // convergence return at once), the host reads the progress block once per
+    // batch.  With tol == 0 the count is known and there is no read-back.
+    c->iter_ms = 0.0;
+    c->iter_kernels = 0;
+    int launched = 0, batches = 0;
+    State* h = c->st_h;
+    while (launched < max_iter) {
+        const int n = (max_iter - launched) < U ? (max_iter - launched) : U;
+        if (c->timing) {
+            rc = ensure_events(c, 2 * (batches + 1));
+            if (rc) return rc;
+            KM_HIP(c, hipEventRecord(c->ev[2 * batches], c->stream));
+        }
+        rc = run_iterations(c, d, vec, grid, n);
+        if (rc) return rc;
+        if (c->timing) KM_HIP(c, hipEventRecord(c->ev[2 * batches + 1], c->stream));
+        launched += n;
+        batches += 1;
+        if (tol > 0.0 && launched < max_iter) {
+            KM_HIP(c, hipMemcpyAsync(reinterpret_cast<char*>(h) + km::kProgressOffset,
+                                     reinterpret_cast<char*>(c->st) + km::kProgressOffset,
+                                     km::kProgressBytes, hipMemcpyDeviceToHost, c->stream));
+            KM_HIP(c, hipStreamSynchronize(c->stream));
+            if (h->done) break;
+        }
+    }
+    KM_HIP(c, km::launch_label(c->st, labels_out, d, vec, grid, c->stream));
+    KM_HIP(c, hipMemcpyAsync(reinterpret_cast<char*>(h) + km::kProgressOffset,
+                             reinterpret_cast<char*>(c->st) + km::kProgressOffset,
+                             km::kUploadBytes - km::kProgressOffset, hipMemcpyDeviceToHost,
+                             c->stream));
+    KM_HIP(c, hipStreamSynchronize(c->stream));
+    const int T = h->t;
+    c->last_T = T;
+    if (c->timing) {
+        for (int b = 0; b < batches; ++b) {
+            float ms = 0.f;
+            KM_HIP(c, hipEventElapsedTime(&ms, c->ev[2 * b], c->ev[2 * b + 1]));
+            c->iter_ms += ms;
+        }
+        c->iter_kernels = launched;
+    }
+    const int nh = T < c->hist_cap ? T : c->hist_cap;
+    if (nh > 0) {
+        KM_HIP(c, hipMemcpyAsync(c->hist_h, c->hist, sizeof(double) * (size_t)nh,
+                                 hipMemcpyDeviceToHost, c->stream));
+        KM_HIP(c, hipMemcpyAsync(c->hist_h + c->hist_cap, c->hist + c->hist_cap,
+                                 sizeof(double) * (size_t)nh, hipMemcpyDeviceToHost, c->stream));
+        KM_HIP(c, hipStreamSynchronize(c->stream));
+    }
+    if (h->flags & km::FLAG_NONFINITE) return fail(c, KM_EINVAL, "X holds a NaN or an infinity");
+    memcpy(centroids_out, h->mu64, sizeof(double) * (size_t)K * d);
+    if (res) {
+        res->iters = T;
+        res->converged = h->E < tol ? 1 : 0;
+        res->E = h->E;
+        res->shift_l2 = sqrt(h->E);
+        res->objective = h->J;
+        res->empty_events = h->empty_events;
+    }
+    return KM_OK;
+}
+
+int kmeans_get_history(kmeans_ctx* c, double* E, double* J, int32_t cap) {
+    if (!c || cap < 0) return KM_EINVAL;
+    int n = c->last_T < cap ? c->last_T : cap;
+    if (n > c->hist_cap) n = c->hist_cap;
+    if (E) memcpy(E, c->hist_h, sizeof(double) * (size_t)n);
+    if (J) memcpy(J, c->hist_h + c->hist_cap, sizeof(double) * (size_t)n);
+    return n;
+}
+
+int kmeans_get_timing(kmeans_ctx* c, double* iter_ms, int64_t* iter_kernels) {
+    if (!c) return KM_EINVAL;
+    if (iter_ms) *iter_ms = c->iter_ms;
+    if (iter_kernels) *iter_kernels = c->iter_kernels;
+    return KM_OK;
+}
+
+}  // extern "C"

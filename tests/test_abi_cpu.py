@@ -1,0 +1,93 @@
+"""The C-ABI library without a GPU: it loads, exports every entry point that
+include/kmeans.h declares, validates arguments on the host, and reports the
+absence of a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2405_12052_amd as km
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(kmeans_\w+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = km.load_library()
+    names = declared_functions()
+    assert {"kmeans_create", "kmeans_fit", "kmeans_assign"} <= names
+    for n in names:
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", km.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (kmeans_\w+)", out))
+    assert names <= exported
+    assert exported <= names, f"undeclared exports: {exported - names}"
+
+
+def test_abi_version():
+    assert km.load_library().kmeans_abi_version() == 1
+
+
+@pytest.mark.parametrize("args,code", [
+    ((100, 100, 3, 4, 1e-6, 10), km.KM_OK),
+    ((100, 128, 2, 64, 0.0, 1), km.KM_OK),
+    ((100, 100, 4, 4, 1e-6, 10), km.KM_EUNSUPPORTED),
+    ((100, 100, 1, 4, 1e-6, 10), km.KM_EUNSUPPORTED),
+    ((100, 100, 3, 65, 1e-6, 10), km.KM_EUNSUPPORTED),
+    ((10, 10, 2, 11, 1e-6, 10), km.KM_EINVAL),
+    ((0, 0, 2, 1, 1e-6, 10), km.KM_EINVAL),
+    ((100, 99, 2, 4, 1e-6, 10), km.KM_EINVAL),
+    ((100, 100, 2, 0, 1e-6, 10), km.KM_EINVAL),
+    ((100, 100, 2, 4, -1.0, 10), km.KM_EINVAL),
+    ((100, 100, 2, 4, float("nan"), 10), km.KM_EINVAL),
+    ((100, 100, 2, 4, float("inf"), 10), km.KM_EINVAL),
+    ((100, 100, 2, 4, 1e-6, 0), km.KM_EINVAL),
+    ((2 ** 31, 2 ** 31, 2, 4, 1e-6, 10), km.KM_EINVAL),
+])
+def test_host_validation(args, code):
+    assert km.validate(*args) == code
+
+
+def test_status_strings():
+    lib = km.load_library()
+    assert lib.kmeans_status_string(km.KM_EUNSUPPORTED) == b"KM_EUNSUPPORTED"
+    assert lib.kmeans_status_string(7) == b"KM_UNKNOWN"
+
+
+def test_create_without_gpu_reports_enodev():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    lib = km.load_library()
+    ctx = ctypes.c_void_p()
+    assert lib.kmeans_create(ctypes.byref(ctx), 0, None, 0) == km.KM_ENODEV
+    assert ctx.value is None
+    assert b"no HIP device" in lib.kmeans_last_error(None)
+    assert lib.kmeans_create(ctypes.byref(ctx), 0, None, 1) == km.KM_EINVAL
+    lib.kmeans_destroy(None)                      # accepted
+
+
+def test_null_context_is_rejected():
+    lib = km.load_library()
+    assert lib.kmeans_fit(None, None, 10, 10, 2, 2, None, 1e-6, 10, None, None, None) == km.KM_EINVAL
+    assert lib.kmeans_set_option(None, 1, 1) == km.KM_EINVAL
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_2405_12052_amd import _binding
+    monkeypatch.setattr(_binding, "_lib", None)
+    monkeypatch.setattr(_binding, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        _binding.load_library()

@@ -1,0 +1,261 @@
+"""GPU parity of the Lloyd path (through the C ABI) against the FP64 oracle,
+at sizes the oracle finishes in seconds that span many tiles and ragged tails,
+plus determinism, schedule independence, resume and the error paths."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from parity import centre_check, e_check, label_check
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def km():
+    from paper_2405_12052_amd import KMeans
+    k = KMeans(0)
+    yield k
+    k.close()
+
+
+def data(name, **kw):
+    s = datagen.spec(name, **kw)
+    X, meta = datagen.generate(s)
+    return s, X, torch.from_numpy(X).cuda()
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+# --------------------------------------------------------------- reassignment
+@pytest.mark.parametrize("d,K,N", [(2, 1, 1), (2, 4, 1003), (3, 16, 50_003), (3, 64, 200_001),
+                                   (2, 64, 64), (3, 5, 5), (2, 33, 100_000)])
+def test_assign_matches_oracle(km, d, K, N):
+    log(f"assign d={d} K={K} N={N}")
+    s, X, Xd = data("C2", N=N, d=d, K=max(K, 2), seed=4000 + K + N)
+    mu = datagen.init_sample(X, N, K, 7)
+    mu += np.random.default_rng(1).normal(size=mu.shape) * 0.37   # centres off the data
+    lab, J = km.assign(Xd, mu)
+    mism, near, _, _ = label_check(lab.cpu().numpy(), X, mu)
+    _, dmin, _ = oracle.assign(X, mu)
+    assert abs(J - dmin.sum()) <= 1e-6 * dmin.sum() + 1e-12
+    log(f"  mismatches {mism} (near-ties {near})")
+
+
+# -------------------------------------------------------------- step parity
+@pytest.mark.parametrize("name,kw,steps", [
+    ("C1", {}, 30),
+    ("C5", {"N": 400_001}, 12),
+    ("C3", {"N": 1_000_003}, 6),
+])
+def test_stepwise_parity(km, name, kw, steps):
+    """Feed the GPU's float64 centres mu^t to the oracle each step and compare
+    labels, mu^{t+1} and E_t."""
+    s, X, Xd = data(name, **kw)
+    mu = datagen.init_sample(X, s.N, s.K, s.init_seed)
+    worst_c, worst_e, total_mism = 0.0, 0.0, 0
+    for t in range(steps):
+        lab, _ = km.assign(Xd, mu)
+        gl = lab.cpu().numpy()
+        mism, _, _, _ = label_check(gl, X, mu)
+        total_mism += mism
+        r = km.fit(Xd, mu, tol=0.0, max_iter=1, labels=False)
+        ref = oracle.update(X, gl, mu)          # mean step on the (valid) GPU labels
+        worst_c = max(worst_c, centre_check(r.centroids, ref["mu"]))
+        worst_e = max(worst_e, e_check(r.E, ref["E"]))
+        assert r.iters == 1 and r.empty_events == ref["empty"]
+        mu = r.centroids
+    log(f"{name} {kw}: {steps} steps, max centre err {worst_c:.2e}, max |dE| {worst_e:.2e}, "
+        f"excused label mismatches {total_mism}")
+
+
+# ---------------------------------------------------------------- end to end
+@pytest.mark.parametrize("name,kw", [("C1", {}), ("C5", {"N": 300_000}),
+                                     ("C2", {"N": 200_000, "d": 2, "K": 9})])
+def test_fit_end_to_end(km, name, kw):
+    s, X, Xd = data(name, **kw)
+    mu0 = datagen.init_sample(X, s.N, s.K, s.init_seed)
+    r = km.fit(Xd, mu0, tol=s.tol, max_iter=s.max_iter)
+    ref = oracle.fit(X, mu0, tol=s.tol, max_iter=s.max_iter)
+    log(f"{name}: T gpu {r.iters} oracle {ref['T']}, E {r.E:.3e}/{ref['E']:.3e}, "
+        f"J {r.objective:.9e}/{ref['J']:.9e}")
+    try:
+        assert r.iters == ref["T"] and r.converged == ref["converged"]
+        centre_check(r.centroids, ref["mu"])
+        e_check(r.E, ref["E"])
+        assert abs(r.objective - ref["J"]) <= 1e-6 * ref["J"]
+        assert r.empty_events == ref["empty_events"]
+    except AssertionError:
+        # Trajectories may part at an excused near-tie; then the first step
+        # where they part must show a label flip inside the near-tie window.
+        t = first_divergence(km, X, Xd, mu0, max(r.iters, ref["T"]))
+        log(f"{name}: trajectories part at update {t}: an excused near-tie flip")
+        return
+    label_check(r.labels.cpu().numpy(), X, r.centroids)
+    Eh, Jh = km.history()
+    assert len(Eh) == r.iters
+    assert np.all(np.abs(Eh - ref["E_hist"]) <= 1e-6)
+    assert np.all(np.abs(Jh - ref["J_hist"]) <= 1e-6 * ref["J_hist"])
+
+
+def first_divergence(km, X, Xd, mu0, T):
+    """First update t whose GPU centres leave the oracle's tolerance when both
+    start from the same mu^{t-1}; asserts the step had an excused label flip."""
+    mu_ref = mu0
+    for t in range(1, T + 1):
+        g = km.fit(Xd, mu0, tol=0.0, max_iter=t, labels=False).centroids
+        prev = km.fit(Xd, mu0, tol=0.0, max_iter=t - 1, labels=False).centroids if t > 1 else mu0
+        o = oracle.step(X, prev)
+        try:
+            centre_check(g, o["mu"])
+        except AssertionError:
+            lab, _ = km.assign(Xd, prev)
+            mism, _, _, _ = label_check(lab.cpu().numpy(), X, prev)
+            assert mism > 0, f"update {t} differs without a label flip"
+            return t
+        mu_ref = o["mu"]
+    raise AssertionError("results differ but no step diverges")
+
+
+# -------------------------------------------------------------- determinism
+def test_bitwise_repeat_and_schedule_independence(km):
+    from paper_2405_12052_amd import KM_OPT_BLOCKS, KM_OPT_GRAPH, KM_OPT_UNROLL
+    s, X, Xd = data("C5", N=2_000_000)
+    mu0 = datagen.init_sample(X, s.N, s.K, s.init_seed)
+    base = km.fit(Xd, mu0, tol=1e-6, max_iter=40)
+    runs = []
+    for graph, unroll, blocks in [(1, 0, 0), (0, 0, 0), (1, 3, 7), (1, 1, 100), (0, 0, 513)]:
+        km.set_option(KM_OPT_GRAPH, graph)
+        km.set_option(KM_OPT_UNROLL, unroll)
+        km.set_option(KM_OPT_BLOCKS, blocks)
+        runs.append(((graph, unroll, blocks), km.fit(Xd, mu0, tol=1e-6, max_iter=40)))
+    km.set_option(KM_OPT_GRAPH, 1)
+    km.set_option(KM_OPT_UNROLL, 0)
+    km.set_option(KM_OPT_BLOCKS, 0)
+    bl = base.labels.cpu().numpy()
+    for cfg, r in runs:
+        assert r.iters == base.iters, cfg
+        assert np.array_equal(r.centroids, base.centroids), cfg
+        assert r.E == base.E, cfg
+        assert np.array_equal(r.labels.cpu().numpy(), bl), cfg
+        assert abs(r.objective - base.objective) <= 1e-12 * base.objective, cfg
+
+
+def test_resume_equals_one_long_run(km):
+    s, X, Xd = data("C5", N=500_000)
+    mu0 = datagen.init_sample(X, s.N, s.K, s.init_seed)
+    a = km.fit(Xd, mu0, tol=0.0, max_iter=7)
+    b = km.fit(Xd, a.centroids, tol=0.0, max_iter=5)
+    c = km.fit(Xd, mu0, tol=0.0, max_iter=12)
+    assert np.array_equal(b.centroids, c.centroids)
+    assert b.E == c.E and not c.converged and c.iters == 12
+    assert np.array_equal(b.labels.cpu().numpy(), c.labels.cpu().numpy())
+
+
+# --------------------------------------------------------------- edge cases
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 6, 7, 4097])
+def test_tiny_and_ragged(km, N):
+    rng = np.random.default_rng(N)
+    X = rng.normal(size=(3, N)).astype(np.float32) * 10
+    K = min(N, 3)
+    mu0 = X[:, :K].T.astype(np.float64)
+    r = km.fit(torch.from_numpy(X).cuda(), mu0, tol=1e-6, max_iter=50)
+    ref = oracle.fit(X, mu0, tol=1e-6, max_iter=50)
+    assert r.iters == ref["T"]
+    centre_check(r.centroids, ref["mu"])
+    assert np.array_equal(r.labels.cpu().numpy(), ref["labels"])
+
+
+def test_unaligned_rows_use_the_scalar_path(km):
+    s, X, _ = data("C5", N=100_001)
+    big = np.zeros((3, 100_003), np.float32)
+    big[:, 1:100_002] = X
+    Xd = torch.from_numpy(big).cuda()[:, 1:]            # row start off 16 bytes, odd ld
+    assert Xd.data_ptr() % 16 != 0 and Xd.stride(0) % 4 != 0
+    mu0 = datagen.init_sample(X, s.N, s.K, s.init_seed)
+    r = km.fit(Xd, mu0, tol=1e-6, max_iter=60, N=s.N)
+    a = km.fit(torch.from_numpy(X).cuda(), mu0, tol=1e-6, max_iter=60)
+    assert np.array_equal(r.centroids, a.centroids) and r.iters == a.iters
+
+
+def test_empty_clusters_and_duplicates(km):
+    s, X, Xd = data("C1", N=50_000)
+    mu0 = datagen.init_sample(X, s.N, 4, s.init_seed)
+    mu0 = np.vstack([mu0, mu0[1:2], [[1e6, -1e6]]])     # a duplicate and a far centre
+    r = km.fit(Xd, mu0, tol=1e-6, max_iter=100)
+    ref = oracle.fit(X, mu0, tol=1e-6, max_iter=100)
+    assert r.iters == ref["T"] and r.empty_events == ref["empty_events"] > 0
+    centre_check(r.centroids, ref["mu"])
+    assert np.array_equal(r.centroids[5], mu0[5])
+
+
+def test_k_equals_n_and_k1(km):
+    X = np.random.default_rng(0).normal(size=(2, 64)).astype(np.float32)
+    Xd = torch.from_numpy(X).cuda()
+    r = km.fit(Xd, X.T.astype(np.float64), tol=1e-6, max_iter=5)
+    # each point is its own cluster: the new centres are the points up to the
+    # 2^-G grid of the sums, so E is tiny but need not be exactly 0
+    assert r.iters == 1 and r.E < 1e-12 and np.array_equal(r.labels.cpu().numpy(), np.arange(64))
+    r1 = km.fit(Xd, np.zeros((1, 2)), tol=1e-6, max_iter=5)
+    ref = oracle.fit(X, np.zeros((1, 2)), tol=1e-6, max_iter=5)
+    assert r1.iters == ref["T"] == 2
+    centre_check(r1.centroids, ref["mu"])
+
+
+# ------------------------------------------------------------------- errors
+def test_error_paths(km):
+    from paper_2405_12052_amd import (KM_EINVAL, KM_EUNSUPPORTED, KMeansError)
+    X = np.random.default_rng(0).normal(size=(3, 1000)).astype(np.float32)
+    Xd = torch.from_numpy(X).cuda()
+    mu = X[:, :4].T.astype(np.float64)
+    for bad_mu, n, code in [(np.zeros((65, 3)), 1000, KM_EUNSUPPORTED),
+                            (np.zeros((11, 3)), 10, KM_EINVAL)]:
+        with pytest.raises(KMeansError) as e:
+            km.fit(Xd, bad_mu, N=n)
+        assert e.value.code == code
+    with pytest.raises(KMeansError) as e:
+        km.fit(Xd, mu, tol=-1.0)
+    assert e.value.code == KM_EINVAL
+    m2 = mu.copy()
+    m2[0, 0] = np.nan
+    with pytest.raises(KMeansError) as e:
+        km.fit(Xd, m2)
+    assert e.value.code == KM_EINVAL
+    Xn = X.copy()
+    Xn[1, 777] = np.nan
+    with pytest.raises(KMeansError, match="NaN") as e:
+        km.fit(torch.from_numpy(Xn).cuda(), mu)
+    assert e.value.code == KM_EINVAL
+    Xi = X.copy()
+    Xi[2, 5] = np.inf
+    with pytest.raises(KMeansError) as e:
+        km.assign(torch.from_numpy(Xi).cuda(), mu)
+    assert e.value.code == KM_EINVAL
+    # a host pointer for X
+    out = np.empty((4, 3))
+    rc = km._lib.kmeans_fit(km._ctx, X.ctypes.data, 1000, 1000, 3, 4,
+                            mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 1e-6, 10,
+                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None, None)
+    assert rc == KM_EINVAL
+    # the context still works afterwards
+    r = km.fit(Xd, mu, tol=1e-6, max_iter=20)
+    ref = oracle.fit(X, mu, tol=1e-6, max_iter=20)
+    centre_check(r.centroids, ref["mu"])
+
+
+def test_timing_counts_iteration_kernels(km):
+    from paper_2405_12052_amd import KM_OPT_TIMING
+    s, X, Xd = data("C5", N=1_000_000)
+    mu0 = datagen.init_sample(X, s.N, s.K, s.init_seed)
+    km.set_option(KM_OPT_TIMING, 1)
+    r = km.fit(Xd, mu0, tol=0.0, max_iter=20)
+    ms, n = km.timing()
+    km.set_option(KM_OPT_TIMING, 0)
+    assert n == 20 and ms > 0
+    log(f"C5-size iteration: {ms / n * 1e3:.1f} us/iter, {s.N * n / ms * 1e3:.3e} pt-it/s")
