@@ -11,7 +11,11 @@ namespace km {
 constexpr int KMAX = 64;          // largest K of a single fit
 constexpr int DMAX = 3;           // points are 2-D or 3-D (problem statement)
 constexpr int BLOCK = 256;        // threads per block of the point kernels
-constexpr int MAX_BLOCKS = 8192;  // grid cap (size of the per-block partials)
+constexpr int MAX_BLOCKS = 4096;  // grid cap (size of the per-block partials)
+constexpr int GROUP = 32;         // blocks per first-level reduction group
+constexpr int MAX_GROUPS = MAX_BLOCKS / GROUP;
+constexpr int KPAD = 66;          // KMAX rounded up to whole triples of centres
+constexpr int PART = KMAX * (DMAX + 1);  // int64 slots of one block partial
 
 // Status flags written by the device.
 enum : int32_t { FLAG_NONFINITE = 1 };
@@ -31,6 +35,10 @@ struct alignas(16) State {
     int32_t max_iter;
     int32_t hist_cap;      // entries of E_hist / J_hist
     double* jpart;         // [MAX_BLOCKS] per-block objective partials
+    unsigned long long* part;   // [MAX_BLOCKS][PART] per-block sums | counts
+    unsigned long long* gpart;  // [MAX_GROUPS][PART] per-group sums | counts
+    double* gjpart;        // [MAX_GROUPS] per-group objective partials
+    uint32_t* gticket;     // [MAX_GROUPS] blocks finished per group
     double* E_hist;        // [hist_cap]
     double* J_hist;        // [hist_cap]
     // ---- progress (device-written; read back by the host) ----
@@ -41,6 +49,8 @@ struct alignas(16) State {
     double E;              // E of the last update
     double J;              // objective of the last reassignment-only pass
     int64_t empty_events;  // clusters left empty, summed over updates
+    float minus_inf;       // -infinity, read at run time by the kernels
+    int32_t pad1;
     // ---- device scratch ----
     uint32_t absmax_bits;  // max |x| over the data, as float bits
     uint32_t ticket;       // blocks finished in the current kernel
@@ -49,12 +59,15 @@ struct alignas(16) State {
     // ---- centres ----
     double mu64[KMAX * DMAX];          // float64 centres, row-major K x d
     float4 mu32[KMAX];                 // the same rounded to float32, padded
-    unsigned long long acc[KMAX * (DMAX + 1)];  // per-cluster sums | count
+    // ---- derived from mu32 on the device before each reassignment ----
+    float4 cand[KPAD];                 // {-2 m0, -2 m1, -2 m2, fl32(|m|^2)}; pads
+                                       // {0, 0, 0, +inf} up to a whole triple
+    float4 bnd;                        // {2^-20 Cmax, 2^-19 A0, 2^-19 A1, 2^-19 A2}
 };
 
 // Bytes of State the host uploads (problem, progress and centres) and the
 // progress block it reads back.
-constexpr size_t kUploadBytes = offsetof(State, acc);
+constexpr size_t kUploadBytes = offsetof(State, cand);
 constexpr size_t kProgressOffset = offsetof(State, t);
 constexpr size_t kProgressBytes = offsetof(State, absmax_bits) - offsetof(State, t);
 

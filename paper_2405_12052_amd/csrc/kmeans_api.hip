@@ -37,6 +37,10 @@ struct kmeans_ctx {
     State* st = nullptr;               // device state
     State* st_h = nullptr;             // pinned host staging of the state
     double* jpart = nullptr;           // [MAX_BLOCKS]
+    unsigned long long* part = nullptr;   // [MAX_BLOCKS][PART]
+    unsigned long long* gpart = nullptr;  // [MAX_GROUPS][PART]
+    double* gjpart = nullptr;          // [MAX_GROUPS]
+    uint32_t* gticket = nullptr;       // [MAX_GROUPS]
     double* hist = nullptr;            // [2 * hist_cap]: E then J
     int hist_cap = 0;
     double* hist_h = nullptr;          // pinned copy of the history
@@ -167,9 +171,14 @@ void stage(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, int K,
     h->max_iter = max_iter;
     h->hist_cap = c->hist_cap;
     h->jpart = c->jpart;
+    h->part = c->part;
+    h->gpart = c->gpart;
+    h->gjpart = c->gjpart;
+    h->gticket = c->gticket;
     h->E_hist = c->hist;
     h->J_hist = c->hist + c->hist_cap;
     h->E = INFINITY;
+    h->minus_inf = -INFINITY;
     for (int k = 0; k < K; ++k) {
         float m[3] = {0.f, 0.f, 0.f};
         for (int j = 0; j < d; ++j) {
@@ -274,8 +283,15 @@ int kmeans_create(kmeans_ctx** out, int device, void* hip_stream, uint32_t flags
     if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         rc = fail(nullptr, KM_EHIP, "stream/event creation failed");
     } else if (hipMalloc(&c->st, sizeof(State)) != hipSuccess ||
-               hipMalloc(&c->jpart, sizeof(double) * km::MAX_BLOCKS) != hipSuccess) {
+               hipMalloc(&c->jpart, sizeof(double) * km::MAX_BLOCKS) != hipSuccess ||
+               hipMalloc(&c->part, sizeof(unsigned long long) * km::PART * km::MAX_BLOCKS) != hipSuccess ||
+               hipMalloc(&c->gpart, sizeof(unsigned long long) * km::PART * km::MAX_GROUPS) != hipSuccess ||
+               hipMalloc(&c->gjpart, sizeof(double) * km::MAX_GROUPS) != hipSuccess ||
+               hipMalloc(&c->gticket, sizeof(uint32_t) * km::MAX_GROUPS) != hipSuccess) {
         rc = fail(nullptr, KM_ENOMEM, "hipMalloc of the workspace failed");
+    } else if (hipMemset(c->gticket, 0, sizeof(uint32_t) * km::MAX_GROUPS) != hipSuccess ||
+               hipDeviceSynchronize() != hipSuccess) {
+        rc = fail(nullptr, KM_EHIP, "clearing the workspace failed");
     } else if (hipHostMalloc(&c->st_h, sizeof(State), 0) != hipSuccess) {
         rc = fail(nullptr, KM_ENOMEM, "hipHostMalloc of the staging buffer failed");
     } else if (ensure_hist(c, 256) != KM_OK) {
@@ -296,6 +312,10 @@ void kmeans_destroy(kmeans_ctx* c) {
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     if (c->st) (void)hipFree(c->st);
     if (c->jpart) (void)hipFree(c->jpart);
+    if (c->part) (void)hipFree(c->part);
+    if (c->gpart) (void)hipFree(c->gpart);
+    if (c->gjpart) (void)hipFree(c->gjpart);
+    if (c->gticket) (void)hipFree(c->gticket);
     if (c->hist) (void)hipFree(c->hist);
     if (c->st_h) (void)hipHostFree(c->st_h);
     if (c->hist_h) (void)hipHostFree(c->hist_h);

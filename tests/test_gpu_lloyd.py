@@ -48,6 +48,30 @@ def test_assign_matches_oracle(km, d, K, N):
     log(f"  mismatches {mism} (near-ties {near})")
 
 
+@pytest.mark.parametrize("d", [2, 3])
+def test_exact_ties_take_the_rescan_path(km, d):
+    """Integer points and half-integer centres: a large share of the points
+    are exactly equidistant from two or more centres, so they fail the
+    certificate and go through the per-wave re-scan queue; ties must still go
+    to the lowest index, exactly as in the oracle."""
+    rng = np.random.default_rng(40 + d)
+    N = 300_001
+    X = rng.integers(-6, 7, size=(d, N)).astype(np.float32)
+    K = 40
+    mu = (rng.integers(-6, 6, size=(K, d)) + 0.5).astype(np.float64)
+    mu[:, 0] = np.round(mu[:, 0])          # ties along the other axes
+    Xd = torch.from_numpy(X).cuda()
+    lab, J = km.assign(Xd, mu)
+    ref, dmin, dsec = oracle.assign(X, mu)
+    assert (dsec == dmin).mean() > 0.1       # the case really is tie-heavy
+    assert np.array_equal(lab.cpu().numpy(), ref)
+    assert J == pytest.approx(dmin.sum(), rel=1e-12)
+    r = km.fit(Xd, mu, tol=0.0, max_iter=1, labels=False)
+    o = oracle.update(X, ref, mu)
+    centre_check(r.centroids, o["mu"])
+    e_check(r.E, o["E"])
+
+
 # -------------------------------------------------------------- step parity
 @pytest.mark.parametrize("name,kw,steps", [
     ("C1", {}, 30),
