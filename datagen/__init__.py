@@ -33,7 +33,7 @@ import numpy as np
 
 __all__ = [
     "MixtureSpec", "CONFIGS", "spec", "generate", "init_sample", "batched_specs",
-    "round_up",
+    "batched_generate", "round_up",
 ]
 
 
@@ -186,3 +186,29 @@ def batched_specs(n_inst: int = 4096, seed: int = 20240504, restarts: int = 8,
             init_seed=seed * 104729 + i, max_iter=300,
             extra={"restart_seeds": [seed * 104729 + i * 131 + r for r in range(restarts)]}))
     return specs
+
+
+def batched_generate(specs, restarts=None, threads=None):
+    """Points and restart initialisations of a batch.
+
+    Returns (flat, offsets, inits): flat is one float32 array holding every
+    instance's (d, round_up(N, 4)) rows back to back (each instance starts at a
+    multiple of 4 floats, so its rows are 16-byte aligned when the buffer is);
+    offsets[i] is instance i's first element; inits[i] has shape (R, K, d), the
+    R seeded samples of K distinct points (R = len(restart_seeds) unless
+    `restarts` overrides it)."""
+    offsets, total = [], 0
+    for s in specs:
+        offsets.append(total)
+        total += s.d * round_up(s.N, 4)
+    flat = np.zeros(total, dtype=np.float32)
+    inits = []
+    for s, off in zip(specs, offsets):
+        ld = round_up(s.N, 4)
+        X, _ = generate(s, ld=ld, threads=threads)
+        flat[off:off + s.d * ld] = X.reshape(-1)
+        seeds = s.extra.get("restart_seeds", [s.init_seed])
+        if restarts is not None:
+            seeds = [seeds[i % len(seeds)] + 7 * (i // len(seeds)) for i in range(restarts)]
+        inits.append(np.stack([init_sample(X, s.N, s.K, sd) for sd in seeds]))
+    return flat, offsets, inits

@@ -30,7 +30,8 @@
  *     tolerance test are float64.  Results do not depend on the launch
  *     configuration and repeat bit for bit from run to run.
  *   - An empty cluster keeps its previous centre and is counted.
- *   - Supported shapes: d in {2, 3}; 1 <= K <= 64; K <= N <= 2^31 - 1.
+ *   - Supported shapes: d in {2, 3}; 1 <= K <= 64; K <= N <= 2^31 - 1
+ *     (kmeans_fit_batched: K <= 32, N <= 2^27, up to 8 restarts).
  *   - Every call is synchronous with respect to the host: it returns after
  *     its device work on the context's stream has completed.  There is no
  *     host synchronisation between iterations of a fit.
@@ -159,6 +160,65 @@ int kmeans_get_history(kmeans_ctx *ctx, double *E, double *J, int32_t cap);
  * iteration kernels those launches contained.
  */
 int kmeans_get_timing(kmeans_ctx *ctx, double *iter_ms, int64_t *iter_kernels);
+
+/* ---------------------------------------------------------- batched fits */
+
+/* One instance of a batched fit: its own points and K, and n_restarts
+ * independent Lloyd runs from different initial centres, of which the one
+ * with the smallest final objective is kept. */
+typedef struct km_instance {
+    const float *X;             /* device, d rows of N float32, row stride ld  */
+    int64_t N;
+    int64_t ld;
+    int32_t d;                  /* 2 or 3                                       */
+    int32_t K;                  /* 1..32                                        */
+    int32_t n_restarts;         /* 1..8                                         */
+    const double *init;         /* host, n_restarts*K*d initial centres          */
+    double *centroids_out;      /* host, K*d: final centres of the kept restart  */
+    int32_t *labels_out;        /* device, N labels of the kept restart, or NULL */
+    double *restart_objective;  /* host, n_restarts final objectives, or NULL    */
+    int32_t best_restart;       /* out: index of the kept restart                */
+    km_result res;              /* out: outcome of the kept restart              */
+} km_instance;
+
+/* Launch schedule of kmeans_fit_batched (see kmeans_tune_batched). */
+typedef struct km_schedule {
+    int32_t team_size;          /* blocks that share one large instance (1..16; 1 = no teams) */
+    int32_t blocks_per_cu;      /* persistent grid = blocks_per_cu x compute units (capped by
+                                   occupancy)                                       */
+    double big_work;            /* instances with N*K*n_restarts >= big_work go to teams */
+} km_schedule;
+
+/*
+ * Many independent fits in one persistent launch (the points of every
+ * instance must stay valid until the call returns).  Every restart follows
+ * exactly the iteration of kmeans_fit (same labels, centres, E and T as a
+ * kmeans_fit from the same initial centres, tol and max_iter); afterwards the
+ * objective of each restart is evaluated at its final centres and the
+ * smallest is kept (lowest restart index on ties).  Constraints per
+ * instance: d in {2, 3}, 1 <= K <= 32, K <= N <= 2^27, 1 <= n_restarts <= 8,
+ * ld >= N.  Returns KM_EINVAL if any instance holds a NaN or an infinity
+ * (after the run; the other instances' outputs are valid).
+ */
+int kmeans_fit_batched(kmeans_ctx *ctx, int32_t n_inst, km_instance *inst, double tol,
+                       int32_t max_iter);
+
+/* Set / read the schedule used by kmeans_fit_batched on this context. */
+int kmeans_set_batched_schedule(kmeans_ctx *ctx, const km_schedule *s);
+int kmeans_get_batched_schedule(kmeans_ctx *ctx, km_schedule *s);
+
+/*
+ * Autotuner of the batched schedule: times kmeans_fit_batched on `inst`
+ * (typically a sample of the workload) for each candidate schedule (team
+ * size, grid occupancy, team threshold), keeps the fastest on the context and
+ * writes it to *best (may be NULL).  If cache_path is not NULL the result is
+ * looked up first and stored afterwards in that JSON file, keyed by a coarse
+ * signature of the batch (restarts, d mix, K and N ranges).  Results of the
+ * fits do not depend on the schedule (integer cluster sums), except the last
+ * bits of the objectives.
+ */
+int kmeans_tune_batched(kmeans_ctx *ctx, int32_t n_inst, km_instance *inst, double tol,
+                        int32_t max_iter, const char *cache_path, km_schedule *best);
 
 #ifdef __cplusplus
 }

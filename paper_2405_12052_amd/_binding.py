@@ -36,6 +36,18 @@ class km_result(C.Structure):
                 ("empty_events", C.c_int64)]
 
 
+class km_instance(C.Structure):
+    _fields_ = [("X", C.c_void_p), ("N", C.c_int64), ("ld", C.c_int64), ("d", C.c_int32),
+                ("K", C.c_int32), ("n_restarts", C.c_int32), ("init", C.POINTER(C.c_double)),
+                ("centroids_out", C.POINTER(C.c_double)), ("labels_out", C.c_void_p),
+                ("restart_objective", C.POINTER(C.c_double)), ("best_restart", C.c_int32),
+                ("res", km_result)]
+
+
+class km_schedule(C.Structure):
+    _fields_ = [("team_size", C.c_int32), ("blocks_per_cu", C.c_int32), ("big_work", C.c_double)]
+
+
 _lib = None
 
 
@@ -64,6 +76,12 @@ def load_library():
                                  C.c_double, C.c_int32, f64p, i32p, C.POINTER(km_result)]),
         "kmeans_get_history": (C.c_int, [vp, f64p, f64p, C.c_int32]),
         "kmeans_get_timing": (C.c_int, [vp, f64p, C.POINTER(C.c_int64)]),
+        "kmeans_fit_batched": (C.c_int, [vp, C.c_int32, C.POINTER(km_instance), C.c_double,
+                                         C.c_int32]),
+        "kmeans_set_batched_schedule": (C.c_int, [vp, C.POINTER(km_schedule)]),
+        "kmeans_get_batched_schedule": (C.c_int, [vp, C.POINTER(km_schedule)]),
+        "kmeans_tune_batched": (C.c_int, [vp, C.c_int32, C.POINTER(km_instance), C.c_double,
+                                          C.c_int32, C.c_char_p, C.POINTER(km_schedule)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -162,6 +180,65 @@ class KMeans:
                                          lab.data_ptr() if labels else None, C.byref(res)))
         return FitResult(out, lab, res.iters, bool(res.converged), res.E, res.shift_l2,
                          res.objective, res.empty_events)
+
+    # ------------------------------------------------------- batched fits
+    def _instances(self, instances, labels):
+        """instances: sequence of (X, N, init) with X a float32 CUDA tensor of
+        shape (d, >= N) (unit stride along the points) and init an array of
+        shape (R, K, d)."""
+        n = len(instances)
+        arr = (km_instance * n)()
+        keep = []
+        for i, (X, N, init) in enumerate(instances):
+            ptr, n_pts, ld, d = self._points(X, N)
+            mu0 = _f64(init)
+            if mu0.ndim != 3 or mu0.shape[2] != d:
+                raise ValueError("init must have shape (restarts, K, d)")
+            R, K = mu0.shape[0], mu0.shape[1]
+            out = np.empty((K, d), np.float64)
+            robj = np.empty(R, np.float64)
+            lab = self._torch.empty(n_pts, dtype=self._torch.int32, device=X.device) if labels else None
+            a = arr[i]
+            a.X, a.N, a.ld, a.d, a.K, a.n_restarts = ptr, n_pts, ld, d, K, R
+            a.init = _dptr(mu0)
+            a.centroids_out = _dptr(out)
+            a.labels_out = lab.data_ptr() if labels else None
+            a.restart_objective = _dptr(robj)
+            keep.append((mu0, out, robj, lab))
+        return arr, keep
+
+    def fit_batched(self, instances, tol=1e-6, max_iter=300, labels=True):
+        """Independent fits of many instances with restarts in one persistent
+        launch; returns one dict per instance (kept restart)."""
+        arr, keep = self._instances(instances, labels)
+        self._check(self._lib.kmeans_fit_batched(self._ctx, len(instances), arr, float(tol),
+                                                 int(max_iter)))
+        res = []
+        for i, (mu0, out, robj, lab) in enumerate(keep):
+            r = arr[i].res
+            res.append({"centroids": out, "labels": lab, "best_restart": arr[i].best_restart,
+                        "restart_objective": robj, "iters": r.iters,
+                        "converged": bool(r.converged), "E": r.E, "objective": r.objective,
+                        "empty_events": r.empty_events})
+        return res
+
+    def set_batched_schedule(self, team_size=0, blocks_per_cu=0, big_work=0.0):
+        s = km_schedule(int(team_size), int(blocks_per_cu), float(big_work))
+        self._check(self._lib.kmeans_set_batched_schedule(self._ctx, C.byref(s)))
+
+    def batched_schedule(self):
+        s = km_schedule()
+        self._check(self._lib.kmeans_get_batched_schedule(self._ctx, C.byref(s)))
+        return {"team_size": s.team_size, "blocks_per_cu": s.blocks_per_cu, "big_work": s.big_work}
+
+    def tune_batched(self, instances, tol=1e-6, max_iter=300, cache_path=None):
+        """Search the batched schedule on `instances`; keeps the fastest."""
+        arr, keep = self._instances(instances, False)
+        s = km_schedule()
+        cp = cache_path.encode() if cache_path else None
+        self._check(self._lib.kmeans_tune_batched(self._ctx, len(instances), arr, float(tol),
+                                                  int(max_iter), cp, C.byref(s)))
+        return {"team_size": s.team_size, "blocks_per_cu": s.blocks_per_cu, "big_work": s.big_work}
 
     def history(self, cap: int = 1 << 20):
         E = np.empty(cap, np.float64)

@@ -1,0 +1,72 @@
+// ctx.h -- the context object behind the opaque kmeans_ctx of include/kmeans.h
+// and helpers shared by the host-side sources of libkmeans_mi355x.so.
+#pragma once
+
+#include "../../include/kmeans.h"
+#include "km_internal.h"
+
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+namespace km {
+
+struct GraphKey {
+    int d, vec, grid, unroll;
+    bool operator<(const GraphKey& o) const {
+        return std::tie(d, vec, grid, unroll) < std::tie(o.d, o.vec, o.grid, o.unroll);
+    }
+};
+
+struct BatchedWS;                    // workspace of kmeans_fit_batched (batched_api.hip)
+void batched_ws_free(BatchedWS* w);
+
+}  // namespace km
+
+struct kmeans_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;      // caller's stream: all work goes here
+    hipStream_t cap_stream = nullptr;  // private stream used only for capture
+    int n_cu = 256;
+    km::State* st = nullptr;           // device state
+    km::State* st_h = nullptr;         // pinned host staging of the state
+    double* jpart = nullptr;           // [MAX_BLOCKS]
+    unsigned long long* part = nullptr;   // [MAX_BLOCKS][PART]
+    unsigned long long* gpart = nullptr;  // [MAX_GROUPS][PART]
+    double* gjpart = nullptr;          // [MAX_GROUPS]
+    uint32_t* gticket = nullptr;       // [MAX_GROUPS]
+    double* hist = nullptr;            // [2 * hist_cap]: E then J
+    int hist_cap = 0;
+    double* hist_h = nullptr;          // pinned copy of the history
+    std::string err;
+    // options
+    int use_graph = 1;
+    int unroll = 0;
+    int blocks = 0;
+    int timing = 0;
+    // graph cache
+    std::map<km::GraphKey, hipGraphExec_t> graphs;
+    // timing of the last fit: one event pair per batch of iterations
+    std::vector<hipEvent_t> ev;
+    double iter_ms = 0.0;
+    int64_t iter_kernels = 0;
+    int last_T = 0;
+    // batched fits
+    km::BatchedWS* bws = nullptr;
+    km_schedule sched = {0, 0, 0.0};   // zeros: automatic
+};
+
+namespace km {
+// Record an error message on c (or, with c == NULL, for kmeans_create) and
+// return `code`.
+int fail(kmeans_ctx* c, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int check_device_ptr(kmeans_ctx* c, const void* p, const char* what);
+}  // namespace km
+
+#define KM_HIP(ctx, call)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return km::fail(ctx, KM_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));  \
+    } while (0)

@@ -71,6 +71,65 @@ constexpr size_t kUploadBytes = offsetof(State, cand);
 constexpr size_t kProgressOffset = offsetof(State, t);
 constexpr size_t kProgressBytes = offsetof(State, absmax_bits) - offsetof(State, t);
 
+// ---------------------------------------------------------------- batched fit
+// Many independent instances, each with up to BK_RMAX restarts (independent
+// Lloyd runs from different initial centres), in one persistent launch.
+constexpr int BK_KMAX = 32;                        // K per restart
+constexpr int BK_RMAX = 8;                         // restarts per instance
+constexpr int BK_KPAD = 33;                        // BK_KMAX rounded up to triples
+constexpr int BK_PART = BK_RMAX * BK_KMAX * (DMAX + 1);  // int64 per block partial
+constexpr int BK_TEAM_MAX = 16;                    // blocks per team
+constexpr int64_t BK_NMAX = (int64_t)1 << 27;      // points per instance
+
+struct BInst {                 // one instance (host-written)
+    const float* X;            // d rows of N float32, row j at X + j*ld
+    int64_t N;
+    int64_t ld;
+    int32_t d, K, R, vec;      // vec: 16-byte aligned rows
+    int32_t* labels;           // device labels of the best restart, or null
+    const double* init;        // device, R*K*d initial centres
+};
+
+struct BOut {                  // one (instance, restart) result (device-written)
+    int32_t iters;
+    int32_t converged;
+    int64_t empty_events;
+    double E;                  // E of the last update
+    double J;                  // objective at the final centres
+};
+
+struct alignas(64) BTeam {     // one team of blocks
+    uint32_t bar;              // barrier arrivals (monotonic within a launch)
+    int32_t inst;              // instance the team works on, -1 when none is left
+    uint32_t pad[14];
+};
+
+struct BatchState {
+    const BInst* inst;         // [n_inst]
+    const int32_t* order_big;  // instances processed by teams, largest first
+    const int32_t* order_small;// instances processed by single blocks, largest first
+    int32_t n_inst, n_big, n_small;
+    int32_t team_size;         // blocks per team (1 = no teams)
+    int32_t n_teams;
+    int32_t max_iter;
+    double tol;
+    float minus_inf;
+    int32_t error;             // 1: a team barrier timed out
+    uint32_t big_ctr;          // next entry of order_big
+    uint32_t small_ctr;        // next entry of order_small
+    uint32_t* absmax;          // [n_inst] max |x| bits per instance
+    BOut* out;                 // [n_inst][BK_RMAX]
+    int32_t* best;             // [n_inst] restart with the smallest objective
+    double* best_mu;           // [n_inst][BK_KMAX * DMAX] its final centres
+    unsigned long long* tpart; // [n_teams][2][team_size][BK_PART]
+    double* tjpart;            // [n_teams][2][team_size][BK_RMAX]
+    BTeam* teams;              // [n_teams]
+};
+
+hipError_t launch_batched_scan(BatchState* bs, int n_inst, int grid, hipStream_t s);
+hipError_t launch_batched_fit(BatchState* bs, int grid, hipStream_t s, bool cooperative);
+int batched_max_blocks_per_cu();
+
 // Launchers (lloyd_kernels.hip).  `vec`: X is 16-byte aligned with ld % 4 == 0.
 hipError_t launch_scan(State* st, int d, bool vec, int grid, hipStream_t s);
 hipError_t launch_iter(State* st, int d, bool vec, int grid, hipStream_t s);

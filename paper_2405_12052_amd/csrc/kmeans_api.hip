@@ -1,8 +1,7 @@
 // kmeans_api.hip -- host runtime behind include/kmeans.h: contexts, argument
 // validation, device workspace, the iteration loop (hipGraph replays with one
 // status read-back per batch of iterations) and result read-back.
-#include "../../include/kmeans.h"
-#include "km_internal.h"
+#include "ctx.h"
 
 #include <math.h>
 #include <stdarg.h>
@@ -16,53 +15,14 @@
 
 using km::State;
 
+using km::fail;
+using km::check_device_ptr;
+
 namespace {
-
 thread_local std::string g_create_error;
-
-struct GraphKey {
-    int d, vec, grid, unroll;
-    bool operator<(const GraphKey& o) const {
-        return std::tie(d, vec, grid, unroll) < std::tie(o.d, o.vec, o.grid, o.unroll);
-    }
-};
-
 }  // namespace
 
-struct kmeans_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;      // caller's stream: all work goes here
-    hipStream_t cap_stream = nullptr;  // private stream used only for capture
-    int n_cu = 256;
-    State* st = nullptr;               // device state
-    State* st_h = nullptr;             // pinned host staging of the state
-    double* jpart = nullptr;           // [MAX_BLOCKS]
-    unsigned long long* part = nullptr;   // [MAX_BLOCKS][PART]
-    unsigned long long* gpart = nullptr;  // [MAX_GROUPS][PART]
-    double* gjpart = nullptr;          // [MAX_GROUPS]
-    uint32_t* gticket = nullptr;       // [MAX_GROUPS]
-    double* hist = nullptr;            // [2 * hist_cap]: E then J
-    int hist_cap = 0;
-    double* hist_h = nullptr;          // pinned copy of the history
-    std::string err;
-    // options
-    int use_graph = 1;
-    int unroll = 0;
-    int blocks = 0;
-    int timing = 0;
-    // graph cache
-    std::map<GraphKey, hipGraphExec_t> graphs;
-    // timing of the last fit: one event pair per batch of iterations
-    std::vector<hipEvent_t> ev;
-    double iter_ms = 0.0;
-    int64_t iter_kernels = 0;
-    int last_T = 0;
-};
-
-namespace {
-
-int fail(kmeans_ctx* c, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
-int fail(kmeans_ctx* c, int code, const char* fmt, ...) {
+int km::fail(kmeans_ctx* c, int code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -73,12 +33,19 @@ int fail(kmeans_ctx* c, int code, const char* fmt, ...) {
     return code;
 }
 
-#define KM_HIP(ctx, call)                                                               \
-    do {                                                                                \
-        hipError_t e_ = (call);                                                         \
-        if (e_ != hipSuccess)                                                           \
-            return fail(ctx, KM_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));  \
-    } while (0)
+int km::check_device_ptr(kmeans_ctx* c, const void* p, const char* what) {
+    if (!p) return fail(c, KM_EINVAL, "%s is NULL", what);
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, KM_EINVAL, "%s is not a HIP device pointer", what);
+    }
+    if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged)
+        return fail(c, KM_EINVAL, "%s must be device memory", what);
+    return KM_OK;
+}
+
+namespace {
 
 int validate(kmeans_ctx* c, int64_t N, int64_t ld, int32_t d, int32_t K, double tol,
              int32_t max_iter) {
@@ -90,18 +57,6 @@ int validate(kmeans_ctx* c, int64_t N, int64_t ld, int32_t d, int32_t K, double 
     if (K > N) return fail(c, KM_EINVAL, "K=%d > N=%lld", K, (long long)N);
     if (!(tol >= 0.0) || !isfinite(tol)) return fail(c, KM_EINVAL, "tol must be finite and >= 0");
     if (max_iter < 1) return fail(c, KM_EINVAL, "max_iter=%d < 1", max_iter);
-    return KM_OK;
-}
-
-int check_device_ptr(kmeans_ctx* c, const void* p, const char* what) {
-    if (!p) return fail(c, KM_EINVAL, "%s is NULL", what);
-    hipPointerAttribute_t a;
-    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(c, KM_EINVAL, "%s is not a HIP device pointer", what);
-    }
-    if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged)
-        return fail(c, KM_EINVAL, "%s must be device memory", what);
     return KM_OK;
 }
 
@@ -190,7 +145,7 @@ void stage(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, int K,
 }
 
 int get_graph(kmeans_ctx* c, int d, bool vec, int grid, int unroll, hipGraphExec_t* out) {
-    GraphKey key{d, vec ? 1 : 0, grid, unroll};
+    km::GraphKey key{d, vec ? 1 : 0, grid, unroll};
     auto it = c->graphs.find(key);
     if (it != c->graphs.end()) {
         *out = it->second;
@@ -321,6 +276,7 @@ void kmeans_destroy(kmeans_ctx* c) {
     if (c->hist_h) (void)hipHostFree(c->hist_h);
     for (auto& e : c->ev) (void)hipEventDestroy(e);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->bws) km::batched_ws_free(c->bws);
     delete c;
 }
 

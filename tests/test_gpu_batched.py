@@ -1,0 +1,131 @@
+"""GPU tests of the batched persistent fit (many instances x restarts in one
+launch): every restart equals a single kmeans_fit from the same initial
+centres, the kept restart has the smallest objective, results do not depend
+on the schedule, the kept restart matches the FP64 oracle, and the error
+paths and the autotuner cache work."""
+import json
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from parity import centre_check, e_check, label_check
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def km():
+    from paper_2405_12052_amd import KMeans
+    k = KMeans(0)
+    yield k
+    k.close()
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def make_batch(n, seed, n_range=(3.0, 5.0), restarts=None):
+    specs = datagen.batched_specs(n, seed=seed, n_range=n_range)
+    flat, offs, inits = datagen.batched_generate(specs)
+    if restarts is not None:
+        rng = np.random.default_rng(seed)
+        inits = [ini[:int(rng.integers(1, restarts + 1))] for ini in inits]
+    dev = torch.from_numpy(flat).cuda()
+    inst, host = [], []
+    for s, off, ini in zip(specs, offs, inits):
+        ld = datagen.round_up(s.N, 4)
+        X = dev[off:off + s.d * ld].view(s.d, ld)
+        inst.append((X, s.N, ini))
+        host.append(flat[off:off + s.d * ld].reshape(s.d, ld))
+    return specs, inst, host, dev
+
+
+@pytest.fixture(scope="module")
+def batch():
+    return make_batch(40, 777, restarts=8)
+
+
+def test_every_restart_equals_a_single_fit(km, batch):
+    specs, inst, host, _ = batch
+    out = km.fit_batched(inst, tol=1e-6, max_iter=300)
+    n_restarts = 0
+    for s, (X, N, ini), r in zip(specs, inst, out):
+        singles = [km.fit(X, ini[q], tol=1e-6, max_iter=300, N=N) for q in range(len(ini))]
+        n_restarts += len(ini)
+        J = np.array([f.objective for f in singles])
+        assert np.allclose(r["restart_objective"], J, rtol=1e-12, atol=0), s.name
+        b = r["best_restart"]
+        assert b == int(np.argmin(r["restart_objective"]))
+        f = singles[b]
+        assert np.array_equal(r["centroids"], f.centroids), s.name
+        assert r["iters"] == f.iters and r["E"] == f.E and r["converged"] == f.converged
+        assert r["empty_events"] == f.empty_events
+        assert np.array_equal(r["labels"].cpu().numpy(), f.labels.cpu().numpy())
+    log(f"{len(specs)} instances, {n_restarts} restarts: identical to single fits")
+
+
+def test_kept_restart_matches_the_oracle(km, batch):
+    specs, inst, host, _ = batch
+    out = km.fit_batched(inst, tol=1e-6, max_iter=300)
+    for i in (0, 5, 11, 23, 39):
+        s, (X, N, ini), r = specs[i], inst[i], out[i]
+        ref = oracle.fit(host[i], ini[r["best_restart"]], tol=1e-6, max_iter=300, N=N)
+        assert r["iters"] == ref["T"], s.name
+        centre_check(r["centroids"], ref["mu"])
+        e_check(r["E"], ref["E"])
+        assert abs(r["objective"] - ref["J"]) <= 1e-6 * ref["J"]
+        label_check(r["labels"].cpu().numpy(), host[i], r["centroids"], N=N)
+
+
+def test_schedule_independence(km, batch):
+    specs, inst, host, _ = batch
+    runs = []
+    for sch in [(1, 1, 0.0), (4, 2, 1.0), (16, 1, 1e6), (8, 2, 0.0)]:
+        km.set_batched_schedule(*sch)
+        runs.append((sch, km.fit_batched(inst, tol=1e-6, max_iter=300)))
+    km.set_batched_schedule(0, 0, 0.0)
+    base = runs[0][1]
+    for sch, out in runs[1:]:
+        for a, b in zip(base, out):
+            assert np.array_equal(a["centroids"], b["centroids"]), sch
+            assert a["iters"] == b["iters"] and a["E"] == b["E"], sch
+            assert a["best_restart"] == b["best_restart"], sch
+            assert np.allclose(a["restart_objective"], b["restart_objective"], rtol=1e-12, atol=0)
+            assert np.array_equal(a["labels"].cpu().numpy(), b["labels"].cpu().numpy())
+
+
+def test_batched_errors(km, batch):
+    from paper_2405_12052_amd import KM_EINVAL, KM_EUNSUPPORTED, KMeansError
+    specs, inst, host, dev = batch
+    X, N, ini = inst[0]
+    bad_k = np.zeros((1, 33, X.shape[0]))
+    with pytest.raises(KMeansError) as e:
+        km.fit_batched([(X, N, bad_k)])
+    assert e.value.code == KM_EUNSUPPORTED
+    with pytest.raises(KMeansError) as e:
+        km.fit_batched([(X, N, np.concatenate([ini] * 2)[:9] if len(ini) >= 5 else np.zeros((9, 2, X.shape[0])))])
+    assert e.value.code in (KM_EUNSUPPORTED, KM_EINVAL)
+    Xn = X.clone()
+    Xn[0, 3] = float("nan")
+    with pytest.raises(KMeansError, match="NaN") as e:
+        km.fit_batched([inst[1], (Xn, N, ini)])
+    assert e.value.code == KM_EINVAL
+    out = km.fit_batched(inst[:3])          # the context still works
+    assert len(out) == 3
+
+
+def test_tuner_and_cache(km, tmp_path):
+    specs, inst, host, _ = make_batch(24, 999, n_range=(3.0, 5.5), restarts=4)
+    cache = str(tmp_path / "tune.json")
+    best = km.tune_batched(inst, tol=1e-6, max_iter=300, cache_path=cache)
+    log(f"tuned schedule {best}")
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1 and json.loads(lines[0])["team_size"] == best["team_size"]
+    again = km.tune_batched(inst, tol=1e-6, max_iter=300, cache_path=cache)
+    assert again == best and len(open(cache).read().strip().splitlines()) == 1
+    assert km.batched_schedule() == best
+    km.set_batched_schedule(0, 0, 0.0)
