@@ -202,13 +202,18 @@ def batched_generate(specs, restarts=None, threads=None):
         offsets.append(total)
         total += s.d * round_up(s.N, 4)
     flat = np.zeros(total, dtype=np.float32)
-    inits = []
-    for s, off in zip(specs, offsets):
+
+    def one(i):
+        s, off = specs[i], offsets[i]
         ld = round_up(s.N, 4)
-        X, _ = generate(s, ld=ld, threads=threads)
+        X, _ = generate(s, ld=ld, threads=1)
         flat[off:off + s.d * ld] = X.reshape(-1)
         seeds = s.extra.get("restart_seeds", [s.init_seed])
         if restarts is not None:
-            seeds = [seeds[i % len(seeds)] + 7 * (i // len(seeds)) for i in range(restarts)]
-        inits.append(np.stack([init_sample(X, s.N, s.K, sd) for sd in seeds]))
+            seeds = [seeds[q % len(seeds)] + 7 * (q // len(seeds)) for q in range(restarts)]
+        return np.stack([init_sample(X, s.N, s.K, sd) for sd in seeds])
+
+    threads = threads or min(16, os.cpu_count() or 1)
+    with _cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        inits = list(ex.map(one, range(len(specs))))
     return flat, offsets, inits

@@ -177,6 +177,7 @@ typedef struct km_instance {
     double *centroids_out;      /* host, K*d: final centres of the kept restart  */
     int32_t *labels_out;        /* device, N labels of the kept restart, or NULL */
     double *restart_objective;  /* host, n_restarts final objectives, or NULL    */
+    int32_t *restart_iters;     /* host, n_restarts update counts T, or NULL      */
     int32_t best_restart;       /* out: index of the kept restart                */
     km_result res;              /* out: outcome of the kept restart              */
 } km_instance;
@@ -219,6 +220,65 @@ int kmeans_get_batched_schedule(kmeans_ctx *ctx, km_schedule *s);
  */
 int kmeans_tune_batched(kmeans_ctx *ctx, int32_t n_inst, km_instance *inst, double tol,
                         int32_t max_iter, const char *cache_path, km_schedule *best);
+
+/* ------------------------------------------------ learned initialiser */
+/*
+ * A small permutation-invariant network proposes the K initial centres of a
+ * 3-D instance from a sample of P of its points, to cut the number of Lloyd
+ * updates (the paper notes that the initialisation steers the result and that
+ * the iteration count grows with N).  Architecture, on points normalised by
+ * the sample's mean and scalar standard deviation s (s^2 = mean over points
+ * and coordinates of (x - mean)^2):
+ *   per point  h1 = relu(x W1 + b1) (3 -> 64), h2 = relu(h1 W2 + b2) (64 -> 64)
+ *   pooling    p = [mean over points of h2, max over points of h2]  (128)
+ *   head       z = relu(p W3 + b3) (128 -> 256), y = z W4 + b4 (256 -> 3K)
+ * y holds K normalised centres; centre = y * s + mean.  Weights are float32
+ * masters used as bfloat16 copies; the per-point products run on bfloat16
+ * MFMA with float32 accumulation.  Training minimises
+ *   L = (1/B) sum_b sum_k |y_b[pi_b(k)] - t_b[k]|^2
+ * against target centres t (normalised the same way), pi_b the least-cost
+ * assignment (Hungarian matching on the device, held fixed for the gradient).
+ *
+ * Parameters: one caller-owned DEVICE float32 array of
+ * kmeans_initnet_param_count(K) values, row-major blocks W1 [3][64], b1 [64],
+ * W2 [64][64], b2 [64], W3 [128][256], b3 [256], W4 [256][3K], b4 [3K]
+ * (rows = inputs).  Points: DEVICE float32 [B][P][3] (normalised); targets:
+ * DEVICE float32 [B][K][3].  Shapes: 1 <= B <= 4096, P a multiple of 32 in
+ * [32, 65536], 1 <= K <= 16.
+ */
+
+/* Number of floats in the parameter array for K centres (-1 if K is out of
+ * range).  Needs no GPU. */
+int32_t kmeans_initnet_param_count(int32_t K);
+
+/* Forward pass: pred_out (device [B][K][3]) and optionally the pooled
+ * features pool_out (device [B][128]). */
+int kmeans_initnet_forward(kmeans_ctx *ctx, const float *pts, int32_t B, int32_t P,
+                           int32_t K, const float *params, float *pred_out, float *pool_out);
+
+/* Gradient of L at `params` into grad_out (device, parameter layout); the
+ * loss to *loss_out (host, may be NULL) and the matching pi to match_out
+ * (device [B][K], the predicted centre assigned to each target, may be NULL). */
+int kmeans_initnet_grad(kmeans_ctx *ctx, const float *pts, const float *targets, int32_t B,
+                        int32_t P, int32_t K, const float *params, float *grad_out,
+                        double *loss_out, int32_t *match_out);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected for `step`
+ * >= 1) on params with the moment arrays adam_m, adam_v (device, parameter
+ * layout, zero before step 1).  *loss_out (host, may be NULL: then the call
+ * returns without waiting for the device) receives the loss before the step. */
+int kmeans_initnet_train_step(kmeans_ctx *ctx, const float *pts, const float *targets,
+                              int32_t B, int32_t P, int32_t K, float *params, float *adam_m,
+                              float *adam_v, float lr, int32_t step, double *loss_out);
+
+/* Initial centres of one 3-D instance (X as in kmeans_fit, d = 3) from the P
+ * sample points idx[0..P) (device int32 indices into [0, N)): gather,
+ * normalise, forward pass, de-normalise, into centroids_out (host, K*3
+ * float64).  Returns KM_EINVAL if the network yields a non-finite centre
+ * (callers then fall back to a seeded sample of data points). */
+int kmeans_init_learned(kmeans_ctx *ctx, const float *X, int64_t N, int64_t ld, int32_t K,
+                        const int32_t *idx, int32_t P, const float *params,
+                        double *centroids_out);
 
 #ifdef __cplusplus
 }

@@ -40,7 +40,8 @@ class km_instance(C.Structure):
     _fields_ = [("X", C.c_void_p), ("N", C.c_int64), ("ld", C.c_int64), ("d", C.c_int32),
                 ("K", C.c_int32), ("n_restarts", C.c_int32), ("init", C.POINTER(C.c_double)),
                 ("centroids_out", C.POINTER(C.c_double)), ("labels_out", C.c_void_p),
-                ("restart_objective", C.POINTER(C.c_double)), ("best_restart", C.c_int32),
+                ("restart_objective", C.POINTER(C.c_double)),
+                ("restart_iters", C.POINTER(C.c_int32)), ("best_restart", C.c_int32),
                 ("res", km_result)]
 
 
@@ -82,6 +83,15 @@ def load_library():
         "kmeans_get_batched_schedule": (C.c_int, [vp, C.POINTER(km_schedule)]),
         "kmeans_tune_batched": (C.c_int, [vp, C.c_int32, C.POINTER(km_instance), C.c_double,
                                           C.c_int32, C.c_char_p, C.POINTER(km_schedule)]),
+        "kmeans_initnet_param_count": (C.c_int32, [C.c_int32]),
+        "kmeans_initnet_forward": (C.c_int, [vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp]),
+        "kmeans_initnet_grad": (C.c_int, [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, vp,
+                                          C.POINTER(C.c_double), vp]),
+        "kmeans_initnet_train_step": (C.c_int, [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, vp,
+                                                vp, vp, C.c_float, C.c_int32,
+                                                C.POINTER(C.c_double)]),
+        "kmeans_init_learned": (C.c_int, [vp, vp, C.c_int64, C.c_int64, C.c_int32, vp, C.c_int32,
+                                          vp, f64p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -94,6 +104,11 @@ def load_library():
 def validate(N, ld, d, K, tol=1e-6, max_iter=100) -> int:
     """Host-only argument check (no GPU needed); returns the status code."""
     return load_library().kmeans_validate(N, ld, d, K, tol, max_iter)
+
+
+def initnet_param_count(K: int) -> int:
+    """Floats in the learned initialiser's parameter array for K centres."""
+    return load_library().kmeans_initnet_param_count(int(K))
 
 
 def _f64(a):
@@ -197,6 +212,7 @@ class KMeans:
             R, K = mu0.shape[0], mu0.shape[1]
             out = np.empty((K, d), np.float64)
             robj = np.empty(R, np.float64)
+            rit = np.empty(R, np.int32)
             lab = self._torch.empty(n_pts, dtype=self._torch.int32, device=X.device) if labels else None
             a = arr[i]
             a.X, a.N, a.ld, a.d, a.K, a.n_restarts = ptr, n_pts, ld, d, K, R
@@ -204,7 +220,8 @@ class KMeans:
             a.centroids_out = _dptr(out)
             a.labels_out = lab.data_ptr() if labels else None
             a.restart_objective = _dptr(robj)
-            keep.append((mu0, out, robj, lab))
+            a.restart_iters = rit.ctypes.data_as(C.POINTER(C.c_int32))
+            keep.append((mu0, out, robj, rit, lab))
         return arr, keep
 
     def fit_batched(self, instances, tol=1e-6, max_iter=300, labels=True):
@@ -214,10 +231,10 @@ class KMeans:
         self._check(self._lib.kmeans_fit_batched(self._ctx, len(instances), arr, float(tol),
                                                  int(max_iter)))
         res = []
-        for i, (mu0, out, robj, lab) in enumerate(keep):
+        for i, (mu0, out, robj, rit, lab) in enumerate(keep):
             r = arr[i].res
             res.append({"centroids": out, "labels": lab, "best_restart": arr[i].best_restart,
-                        "restart_objective": robj, "iters": r.iters,
+                        "restart_objective": robj, "restart_iters": rit, "iters": r.iters,
                         "converged": bool(r.converged), "E": r.E, "objective": r.objective,
                         "empty_events": r.empty_events})
         return res
@@ -239,6 +256,65 @@ class KMeans:
         self._check(self._lib.kmeans_tune_batched(self._ctx, len(instances), arr, float(tol),
                                                   int(max_iter), cp, C.byref(s)))
         return {"team_size": s.team_size, "blocks_per_cu": s.blocks_per_cu, "big_work": s.big_work}
+
+    # ------------------------------------------------ learned initialiser
+    def _net_args(self, pts, K, params):
+        t = self._torch
+        if pts.dtype != t.float32 or not pts.is_cuda or pts.dim() != 3 or pts.shape[2] != 3:
+            raise TypeError("pts must be a float32 CUDA tensor [B, P, 3]")
+        if not pts.is_contiguous():
+            raise ValueError("pts must be contiguous")
+        if params.dtype != t.float32 or not params.is_cuda or params.numel() != initnet_param_count(K):
+            raise TypeError("params must be a float32 CUDA tensor of initnet_param_count(K) values")
+        return pts.shape[0], pts.shape[1]
+
+    def initnet_forward(self, pts, K, params):
+        """Predicted normalised centres [B, K, 3] and pooled features [B, 128]."""
+        B, P = self._net_args(pts, K, params)
+        pred = self._torch.empty((B, K, 3), dtype=self._torch.float32, device=pts.device)
+        pool = self._torch.empty((B, 128), dtype=self._torch.float32, device=pts.device)
+        self._check(self._lib.kmeans_initnet_forward(self._ctx, pts.data_ptr(), B, P, K,
+                                                     params.data_ptr(), pred.data_ptr(),
+                                                     pool.data_ptr()))
+        return pred, pool
+
+    def initnet_grad(self, pts, targets, K, params):
+        """Gradient (parameter layout), loss and matching [B, K] at params."""
+        B, P = self._net_args(pts, K, params)
+        grad = self._torch.empty_like(params)
+        match = self._torch.empty((B, K), dtype=self._torch.int32, device=pts.device)
+        loss = C.c_double()
+        self._check(self._lib.kmeans_initnet_grad(self._ctx, pts.data_ptr(),
+                                                  targets.contiguous().data_ptr(), B, P, K,
+                                                  params.data_ptr(), grad.data_ptr(),
+                                                  C.byref(loss), match.data_ptr()))
+        return grad, loss.value, match
+
+    def initnet_train_step(self, pts, targets, K, params, m, v, lr, step, want_loss=True):
+        """One Adam step in place on params/m/v; the loss before it (or None)."""
+        B, P = self._net_args(pts, K, params)
+        loss = C.c_double()
+        self._check(self._lib.kmeans_initnet_train_step(
+            self._ctx, pts.data_ptr(), targets.data_ptr(), B, P, K, params.data_ptr(),
+            m.data_ptr(), v.data_ptr(), float(lr), int(step),
+            C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def init_learned(self, X, K, params, N=None, P=4096, seed=0, idx=None):
+        """K x 3 initial centres proposed by the network from a seeded sample
+        of P points of X (float64, host).  Raises KMeansError if the network
+        yields a non-finite centre."""
+        ptr, n, ld, d = self._points(X, N)
+        if d != 3:
+            raise ValueError("the learned initialiser takes 3-D points")
+        if idx is None:
+            rng = np.random.Generator(np.random.PCG64(seed))
+            idx = self._torch.from_numpy(
+                rng.choice(n, size=min(P, n), replace=False).astype(np.int32)).to(X.device)
+        out = np.empty((K, 3), np.float64)
+        self._check(self._lib.kmeans_init_learned(self._ctx, ptr, n, ld, K, idx.data_ptr(),
+                                                  idx.numel(), params.data_ptr(), _dptr(out)))
+        return out
 
     def history(self, cap: int = 1 << 20):
         E = np.empty(cap, np.float64)

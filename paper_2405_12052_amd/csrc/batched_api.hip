@@ -355,6 +355,8 @@ int run_batched(kmeans_ctx* c, int32_t n_inst, km_instance* inst, double tol, in
         in.res.empty_events = o[b].empty_events;
         if (in.restart_objective)
             for (int r = 0; r < in.n_restarts; ++r) in.restart_objective[r] = o[r].J;
+        if (in.restart_iters)
+            for (int r = 0; r < in.n_restarts; ++r) in.restart_iters[r] = o[r].iters;
     }
     if (nonfinite >= 0)
         return fail(c, KM_EINVAL, "instance %d holds a NaN or an infinity", nonfinite);

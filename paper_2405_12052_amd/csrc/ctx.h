@@ -21,6 +21,8 @@ struct GraphKey {
 
 struct BatchedWS;                    // workspace of kmeans_fit_batched (batched_api.hip)
 void batched_ws_free(BatchedWS* w);
+struct NetWS;                        // workspace of the learned initialiser (initnet_api.hip)
+void net_ws_free(NetWS* w);
 
 }  // namespace km
 
@@ -55,6 +57,8 @@ struct kmeans_ctx {
     // batched fits
     km::BatchedWS* bws = nullptr;
     km_schedule sched = {0, 0, 0.0};   // zeros: automatic
+    // learned initialiser
+    km::NetWS* nws = nullptr;
 };
 
 namespace km {

@@ -277,6 +277,7 @@ void kmeans_destroy(kmeans_ctx* c) {
     for (auto& e : c->ev) (void)hipEventDestroy(e);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->bws) km::batched_ws_free(c->bws);
+    if (c->nws) km::net_ws_free(c->nws);
     delete c;
 }
 

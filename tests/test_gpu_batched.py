@@ -58,6 +58,7 @@ def test_every_restart_equals_a_single_fit(km, batch):
         n_restarts += len(ini)
         J = np.array([f.objective for f in singles])
         assert np.allclose(r["restart_objective"], J, rtol=1e-12, atol=0), s.name
+        assert r["restart_iters"].tolist() == [f.iters for f in singles]
         b = r["best_restart"]
         assert b == int(np.argmin(r["restart_objective"]))
         f = singles[b]
