@@ -140,6 +140,114 @@ def bench_batched(args):
     km.close()
 
 
+def _c5_instance(seed):
+    import datagen
+    s = datagen.spec("C5", seed=int(seed), init_seed=int(seed))
+    X, _ = datagen.generate(s, threads=1)
+    return int(seed), X
+
+
+def time_to_converge(km, X, Xd, N, K, seed, method, weights=None, repeats=3):
+    """One initialisation method followed by kmeans_fit (E < 1e-6 or 300
+    updates) on resident points; the wall-clock span covers the
+    initialisation (sampling, seeding or network inference included), the
+    fit and its final synchronisation.  Median over `repeats` runs (all runs
+    give identical results).  Returns (seconds, updates, objective, fell_back)."""
+    import numpy as np
+    import torch
+
+    import datagen
+    from paper_2405_12052_amd import KMeansError
+    times = []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fell_back = False
+        if method == "sample":
+            mu0 = datagen.init_sample(X, N, K, seed)
+        elif method == "kmeans++":
+            mu0 = km.pp_init(Xd, K, seed=seed)
+        elif method == "learned":
+            rng = np.random.Generator(np.random.PCG64(seed))
+            idx = torch.from_numpy(rng.choice(N, size=4096, replace=False).astype(np.int32)).to(
+                Xd.device, non_blocking=True)
+            try:
+                mu0 = km.init_learned(Xd, K, weights, idx=idx)
+            except KMeansError:
+                mu0 = datagen.init_sample(X, N, K, seed)
+                fell_back = True
+        else:
+            raise ValueError(method)
+        r = km.fit(Xd, mu0, tol=1e-6, max_iter=300, labels=False)
+        times.append(time.perf_counter() - t)
+    return float(np.median(times)), r.iters, r.objective, fell_back
+
+
+def bench_learned(args):
+    """Learned initialiser against a seeded sample of data points and against
+    k-means++ on held-out instances of the N=1e6, d=3, K=16 mixture (16
+    axis-aligned Gaussian components in [-50, 50]^3, Dirichlet weights, 1%
+    uniform noise), seeds 9_000_000 + i, disjoint from the training seeds.
+    Reports, per method, the median time-to-converge, mean updates and the
+    geometric-mean ratios to the seeded sample, and the share of instances on
+    which the learned start reaches an objective within 0.1% of the seeded
+    sample's (or lower) in less wall-clock time."""
+    import multiprocessing as mp
+
+    import numpy as np
+    import torch
+
+    from paper_2405_12052_amd import KMeans, initnet
+    weights = torch.from_numpy(initnet.load_weights(args.weights or initnet.DEFAULT_WEIGHTS)).cuda()
+    km = KMeans(0)
+    seeds = [9_000_000 + i for i in range(args.instances)]
+    methods = ["sample", "kmeans++", "learned"]
+    rec = {m: [] for m in methods}
+    K, N = 16, 1_000_000
+    t0 = time.time()
+    warm = False
+    with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
+        for n_done, (seed, X) in enumerate(pool.imap(_c5_instance, seeds)):
+            Xd = torch.from_numpy(X).cuda()
+            if not warm:        # first-call set-up (graphs, workspaces) out of the records
+                for m in methods:
+                    time_to_converge(km, X, Xd, N, K, seed, m, weights, repeats=1)
+                warm = True
+            for m in methods:
+                rec[m].append(time_to_converge(km, X, Xd, N, K, seed, m, weights, args.repeats))
+            if (n_done + 1) % 10 == 0:
+                log(f"{n_done + 1}/{len(seeds)} instances, {time.time() - t0:.0f}s")
+    km.close()
+    a = {m: np.array([r[:3] for r in rec[m]], np.float64) for m in methods}
+    base = a["sample"]
+    summary = {}
+    for m in methods:
+        summary[m] = {
+            "median_ms": float(np.median(a[m][:, 0]) * 1e3),
+            "mean_updates": float(a[m][:, 1].mean()),
+            "geomean_time_ratio": float(np.exp(np.mean(np.log(a[m][:, 0] / base[:, 0])))),
+            "geomean_J_ratio": float(np.exp(np.mean(np.log(a[m][:, 2] / base[:, 2])))),
+            "share_J_within_0.1pct": float(np.mean(a[m][:, 2] <= 1.001 * base[:, 2])),
+            "share_J_within_0.1pct_and_faster": float(
+                np.mean((a[m][:, 2] <= 1.001 * base[:, 2]) & (a[m][:, 0] < base[:, 0]))),
+        }
+    summary["learned"]["fallbacks"] = int(sum(r[3] for r in rec["learned"]))
+    L = summary["learned"]
+    res = {
+        "metric": "time-to-converge, learned init vs seeded sample (geomean ratio)",
+        "value": L["geomean_time_ratio"], "unit": "ratio", "n_gpus": 1,
+        "steps": len(seeds), "warmup": 1, "ms_per_step": L["median_ms"],
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{len(seeds)} held-out instances, N=1e6, d=3, K=16, E<1e-6 or "
+                               "300 updates; time spans init + fit + sync on resident points",
+                   "parallelism": "single GPU", "repeats": args.repeats},
+        "methods": summary,
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,9 +257,13 @@ def main():
     ap.add_argument("--N", type=int, default=None, help="override N (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=20_000_000)
-    ap.add_argument("--workload", choices=["hbm", "batched"], default="hbm",
-                    help="hbm: the N=2e8, K=64 fit (default); batched: 4096 instances")
-    ap.add_argument("--instances", type=int, default=4096)
+    ap.add_argument("--workload", choices=["hbm", "batched", "learned"], default="hbm",
+                    help="hbm: the N=2e8, K=64 fit (default); batched: 4096 instances; "
+                         "learned: learned init vs seeded sample and k-means++ on N=1e6, K=16")
+    ap.add_argument("--instances", type=int, default=None,
+                    help="instances (batched: 4096, learned: 100)")
+    ap.add_argument("--repeats", type=int, default=3)
+    ap.add_argument("--weights", default=None, help="learned initialiser weights (.npy)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -159,7 +271,12 @@ def main():
         sys.exit(2)
 
     if args.workload == "batched":
+        args.instances = args.instances or 4096
         bench_batched(args)
+        return
+    if args.workload == "learned":
+        args.instances = args.instances or 100
+        bench_learned(args)
         return
 
     import numpy as np

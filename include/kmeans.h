@@ -280,6 +280,31 @@ int kmeans_init_learned(kmeans_ctx *ctx, const float *X, int64_t N, int64_t ld, 
                         const int32_t *idx, int32_t P, const float *params,
                         double *centroids_out);
 
+/* ------------------------------------------------------ k-means++ seeding */
+
+/*
+ * k-means++ initial centres (Arthur and Vassilvitskii, 2007): an alternative
+ * to the paper's random choice of initial centres (Section 3, first step,
+ * whose outcome the paper notes depends on that choice).  The draw is exact
+ * and reproducible given the caller's K uniforms u[0..K) (host, each in
+ * [0, 1)):
+ *   - centre 0 is point min(N-1, floor(u[0] * N));
+ *   - for j >= 1, D_i^2 is the float32 squared distance of point i to its
+ *     nearest chosen centre, ((x0-c0)^2 + (x1-c1)^2) + (x2-c2)^2 with each
+ *     operation rounded on its own; w_i = rint(D_i^2 * 2^G) as a 64-bit
+ *     integer with G = B - ilogb(max_i D_i^2) - 1, B = 62 - ceil(log2 N);
+ *     S = sum_i w_i; if S == 0 centre j is point min(N-1, floor(u[j] * N)),
+ *     else with R = min(S-1, floor(u[j] * S)) it is the first point i whose
+ *     inclusive prefix sum w_0 + ... + w_i exceeds R.
+ * X is as in kmeans_fit (device, d rows of N float32, row stride ld).
+ * Writes the chosen points to centroids_out (host, K*d float64) and their
+ * indices to index_out (host, K int64; may be NULL).  Same shape limits as
+ * kmeans_fit.  Returns KM_EINVAL for a u outside [0, 1) or if X holds a NaN
+ * or an infinity.  Keeps a distance buffer of N floats on the context.
+ */
+int kmeans_pp_init(kmeans_ctx *ctx, const float *X, int64_t N, int64_t ld, int32_t d,
+                   int32_t K, const double *u, double *centroids_out, int64_t *index_out);
+
 #ifdef __cplusplus
 }
 #endif

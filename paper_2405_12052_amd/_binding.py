@@ -92,6 +92,8 @@ def load_library():
                                                 C.POINTER(C.c_double)]),
         "kmeans_init_learned": (C.c_int, [vp, vp, C.c_int64, C.c_int64, C.c_int32, vp, C.c_int32,
                                           vp, f64p]),
+        "kmeans_pp_init": (C.c_int, [vp, f32p, C.c_int64, C.c_int64, C.c_int32, C.c_int32, f64p,
+                                     f64p, C.POINTER(C.c_int64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -315,6 +317,22 @@ class KMeans:
         self._check(self._lib.kmeans_init_learned(self._ctx, ptr, n, ld, K, idx.data_ptr(),
                                                   idx.numel(), params.data_ptr(), _dptr(out)))
         return out
+
+    def pp_init(self, X, K, u=None, seed=0, N=None, return_index=False):
+        """k-means++ initial centres (K x d float64, host) from the uniforms u
+        (K values in [0, 1); drawn from a PCG64 generator seeded with `seed`
+        when not given)."""
+        ptr, n, ld, d = self._points(X, N)
+        if u is None:
+            u = np.random.Generator(np.random.PCG64(seed)).random(K)
+        u = _f64(u)
+        if u.size != K:
+            raise ValueError(f"u holds {u.size} values, K = {K}")
+        out = np.empty((K, d), np.float64)
+        idx = np.empty(K, np.int64)
+        self._check(self._lib.kmeans_pp_init(self._ctx, ptr, n, ld, d, K, _dptr(u), _dptr(out),
+                                             idx.ctypes.data_as(C.POINTER(C.c_int64))))
+        return (out, idx) if return_index else out
 
     def history(self, cap: int = 1 << 20):
         E = np.empty(cap, np.float64)

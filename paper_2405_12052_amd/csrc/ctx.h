@@ -23,6 +23,8 @@ struct BatchedWS;                    // workspace of kmeans_fit_batched (batched
 void batched_ws_free(BatchedWS* w);
 struct NetWS;                        // workspace of the learned initialiser (initnet_api.hip)
 void net_ws_free(NetWS* w);
+struct SeedWS;                       // workspace of k-means++ seeding (seeding.hip)
+void seed_ws_free(SeedWS* w);
 
 }  // namespace km
 
@@ -59,6 +61,8 @@ struct kmeans_ctx {
     km_schedule sched = {0, 0, 0.0};   // zeros: automatic
     // learned initialiser
     km::NetWS* nws = nullptr;
+    // k-means++ seeding
+    km::SeedWS* sws = nullptr;
 };
 
 namespace km {

@@ -278,6 +278,7 @@ void kmeans_destroy(kmeans_ctx* c) {
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->bws) km::batched_ws_free(c->bws);
     if (c->nws) km::net_ws_free(c->nws);
+    if (c->sws) km::seed_ws_free(c->sws);
     delete c;
 }
 

@@ -16,7 +16,6 @@ instance's mean and scalar standard deviation.
 from __future__ import annotations
 
 import argparse
-import concurrent.futures as cf
 import os
 import sys
 import time
@@ -57,31 +56,47 @@ def instance_points(seed):
     return ((X - m[:, None]) / sd).T.astype(np.float32)
 
 
-def load_points(seeds, threads=16):
+def _chunk_points(seeds):
+    return np.stack([instance_points(s) for s in seeds])
+
+
+def load_points(seeds, procs=16, chunk=1000):
+    """Regenerate many instances with a pool of worker processes (numpy only;
+    the workers never touch the GPU)."""
+    import multiprocessing as mp
     out = np.empty((len(seeds), P_POINTS, 3), np.float32)
-
-    def one(i):
-        out[i] = instance_points(seeds[i])
-
-    with cf.ThreadPoolExecutor(threads) as ex:
-        list(ex.map(one, range(len(seeds))))
+    parts = [list(seeds[a:a + chunk]) for a in range(0, len(seeds), chunk)]
+    if len(parts) <= 1 or procs <= 1:
+        for i, p in enumerate(parts):
+            out[i * chunk:i * chunk + len(p)] = _chunk_points(p)
+        return out
+    with mp.get_context("spawn").Pool(procs) as pool:
+        for i, arr in enumerate(pool.imap(_chunk_points, parts)):
+            out[i * chunk:i * chunk + len(arr)] = arr
     return out
 
 
-def train(targets_path, out_path, epochs=8, batch=256, lr=2e-3, lr_end=1e-4, holdout=2048,
-          seed=0, log=print):
+def load_training_set(targets_path, log=print):
+    """(points [n, P, 3], targets [n, K, 3]) of a target file, as float32 CUDA
+    tensors."""
     import torch
-    from . import KMeans
     d = np.load(targets_path)
     seeds, tg = d["seeds"], d["targets"].astype(np.float32)
-    n = len(seeds)
     t0 = time.time()
     pts = load_points(seeds)
-    log(f"regenerated {n} training instances in {time.time() - t0:.1f}s")
-    dev = "cuda"
-    P = torch.from_numpy(pts).to(dev)
-    T = torch.from_numpy(tg).to(dev)
-    del pts
+    log(f"regenerated {len(seeds)} training instances in {time.time() - t0:.1f}s")
+    return torch.from_numpy(pts).cuda(), torch.from_numpy(tg).cuda()
+
+
+def train(targets_path, out_path, epochs=8, batch=256, lr=2e-3, lr_end=1e-4, holdout=2048,
+          seed=0, log=print, data=None):
+    """Adam on the matched loss; the last `holdout` instances are held out.
+    `data` = load_training_set(...) output, to reuse loaded points."""
+    import torch
+    from . import KMeans
+    P, T = data if data is not None else load_training_set(targets_path, log)
+    n = P.shape[0]
+    dev = P.device
     n_train = n - holdout
     params = torch.from_numpy(init_params(K, seed)).to(dev)
     m = torch.zeros_like(params)
