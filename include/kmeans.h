@@ -82,8 +82,13 @@ enum km_option {
                              0: launch each iteration kernel directly          */
     KM_OPT_UNROLL = 2,    /* iterations per graph launch (0 = automatic)       */
     KM_OPT_BLOCKS = 3,    /* grid size of the iteration kernel (0 = automatic) */
-    KM_OPT_TIMING = 4     /* 1: time the iteration launches with HIP events
+    KM_OPT_TIMING = 4,    /* 1: time the iteration launches with HIP events
                              (see kmeans_get_timing)                           */
+    KM_OPT_KEYS = 5       /* how the reassignment scan forms its keys
+                             |m|^2 - 2 m.x: 0 (default) automatic (currently
+                             the vector ALUs), 1 vector ALUs, 2 matrix cores
+                             (FP32 MFMA; slower on gfx950, kept selectable).
+                             Labels, centres, E and T do not depend on it.     */
 };
 
 /*

@@ -13,9 +13,9 @@
 namespace km {
 
 struct GraphKey {
-    int d, vec, grid, unroll;
+    int d, vec, keys, grid, unroll;
     bool operator<(const GraphKey& o) const {
-        return std::tie(d, vec, grid, unroll) < std::tie(o.d, o.vec, o.grid, o.unroll);
+        return std::tie(d, vec, keys, grid, unroll) < std::tie(o.d, o.vec, o.keys, o.grid, o.unroll);
     }
 };
 
@@ -49,6 +49,7 @@ struct kmeans_ctx {
     int unroll = 0;
     int blocks = 0;
     int timing = 0;
+    int keys = 0;                      // KM_OPT_KEYS
     // graph cache
     std::map<km::GraphKey, hipGraphExec_t> graphs;
     // timing of the last fit: one event pair per batch of iterations

@@ -131,9 +131,10 @@ hipError_t launch_batched_fit(BatchState* bs, int grid, hipStream_t s, bool coop
 int batched_max_blocks_per_cu();
 
 // Launchers (lloyd_kernels.hip).  `vec`: X is 16-byte aligned with ld % 4 == 0.
+// `keys`: 0 = VALU scan, 1 / 2 = matrix-core scan with 1 / 2 tiles of 32 centres.
 hipError_t launch_scan(State* st, int d, bool vec, int grid, hipStream_t s);
-hipError_t launch_iter(State* st, int d, bool vec, int grid, hipStream_t s);
-hipError_t launch_label(State* st, int32_t* labels, int d, bool vec, int grid,
+hipError_t launch_iter(State* st, int d, bool vec, int keys, int grid, hipStream_t s);
+hipError_t launch_label(State* st, int32_t* labels, int d, bool vec, int keys, int grid,
                         hipStream_t s);
 
 }  // namespace km

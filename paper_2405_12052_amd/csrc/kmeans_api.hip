@@ -144,8 +144,9 @@ void stage(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, int K,
     }
 }
 
-int get_graph(kmeans_ctx* c, int d, bool vec, int grid, int unroll, hipGraphExec_t* out) {
-    km::GraphKey key{d, vec ? 1 : 0, grid, unroll};
+int get_graph(kmeans_ctx* c, int d, bool vec, int keys, int grid, int unroll,
+              hipGraphExec_t* out) {
+    km::GraphKey key{d, vec ? 1 : 0, keys, grid, unroll};
     auto it = c->graphs.find(key);
     if (it != c->graphs.end()) {
         *out = it->second;
@@ -154,7 +155,7 @@ int get_graph(kmeans_ctx* c, int d, bool vec, int grid, int unroll, hipGraphExec
     hipGraph_t g = nullptr;
     KM_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     for (int i = 0; i < unroll; ++i) {
-        hipError_t e = km::launch_iter(c->st, d, vec, grid, c->cap_stream);
+        hipError_t e = km::launch_iter(c->st, d, vec, keys, grid, c->cap_stream);
         if (e != hipSuccess) {
             hipGraph_t junk = nullptr;
             (void)hipStreamEndCapture(c->cap_stream, &junk);
@@ -172,16 +173,29 @@ int get_graph(kmeans_ctx* c, int d, bool vec, int grid, int unroll, hipGraphExec
     return KM_OK;
 }
 
-int run_iterations(kmeans_ctx* c, int d, bool vec, int grid, int n_iter) {
+int run_iterations(kmeans_ctx* c, int d, bool vec, int keys, int grid, int n_iter) {
     if (c->use_graph) {
         hipGraphExec_t ex;
-        int rc = get_graph(c, d, vec, grid, n_iter, &ex);
+        int rc = get_graph(c, d, vec, keys, grid, n_iter, &ex);
         if (rc) return rc;
         KM_HIP(c, hipGraphLaunch(ex, c->stream));
     } else {
-        for (int i = 0; i < n_iter; ++i) KM_HIP(c, km::launch_iter(c->st, d, vec, grid, c->stream));
+        for (int i = 0; i < n_iter; ++i)
+            KM_HIP(c, km::launch_iter(c->st, d, vec, keys, grid, c->stream));
     }
     return KM_OK;
+}
+
+// Scan variant for K centres.  Automatic = the VALU scan: on gfx950 the FP32
+// matrix-core instructions do not execute alongside VALU instructions
+// (measured: no co-execution cycles), so the matrix-core scan pays its MFMA
+// time on top of its remaining VALU work and is slower at K = 64 (2.44 ms vs
+// 2.00 ms per update at N = 2e8).  It stays selectable.
+int scan_keys(kmeans_ctx* c, int K) {
+    const int tiles = K > 32 ? 2 : 1;
+    if (c->keys == 1) return 0;
+    if (c->keys == 2) return tiles;
+    return 0;
 }
 
 int auto_unroll(int64_t N, int max_iter) {
@@ -301,6 +315,10 @@ int kmeans_set_option(kmeans_ctx* c, int32_t option, int64_t value) {
             if (value != 0 && value != 1) return fail(c, KM_EINVAL, "KM_OPT_TIMING takes 0 or 1");
             c->timing = (int)value;
             return KM_OK;
+        case KM_OPT_KEYS:
+            if (value < 0 || value > 2) return fail(c, KM_EINVAL, "KM_OPT_KEYS takes 0, 1 or 2");
+            c->keys = (int)value;
+            return KM_OK;
         default:
             return fail(c, KM_EINVAL, "unknown option %d", option);
     }
@@ -321,7 +339,7 @@ int kmeans_assign(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int32_t 
     stage(c, X, N, ld, d, K, centroids, 0.0, 1);
     KM_HIP(c, hipMemcpyAsync(c->st, c->st_h, km::kUploadBytes, hipMemcpyHostToDevice, c->stream));
     KM_HIP(c, km::launch_scan(c->st, d, vec, grid, c->stream));
-    KM_HIP(c, km::launch_label(c->st, labels, d, vec, grid, c->stream));
+    KM_HIP(c, km::launch_label(c->st, labels, d, vec, scan_keys(c, K), grid, c->stream));
     KM_HIP(c, hipMemcpyAsync(reinterpret_cast<char*>(c->st_h) + km::kProgressOffset,
                              reinterpret_cast<char*>(c->st) + km::kProgressOffset,
                              km::kProgressBytes, hipMemcpyDeviceToHost, c->stream));
@@ -367,7 +385,7 @@ int kmeans_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int32_t d, 
             if (rc) return rc;
             KM_HIP(c, hipEventRecord(c->ev[2 * batches], c->stream));
         }
-        rc = run_iterations(c, d, vec, grid, n);
+        rc = run_iterations(c, d, vec, scan_keys(c, K), grid, n);
         if (rc) return rc;
         if (c->timing) KM_HIP(c, hipEventRecord(c->ev[2 * batches + 1], c->stream));
         launched += n;
@@ -380,7 +398,7 @@ int kmeans_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int32_t d, 
             if (h->done) break;
         }
     }
-    KM_HIP(c, km::launch_label(c->st, labels_out, d, vec, grid, c->stream));
+    KM_HIP(c, km::launch_label(c->st, labels_out, d, vec, scan_keys(c, K), grid, c->stream));
     KM_HIP(c, hipMemcpyAsync(reinterpret_cast<char*>(h) + km::kProgressOffset,
                              reinterpret_cast<char*>(c->st) + km::kProgressOffset,
                              km::kUploadBytes - km::kProgressOffset, hipMemcpyDeviceToHost,

@@ -26,6 +26,7 @@
 // wave with a fixed butterfly and across waves, blocks and groups in index
 // order.
 #include "lloyd_device.h"
+#include "lloyd_mfma.h"
 
 namespace km {
 namespace {
@@ -181,8 +182,23 @@ __global__ __launch_bounds__(BLOCK) void km_scan(State* __restrict__ st) {
     }
 }
 
+// The reassignment scan: KT == 0 the VALU keys (assign_points), KT = 1, 2 the
+// matrix-core keys with KT tiles of 32 centres (assign_points_mfma).  Both
+// give the same labels.
+template <int D, bool VEC, int KT, typename Sink>
+__device__ __forceinline__ void scan_points(const float* __restrict__ X, int64_t ld, int64_t N,
+                                            const float4* __restrict__ scand,
+                                            const float4* __restrict__ smu, int K, int ntri,
+                                            float4 bnd, float ninf, float4* __restrict__ wq,
+                                            Sink&& sink) {
+    if constexpr (KT == 0)
+        assign_points<D, VEC>(X, ld, N, scand, smu, K, ntri, bnd, ninf, wq, sink);
+    else
+        assign_points_mfma<D, VEC, KT>(X, ld, N, scand, smu, K, bnd, ninf, wq, sink);
+}
+
 // ---------------------------------------------------------------- lloyd_iter
-template <int D, bool VEC>
+template <int D, bool VEC, int KT>
 __global__ __launch_bounds__(BLOCK) void lloyd_iter(State* __restrict__ st) {
     if (st->done) return;
     constexpr int R = D + 1;  // per cluster: D sums, 1 count
@@ -213,8 +229,8 @@ __global__ __launch_bounds__(BLOCK) void lloyd_iter(State* __restrict__ st) {
 
     double jl = 0.0;
     unsigned long long* myacc = sacc[w];
-    assign_points<D, VEC>(X, ld, N, scand, smu, K, ntri, bnd, ninf, squeue[w],
-                          [&](int64_t, float x0, float x1, float x2, int k, float dist) {
+    scan_points<D, VEC, KT>(X, ld, N, scand, smu, K, ntri, bnd, ninf, squeue[w],
+                            [&](int64_t, float x0, float x1, float x2, int k, float dist) {
         unsigned long long* a = &myacc[k * R];
         const float xs[3] = {x0, x1, x2};
 #pragma unroll
@@ -280,7 +296,7 @@ __global__ __launch_bounds__(BLOCK) void lloyd_iter(State* __restrict__ st) {
 }
 
 // ---------------------------------------------------------------- lloyd_label
-template <int D, bool VEC>
+template <int D, bool VEC, int KT>
 __global__ __launch_bounds__(BLOCK) void lloyd_label(State* __restrict__ st,
                                                      int32_t* __restrict__ labels) {
     if (st->flags & FLAG_NONFINITE) return;
@@ -298,8 +314,8 @@ __global__ __launch_bounds__(BLOCK) void lloyd_label(State* __restrict__ st,
     const int ntri = stage_centres(st, K, scand, smu);
     __syncthreads();
     double jl = 0.0;
-    assign_points<D, VEC>(X, ld, N, scand, smu, K, ntri, bnd, ninf, squeue[w],
-                          [&](int64_t i, float, float, float, int k, float dist) {
+    scan_points<D, VEC, KT>(X, ld, N, scand, smu, K, ntri, bnd, ninf, squeue[w],
+                            [&](int64_t i, float, float, float, int k, float dist) {
         if (labels) labels[i] = k;
         jl += (double)dist;
     });
@@ -328,22 +344,49 @@ __global__ __launch_bounds__(BLOCK) void lloyd_label(State* __restrict__ st,
         else return hipErrorInvalidValue;                                             \
     } while (0)
 
+// The scan variants: keys 0 = VALU, 1 / 2 = matrix cores with 1 / 2 tiles of
+// 32 centres.
+#define KM_DISPATCH_SCAN(KERNEL, GRID, STREAM, ...)                                   \
+    do {                                                                              \
+        if (keys == 0) {                                                              \
+            if (d == 2 && vec)      hipLaunchKernelGGL((KERNEL<2, true, 0>), dim3(GRID), dim3(BLOCK), 0, STREAM, __VA_ARGS__); \
+            else if (d == 2)        hipLaunchKernelGGL((KERNEL<2, false, 0>), dim3(GRID), dim3(BLOCK), 0, STREAM, __VA_ARGS__); \
+            else if (d == 3 && vec) hipLaunchKernelGGL((KERNEL<3, true, 0>), dim3(GRID), dim3(BLOCK), 0, STREAM, __VA_ARGS__); \
+            else if (d == 3)        hipLaunchKernelGGL((KERNEL<3, false, 0>), dim3(GRID), dim3(BLOCK), 0, STREAM, __VA_ARGS__); \
+            else return hipErrorInvalidValue;                                         \
+        } else if (keys == 1) {                                                       \
+            if (d == 2 && vec)      hipLaunchKernelGGL((KERNEL<2, true, 1>), dim3(GRID), dim3(BLOCK), 0, STREAM, __VA_ARGS__); \
+            else if (d == 2)        hipLaunchKernelGGL((KERNEL<2, false, 1>), dim3(GRID), dim3(BLOCK), 0, STREAM, __VA_ARGS__); \
+            else if (d == 3 && vec) hipLaunchKernelGGL((KERNEL<3, true, 1>), dim3(GRID), dim3(BLOCK), 0, STREAM, __VA_ARGS__); \
+            else if (d == 3)        hipLaunchKernelGGL((KERNEL<3, false, 1>), dim3(GRID), dim3(BLOCK), 0, STREAM, __VA_ARGS__); \
+            else return hipErrorInvalidValue;                                         \
+        } else if (keys == 2) {                                                       \
+            if (d == 2 && vec)      hipLaunchKernelGGL((KERNEL<2, true, 2>), dim3(GRID), dim3(BLOCK), 0, STREAM, __VA_ARGS__); \
+            else if (d == 2)        hipLaunchKernelGGL((KERNEL<2, false, 2>), dim3(GRID), dim3(BLOCK), 0, STREAM, __VA_ARGS__); \
+            else if (d == 3 && vec) hipLaunchKernelGGL((KERNEL<3, true, 2>), dim3(GRID), dim3(BLOCK), 0, STREAM, __VA_ARGS__); \
+            else if (d == 3)        hipLaunchKernelGGL((KERNEL<3, false, 2>), dim3(GRID), dim3(BLOCK), 0, STREAM, __VA_ARGS__); \
+            else return hipErrorInvalidValue;                                         \
+        } else {                                                                      \
+            return hipErrorInvalidValue;                                              \
+        }                                                                             \
+    } while (0)
+
 hipError_t launch_scan(State* st, int d, bool vec, int grid, hipStream_t s) {
     if (grid < 1 || grid > MAX_BLOCKS) return hipErrorInvalidValue;
     KM_DISPATCH(km_scan, grid, s, st);
     return hipGetLastError();
 }
 
-hipError_t launch_iter(State* st, int d, bool vec, int grid, hipStream_t s) {
+hipError_t launch_iter(State* st, int d, bool vec, int keys, int grid, hipStream_t s) {
     if (grid < 1 || grid > MAX_BLOCKS) return hipErrorInvalidValue;
-    KM_DISPATCH(lloyd_iter, grid, s, st);
+    KM_DISPATCH_SCAN(lloyd_iter, grid, s, st);
     return hipGetLastError();
 }
 
-hipError_t launch_label(State* st, int32_t* labels, int d, bool vec, int grid,
+hipError_t launch_label(State* st, int32_t* labels, int d, bool vec, int keys, int grid,
                         hipStream_t s) {
     if (grid < 1 || grid > MAX_BLOCKS) return hipErrorInvalidValue;
-    KM_DISPATCH(lloyd_label, grid, s, st, labels);
+    KM_DISPATCH_SCAN(lloyd_label, grid, s, st, labels);
     return hipGetLastError();
 }
 

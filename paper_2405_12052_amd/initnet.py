@@ -12,6 +12,14 @@ float64 reference implementation).  Points and targets are normalised by the
 instance's mean and scalar standard deviation.
 
     python -m paper_2405_12052_amd.initnet train TARGETS.npz OUT.npy [--epochs E]
+
+The shipped weights (weights/initnet_c5_k16.npy) come from that command with
+its defaults (40 epochs of Adam, batch 256, learning rate 5e-3 decaying
+exponentially to 1e-4, 2048 instances held out) on 200,000 instances with
+seeds 1,000,000 + i, targets from
+    python oracle/make_initnet_targets.py T.npz --n 200000 --base 1000000
+Held-out matched loss: 233.6 at initialisation, 11.56 after training (sum
+over the 16 centres of squared errors in normalised units).
 """
 from __future__ import annotations
 
@@ -88,7 +96,7 @@ def load_training_set(targets_path, log=print):
     return torch.from_numpy(pts).cuda(), torch.from_numpy(tg).cuda()
 
 
-def train(targets_path, out_path, epochs=8, batch=256, lr=2e-3, lr_end=1e-4, holdout=2048,
+def train(targets_path, out_path, epochs=40, batch=256, lr=5e-3, lr_end=1e-4, holdout=2048,
           seed=0, log=print, data=None):
     """Adam on the matched loss; the last `holdout` instances are held out.
     `data` = load_training_set(...) output, to reuse loaded points."""
@@ -152,9 +160,9 @@ def main():
     t = sub.add_parser("train")
     t.add_argument("targets")
     t.add_argument("out")
-    t.add_argument("--epochs", type=int, default=8)
+    t.add_argument("--epochs", type=int, default=40)
     t.add_argument("--batch", type=int, default=256)
-    t.add_argument("--lr", type=float, default=2e-3)
+    t.add_argument("--lr", type=float, default=5e-3)
     a = ap.parse_args()
     if a.cmd == "train":
         train(a.targets, a.out, epochs=a.epochs, batch=a.batch, lr=a.lr,

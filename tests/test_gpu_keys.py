@@ -1,0 +1,111 @@
+"""The two reassignment scans (keys on the vector ALUs, KM_OPT_KEYS = 1, and
+on the matrix cores, KM_OPT_KEYS = 2) must give identical labels, centres, E
+and T: both certify the exact argmin of the keys of the float32 centres and
+re-scan the rest in the direct form.  Only the objective's float64 summation
+order differs.  (Parity of the default scan, the VALU one, with the oracle is
+covered by the other GPU test files.)"""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from parity import label_check
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def km():
+    from paper_2405_12052_amd import KMeans
+    k = KMeans(0)
+    yield k
+    k.set_option(5, 0)
+    k.close()
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def both(km, fn):
+    from paper_2405_12052_amd import KM_OPT_KEYS
+    out = []
+    for keys in (1, 2):
+        km.set_option(KM_OPT_KEYS, keys)
+        out.append(fn())
+    km.set_option(KM_OPT_KEYS, 0)
+    return out
+
+
+@pytest.mark.parametrize("name,d,K,N", [
+    ("C3", 3, 64, 1_000_003), ("C2", 3, 17, 300_001), ("C2", 2, 33, 200_001),
+    ("C2", 3, 32, 100_000), ("C2", 2, 64, 5_003), ("C2", 3, 4, 70_001), ("C2", 3, 16, 1)])
+def test_fit_identical_across_scans(km, name, d, K, N):
+    log(f"keys fit {name} d={d} K={K} N={N}")
+    kw = {"N": N, "K": K} if name == "C2" else {"N": N}
+    if name == "C2":
+        kw["d"] = d
+    s = datagen.spec(name, seed=7100 + K + N, **kw)
+    X, _ = datagen.generate(s)
+    Xd = torch.from_numpy(X).cuda()
+    Kf = min(K, N)
+    mu0 = datagen.init_sample(X, N, Kf, 3)
+    a, b = both(km, lambda: km.fit(Xd, mu0, tol=1e-6, max_iter=30))
+    assert a.iters == b.iters
+    assert np.array_equal(a.centroids, b.centroids)
+    assert a.E == b.E
+    assert np.array_equal(a.labels.cpu().numpy(), b.labels.cpu().numpy())
+    assert b.objective == pytest.approx(a.objective, rel=1e-9)
+    # and the matrix-core scan against the oracle on the final centres
+    mism, near, _, _ = label_check(b.labels.cpu().numpy(), X, b.centroids, N)
+    log(f"  T={b.iters} mismatches vs oracle {mism} (near-ties {near})")
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_assign_ties_identical_across_scans(km, d):
+    """Tie-heavy integer grid: many points fail both certificates and take
+    the direct-form re-scan with its lowest-index rule."""
+    rng = np.random.default_rng(70 + d)
+    N, K = 200_003, 48
+    X = rng.integers(-5, 6, size=(d, N)).astype(np.float32)
+    mu = (rng.integers(-5, 5, size=(K, d)) + 0.5).astype(np.float64)
+    mu[:, 0] = np.round(mu[:, 0])
+    Xd = torch.from_numpy(X).cuda()
+    (la, Ja), (lb, Jb) = both(km, lambda: km.assign(Xd, mu))
+    ref, dmin, dsec = oracle.assign(X, mu)
+    assert (dsec == dmin).mean() > 0.1
+    assert np.array_equal(la.cpu().numpy(), ref)
+    assert np.array_equal(lb.cpu().numpy(), ref)
+    assert Jb == pytest.approx(Ja, rel=1e-12)
+
+
+def test_far_points_and_large_offsets(km):
+    """Points far from every centre and data offset from the origin: keys
+    are dominated by |m|^2 and 2 m.x, the regime where the rounding bound
+    matters most."""
+    rng = np.random.default_rng(80)
+    N, K = 150_001, 40
+    X = (rng.normal(size=(3, N)) * 3 + 1000.0).astype(np.float32)
+    X[:, ::97] += 5000.0                   # a sprinkle of far outliers
+    mu = (rng.normal(size=(K, 3)) * 3 + 1000.0)
+    Xd = torch.from_numpy(X).cuda()
+    (la, _), (lb, _) = both(km, lambda: km.assign(Xd, mu))
+    assert np.array_equal(la.cpu().numpy(), lb.cpu().numpy())
+    mism, near, _, _ = label_check(lb.cpu().numpy(), X, mu, N)
+    log(f"  far/offset: mismatches vs oracle {mism} (near-ties {near})")
+
+
+def test_unaligned_rows_identical_across_scans(km):
+    N, ld, K = 90_001, 90_003, 37
+    s = datagen.spec("C2", N=N, K=K, seed=7200)
+    X, _ = datagen.generate(s)
+    buf = torch.zeros(3 * ld + 1, dtype=torch.float32, device="cuda")
+    Xu = buf[1:1 + 3 * ld].view(3, ld)      # rows 4 bytes off 16-byte alignment
+    Xu[:, :N] = torch.from_numpy(X).cuda()
+    mu0 = datagen.init_sample(X, N, K, 5)
+    a, b = both(km, lambda: km.fit(Xu, mu0, tol=1e-6, max_iter=20, N=N))
+    assert a.iters == b.iters
+    assert np.array_equal(a.centroids, b.centroids)
+    assert np.array_equal(a.labels.cpu().numpy(), b.labels.cpu().numpy())
