@@ -41,9 +41,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ["lloyd_kernels.hip", "lloyd_device.h", "lloyd_mfma.h", "km_internal.h"]
+
+
 def kernel_source_hash() -> str:
-    p = os.path.join(ROOT, "paper_2405_12052_amd", "csrc", "lloyd_kernels.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    """Hash of the sources the iteration kernel is compiled from."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2405_12052_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def traffic_from_profile(name: str):
@@ -264,12 +270,31 @@ def main():
                     help="instances (batched: 4096, learned: 100)")
     ap.add_argument("--repeats", type=int, default=3)
     ap.add_argument("--weights", default=None, help="learned initialiser weights (.npy)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="before the workload, copy a device buffer of BYTES twice (a plain "
+                         "copy kernel of known size, to calibrate traffic counters)")
+    ap.add_argument("--print-source-hash", action="store_true")
+    ap.add_argument("--keys", type=int, default=0, choices=[0, 1, 2],
+                    help="reassignment scan (KM_OPT_KEYS): 0 automatic, 1 VALU, 2 matrix cores")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU data-parallel design is described, not built)", file=sys.stderr)
         sys.exit(2)
 
+    if args.print_source_hash:
+        print(kernel_source_hash())
+        return
+    if args.copy_probe:
+        import torch
+        n = args.copy_probe // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(2):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log(f"copy probe: 2 x {args.copy_probe} bytes")
     if args.workload == "batched":
         args.instances = args.instances or 4096
         bench_batched(args)
@@ -283,7 +308,7 @@ def main():
     import torch
 
     import datagen
-    from paper_2405_12052_amd import KM_OPT_TIMING, KMeans
+    from paper_2405_12052_amd import KM_OPT_KEYS, KM_OPT_TIMING, KMeans
 
     s = datagen.spec("C3") if args.N is None else datagen.spec("C3", N=args.N)
     t0 = time.time()
@@ -295,6 +320,7 @@ def main():
 
     km = KMeans(0)
     km.set_option(KM_OPT_TIMING, 1)
+    km.set_option(KM_OPT_KEYS, args.keys)
     for i in range(args.warmup):
         r = km.fit(Xd, mu0, tol=0.0, max_iter=args.iters)
         log(f"warmup {i}: T={r.iters} J={r.objective:.6e}")
@@ -318,8 +344,10 @@ def main():
     achieved = flops / avg_kernel_s / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": traffic_from_profile("lloyd_iter_C3_traffic.json"),
-            "kernel": "lloyd_iter<3,true>", "avg_launch_us": avg_kernel_s * 1e6,
+            "traffic": (traffic_from_profile("lloyd_iter_C3_traffic.json")
+                        if args.keys != 2 and args.N is None else None),
+            "kernel": f"lloyd_iter<{s.d},true,{0 if args.keys != 2 else (2 if s.K > 32 else 1)}>",
+            "avg_launch_us": avg_kernel_s * 1e6,
             "alg_flops_per_launch": flops,
             "alg_bytes_per_launch": alg_bytes_per_point(s.d) * s.N,
             "hbm_gbs_alg": alg_bytes_per_point(s.d) * s.N / avg_kernel_s / 1e9}
