@@ -54,30 +54,31 @@ struct BSmem {
 };
 
 // Team barrier: every block of the team arrives once per call; nbar counts
-// the calls (the same sequence in every block of the team).  The wait is
+// the calls (the same sequence in every block of the team).  Data handed
+// across it moves as device-coherent stores and loads (lloyd_device.h): each
+// thread waits for its stores before the block arrives.  The wait is
 // bounded: after about a second of polling, or when another team has timed
 // out, the block records the error and returns false, so no wave can spin
 // forever.
 __device__ bool team_barrier(BatchState* __restrict__ bs, BTeam* tm, uint32_t& nbar, int S,
                              int* sflag) {
-    __threadfence();
+    wait_mem();
     __syncthreads();
     nbar += 1;
     if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(&tm->bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&tm->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint32_t target = nbar * (uint32_t)S;
         uint32_t spins = 0;
         int ok = 1;
-        while (__hip_atomic_load(&tm->bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (ld_agent(&tm->bar) < target) {
             __builtin_amdgcn_s_sleep(8);
             ++spins;
-            if ((spins & 255u) == 0 &&
-                __hip_atomic_load(&bs->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            if ((spins & 255u) == 0 && ld_agent(&bs->error)) {
                 ok = 0;
                 break;
             }
             if (spins > (1u << 21)) {
-                __hip_atomic_store(&bs->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                st_agent(&bs->error, 1);
                 ok = 0;
                 break;
             }
@@ -85,7 +86,6 @@ __device__ bool team_barrier(BatchState* __restrict__ bs, BTeam* tm, uint32_t& n
         *sflag = ok;
     }
     __syncthreads();
-    __threadfence();
     return *sflag != 0;
 }
 
@@ -249,12 +249,12 @@ __device__ bool run_instance(BatchState* __restrict__ bs, int inst, int rank, in
         if (S > 1) {
             const uint32_t par = nbar & 1u;
             unsigned long long* dst = tpart + ((size_t)par * S + rank) * BK_PART;
-            for (int i = tid; i < nacc; i += BLOCK) dst[i] = sm.acc[i];
+            for (int i = tid; i < nacc; i += BLOCK) st_agent(&dst[i], sm.acc[i]);
             if (!team_barrier(bs, tm, nbar, S, &sm.flag)) return false;
             const unsigned long long* src = tpart + (size_t)par * S * BK_PART;
             for (int i = tid; i < nacc; i += BLOCK) {
                 unsigned long long s = 0ull;
-                for (int q = 0; q < S; ++q) s += src[(size_t)q * BK_PART + i];
+                for (int q = 0; q < S; ++q) s += ld_agent(&src[(size_t)q * BK_PART + i]);
                 sm.acc[i] = s;
             }
             __syncthreads();
@@ -311,12 +311,12 @@ __device__ bool run_instance(BatchState* __restrict__ bs, int inst, int rank, in
         if (S > 1) {
             const uint32_t par = nbar & 1u;
             double* dst = tjpart + ((size_t)par * S + rank) * BK_RMAX;
-            if (tid < R) dst[tid] = sm.J[tid];
+            if (tid < R) st_agent(&dst[tid], sm.J[tid]);
             if (!team_barrier(bs, tm, nbar, S, &sm.flag)) return false;
             const double* src = tjpart + (size_t)par * S * BK_RMAX;
             if (tid < R) {
                 double s = 0.0;
-                for (int q = 0; q < S; ++q) s += src[(size_t)q * BK_RMAX + tid];
+                for (int q = 0; q < S; ++q) s += ld_agent(&src[(size_t)q * BK_RMAX + tid]);
                 sm.J[tid] = s;
             }
             __syncthreads();
@@ -428,10 +428,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
         for (;;) {
             if (rank == 0 && threadIdx.x == 0) {
                 const uint32_t idx = atomicAdd(&bs->big_ctr, 1u);
-                tm->inst = idx < (uint32_t)bs->n_big ? bs->order_big[idx] : -1;
+                st_agent(&tm->inst, idx < (uint32_t)bs->n_big ? bs->order_big[idx] : -1);
             }
             if (!team_barrier(bs, tm, nbar, S, &sm.flag)) return;
-            if (threadIdx.x == 0) sm.inst = tm->inst;
+            if (threadIdx.x == 0) sm.inst = ld_agent(&tm->inst);
             __syncthreads();
             const int inst = sm.inst;
             __syncthreads();

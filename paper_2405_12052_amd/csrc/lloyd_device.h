@@ -39,10 +39,24 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
     return v;
 }
 
+// Data that blocks of one kernel hand to each other (partial sums, tickets'
+// payloads) travel as device-coherent stores and loads: relaxed atomics at
+// device scope, which write through and read past the per-XCD L2 caches.
+// The writer waits for its stores to complete before it signals (wait_mem),
+// and the reader loads after it has seen the signal.  This replaces
+// device-scope fences, each of which writes back and invalidates a whole L2.
 template <typename T>
 __device__ __forceinline__ T ld_agent(const T* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+
+template <typename T>
+__device__ __forceinline__ void st_agent(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until this thread's memory operations have completed.
+__device__ __forceinline__ void wait_mem() { __builtin_amdgcn_s_waitcnt(0); }
 
 // Fixed-point exponent: every |x| * 2^G < 2^30 for |x| <= max|x|.
 __device__ __forceinline__ int scale_exponent(uint32_t absmax_bits) {

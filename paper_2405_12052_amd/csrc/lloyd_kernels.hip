@@ -34,26 +34,23 @@ namespace {
 // Publish this block's objective partial and take a ticket; true in the last
 // block of the grid to arrive (single-level; used by the label kernel).
 __device__ bool finish_block(uint32_t* ticket, double* jslot, double jblock, int* sflag) {
-    __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
-        *jslot = jblock;
-        __threadfence();
-        const uint32_t old = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL,
+        st_agent(jslot, jblock);
+        wait_mem();
+        const uint32_t old = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT);
         *sflag = (old == gridDim.x - 1);
     }
     __syncthreads();
-    const bool last = *sflag != 0;
-    if (last) __threadfence();
-    return last;
+    return *sflag != 0;
 }
 
 // Sum of the per-block objective partials in block order; whole block.
 __device__ double sum_partials(const double* __restrict__ jpart, int nb, double* sred) {
     const int tid = threadIdx.x;
     double s = 0.0;
-    for (int b = tid; b < nb; b += BLOCK) s += jpart[b];
+    for (int b = tid; b < nb; b += BLOCK) s += ld_agent(&jpart[b]);
     s = wave_sum(s);
     __syncthreads();
     if ((tid & 63) == 0) sred[tid >> 6] = s;
@@ -70,60 +67,59 @@ __device__ double sum_partials(const double* __restrict__ jpart, int nb, double*
 // group sums.  Returns true in that one final block, with the grid totals in
 // tot[0..nr) (LDS) and the objective in *jtot.  No two blocks add to the same
 // address, so there is no contention; the integer sums are exact in any order
-// and the objective is added in block, then group, order.
+// and the objective is added in block, then group, order.  Partials move as
+// device-coherent stores and loads (see lloyd_device.h).
 __device__ bool reduce_grid(State* __restrict__ st, const unsigned long long* blk, int nr,
                             double jb, unsigned long long* tot, double* jtot, int* sflag) {
     const int tid = threadIdx.x;
     const int b = blockIdx.x, nb = gridDim.x;
     unsigned long long* mine = st->part + (size_t)b * PART;
-    for (int i = tid; i < nr; i += BLOCK) mine[i] = blk[i];
-    if (tid == 0) st->jpart[b] = jb;
-    __threadfence();
+    for (int i = tid; i < nr; i += BLOCK) st_agent(&mine[i], blk[i]);
+    if (tid == 0) st_agent(&st->jpart[b], jb);
+    wait_mem();
     __syncthreads();
     const int grp = b / GROUP, g0 = grp * GROUP;
     const int gn = (nb - g0) < GROUP ? (nb - g0) : GROUP;
     if (tid == 0) {
-        const uint32_t old = __hip_atomic_fetch_add(&st->gticket[grp], 1u, __ATOMIC_ACQ_REL,
+        const uint32_t old = __hip_atomic_fetch_add(&st->gticket[grp], 1u, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT);
         *sflag = (old == (uint32_t)gn - 1);
     }
     __syncthreads();
     if (!*sflag) return false;
-    __threadfence();
     // last block of its group
     for (int i = tid; i < nr; i += BLOCK) {
         unsigned long long s = 0ull;
-        for (int q = 0; q < gn; ++q) s += st->part[(size_t)(g0 + q) * PART + i];
-        st->gpart[(size_t)grp * PART + i] = s;
+        for (int q = 0; q < gn; ++q) s += ld_agent(&st->part[(size_t)(g0 + q) * PART + i]);
+        st_agent(&st->gpart[(size_t)grp * PART + i], s);
     }
     if (tid == 0) {
         double j = 0.0;
-        for (int q = 0; q < gn; ++q) j += st->jpart[g0 + q];
-        st->gjpart[grp] = j;
-        st->gticket[grp] = 0u;
+        for (int q = 0; q < gn; ++q) j += ld_agent(&st->jpart[g0 + q]);
+        st_agent(&st->gjpart[grp], j);
+        st_agent(&st->gticket[grp], 0u);
     }
-    __threadfence();
+    wait_mem();
     __syncthreads();
     const int ng = (nb + GROUP - 1) / GROUP;
     if (tid == 0) {
-        const uint32_t old = __hip_atomic_fetch_add(&st->ticket, 1u, __ATOMIC_ACQ_REL,
+        const uint32_t old = __hip_atomic_fetch_add(&st->ticket, 1u, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT);
         *sflag = (old == (uint32_t)ng - 1);
     }
     __syncthreads();
     if (!*sflag) return false;
-    __threadfence();
     // the final block
     for (int i = tid; i < nr; i += BLOCK) {
         unsigned long long s = 0ull;
-        for (int q = 0; q < ng; ++q) s += st->gpart[(size_t)q * PART + i];
+        for (int q = 0; q < ng; ++q) s += ld_agent(&st->gpart[(size_t)q * PART + i]);
         tot[i] = s;
     }
     if (tid == 0) {
         double j = 0.0;
-        for (int q = 0; q < ng; ++q) j += st->gjpart[q];
+        for (int q = 0; q < ng; ++q) j += ld_agent(&st->gjpart[q]);
         *jtot = j;
-        st->ticket = 0u;
+        st_agent(&st->ticket, 0u);
     }
     __syncthreads();
     return true;
@@ -160,14 +156,13 @@ __global__ __launch_bounds__(BLOCK) void km_scan(State* __restrict__ st) {
         uint32_t b = 0;
         for (int w = 0; w < NW; ++w) b = sm[w] > b ? sm[w] : b;
         __hip_atomic_fetch_max(&st->absmax_bits, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        const uint32_t old = __hip_atomic_fetch_add(&st->scan_ticket, 1u, __ATOMIC_ACQ_REL,
+        wait_mem();
+        const uint32_t old = __hip_atomic_fetch_add(&st->scan_ticket, 1u, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT);
         slast = (old == gridDim.x - 1);
     }
     __syncthreads();
     if (!slast) return;
-    __threadfence();
     prep_centres(st->mu32, st->K, st->cand, &st->bnd, sc, sa);
     for (int i = tid; i < MAX_GROUPS; i += BLOCK) st->gticket[i] = 0u;
     if (tid == 0) {

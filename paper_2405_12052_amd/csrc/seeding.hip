@@ -185,15 +185,17 @@ __global__ __launch_bounds__(PB) void pp_select(PPArgs a, int j) {
     if (threadIdx.x == 0) {
         unsigned long long t = 0;
         for (int w = 0; w < PB / 64; ++w) t += ws[w];
-        a.bsum[blockIdx.x] = t;
-        __threadfence();
-        const uint32_t old = __hip_atomic_fetch_add(&a.ticket[j], 1u, __ATOMIC_ACQ_REL,
+        // block sums travel as device-coherent stores and loads (they write
+        // through and read past the per-XCD L2 caches), so no device-wide
+        // fence is needed: the store completes before the ticket is taken
+        __hip_atomic_store(&a.bsum[blockIdx.x], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_waitcnt(0);
+        const uint32_t old = __hip_atomic_fetch_add(&a.ticket[j], 1u, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT);
         last = old == (uint32_t)(gridDim.x - 1);
     }
     __syncthreads();
     if (!last || threadIdx.x >= 64) return;
-    __threadfence();
     if (mb >= 0x7f800000u) {               // NaN or infinity among the D^2
         if (threadIdx.x == 0) {
             *a.flag = 1;
