@@ -84,11 +84,18 @@ enum km_option {
     KM_OPT_BLOCKS = 3,    /* grid size of the iteration kernel (0 = automatic) */
     KM_OPT_TIMING = 4,    /* 1: time the iteration launches with HIP events
                              (see kmeans_get_timing)                           */
-    KM_OPT_KEYS = 5       /* how the reassignment scan forms its keys
+    KM_OPT_KEYS = 5,      /* how the reassignment scan forms its keys
                              |m|^2 - 2 m.x: 0 (default) automatic (currently
                              the vector ALUs), 1 vector ALUs, 2 matrix cores
                              (FP32 MFMA; slower on gfx950, kept selectable).
                              Labels, centres, E and T do not depend on it.     */
+    KM_OPT_PERSIST = 6    /* how kmeans_fit runs its updates: 0 (default)
+                             automatic (one persistent cooperative launch for
+                             2^22 <= N <= 2^24 with the VALU scan, else graph
+                             replays of one launch per update), 1 always one
+                             launch per update, 2 persistent whenever the VALU
+                             scan is used and the grid fits on the device.
+                             Results do not depend on it.                      */
 };
 
 /*
@@ -162,7 +169,8 @@ int kmeans_get_history(kmeans_ctx *ctx, double *E, double *J, int32_t cap);
 /*
  * With KM_OPT_TIMING on: total device time (ms, HIP events on the context's
  * stream) of the iteration launches of the last kmeans_fit, and the number of
- * iteration kernels those launches contained.
+ * iteration kernels those launches contained (for a persistent fit: the one
+ * launch's time and the number of updates it performed).
  */
 int kmeans_get_timing(kmeans_ctx *ctx, double *iter_ms, int64_t *iter_kernels);
 

@@ -50,6 +50,8 @@ struct kmeans_ctx {
     int blocks = 0;
     int timing = 0;
     int keys = 0;                      // KM_OPT_KEYS
+    int persist = 0;                   // KM_OPT_PERSIST
+    int persist_bpc[2][2] = {{0, 0}, {0, 0}};  // resident blocks per CU of lloyd_persist [d==3][vec]
     // graph cache
     std::map<km::GraphKey, hipGraphExec_t> graphs;
     // timing of the last fit: one event pair per batch of iterations

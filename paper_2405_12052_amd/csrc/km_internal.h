@@ -18,7 +18,7 @@ constexpr int KPAD = 66;          // KMAX rounded up to whole triples of centres
 constexpr int PART = KMAX * (DMAX + 1);  // int64 slots of one block partial
 
 // Status flags written by the device.
-enum : int32_t { FLAG_NONFINITE = 1 };
+enum : int32_t { FLAG_NONFINITE = 1, FLAG_TIMEOUT = 2 };
 
 // One fit (or one reassignment pass) lives in this struct in device memory.
 // The host writes the problem fields and the initial centres before the
@@ -55,7 +55,7 @@ struct alignas(16) State {
     uint32_t absmax_bits;  // max |x| over the data, as float bits
     uint32_t ticket;       // blocks finished in the current kernel
     uint32_t scan_ticket;  // blocks finished in the scan kernel
-    uint32_t pad0;
+    uint32_t gen;          // updates published by a persistent fit
     // ---- centres ----
     double mu64[KMAX * DMAX];          // float64 centres, row-major K x d
     float4 mu32[KMAX];                 // the same rounded to float32, padded
@@ -136,5 +136,9 @@ hipError_t launch_scan(State* st, int d, bool vec, int grid, hipStream_t s);
 hipError_t launch_iter(State* st, int d, bool vec, int keys, int grid, hipStream_t s);
 hipError_t launch_label(State* st, int32_t* labels, int d, bool vec, int keys, int grid,
                         hipStream_t s);
+// The whole fit as one cooperative launch (VALU scan); grid must fit on the
+// device at persist_max_blocks_per_cu blocks per compute unit.
+hipError_t launch_persist(State* st, int d, bool vec, int grid, hipStream_t s);
+int persist_max_blocks_per_cu(int d, bool vec);
 
 }  // namespace km

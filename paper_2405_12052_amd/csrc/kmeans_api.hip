@@ -191,6 +191,18 @@ int run_iterations(kmeans_ctx* c, int d, bool vec, int keys, int grid, int n_ite
 // (measured: no co-execution cycles), so the matrix-core scan pays its MFMA
 // time on top of its remaining VALU work and is slower at K = 64 (2.44 ms vs
 // 2.00 ms per update at N = 2e8).  It stays selectable.
+// Persistent fit: selected (KM_OPT_PERSIST = 2), or automatically with the
+// VALU scan for 2^22 <= N <= 2^24.  Measured per update (K = 16): below 2^22
+// the launch per update is as fast or faster (15 vs 17 us at N = 1e5, 25 vs
+// 27 us at 1e6: both are bound by the same chain of device-wide round trips
+// of the reduction, not by the launches); from 4e6 to 1e7 the persistent fit
+// is 3-5 % faster; above 2^24 the two are equal within noise.
+bool use_persist(kmeans_ctx* c, int64_t N, int keys) {
+    if (keys != 0 || c->persist == 1) return false;
+    if (c->persist == 2) return true;
+    return N >= (1LL << 22) && N <= (1LL << 24);
+}
+
 int scan_keys(kmeans_ctx* c, int K) {
     const int tiles = K > 32 ? 2 : 1;
     if (c->keys == 1) return 0;
@@ -319,6 +331,10 @@ int kmeans_set_option(kmeans_ctx* c, int32_t option, int64_t value) {
             if (value < 0 || value > 2) return fail(c, KM_EINVAL, "KM_OPT_KEYS takes 0, 1 or 2");
             c->keys = (int)value;
             return KM_OK;
+        case KM_OPT_PERSIST:
+            if (value < 0 || value > 2) return fail(c, KM_EINVAL, "KM_OPT_PERSIST takes 0, 1 or 2");
+            c->persist = (int)value;
+            return KM_OK;
         default:
             return fail(c, KM_EINVAL, "unknown option %d", option);
     }
@@ -371,21 +387,47 @@ int kmeans_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int32_t d, 
     KM_HIP(c, hipMemcpyAsync(c->st, c->st_h, km::kUploadBytes, hipMemcpyHostToDevice, c->stream));
     KM_HIP(c, km::launch_scan(c->st, d, vec, grid, c->stream));
 
-    // Batches of U iterations; the device decides when to stop (kernels after
-    // convergence return at once), the host reads the progress block once per
-    // batch.  With tol == 0 the count is known and there is no read-back.
     c->iter_ms = 0.0;
     c->iter_kernels = 0;
     int launched = 0, batches = 0;
     State* h = c->st_h;
-    while (launched < max_iter) {
+    const int keys = scan_keys(c, K);
+
+    // Small N: the whole fit in one cooperative launch (lloyd_persist), which
+    // saves a kernel launch and its cache maintenance per update.
+    bool persisted = false;
+    if (use_persist(c, N, keys)) {
+        int& per_cu = c->persist_bpc[d == 3][vec ? 1 : 0];
+        if (per_cu == 0) per_cu = km::persist_max_blocks_per_cu(d, vec);
+        const int cap = c->n_cu * per_cu;
+        const int pgrid = grid < cap ? grid : cap;
+        if (pgrid >= 1) {
+            if (c->timing) {
+                rc = ensure_events(c, 2);
+                if (rc) return rc;
+                KM_HIP(c, hipEventRecord(c->ev[0], c->stream));
+            }
+            if (km::launch_persist(c->st, d, vec, pgrid, c->stream) == hipSuccess) {
+                persisted = true;
+                batches = 1;
+                if (c->timing) KM_HIP(c, hipEventRecord(c->ev[1], c->stream));
+            } else {
+                (void)hipGetLastError();  // not co-resident: use the per-update launches
+            }
+        }
+    }
+
+    // Batches of U iterations; the device decides when to stop (kernels after
+    // convergence return at once), the host reads the progress block once per
+    // batch.  With tol == 0 the count is known and there is no read-back.
+    while (!persisted && launched < max_iter) {
         const int n = (max_iter - launched) < U ? (max_iter - launched) : U;
         if (c->timing) {
             rc = ensure_events(c, 2 * (batches + 1));
             if (rc) return rc;
             KM_HIP(c, hipEventRecord(c->ev[2 * batches], c->stream));
         }
-        rc = run_iterations(c, d, vec, scan_keys(c, K), grid, n);
+        rc = run_iterations(c, d, vec, keys, grid, n);
         if (rc) return rc;
         if (c->timing) KM_HIP(c, hipEventRecord(c->ev[2 * batches + 1], c->stream));
         launched += n;
@@ -398,12 +440,14 @@ int kmeans_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int32_t d, 
             if (h->done) break;
         }
     }
-    KM_HIP(c, km::launch_label(c->st, labels_out, d, vec, scan_keys(c, K), grid, c->stream));
+    KM_HIP(c, km::launch_label(c->st, labels_out, d, vec, keys, grid, c->stream));
     KM_HIP(c, hipMemcpyAsync(reinterpret_cast<char*>(h) + km::kProgressOffset,
                              reinterpret_cast<char*>(c->st) + km::kProgressOffset,
                              km::kUploadBytes - km::kProgressOffset, hipMemcpyDeviceToHost,
                              c->stream));
     KM_HIP(c, hipStreamSynchronize(c->stream));
+    if (h->flags & km::FLAG_TIMEOUT)
+        return fail(c, KM_EHIP, "persistent fit: a block's wait for an update timed out");
     const int T = h->t;
     c->last_T = T;
     if (c->timing) {
@@ -412,7 +456,7 @@ int kmeans_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int32_t d, 
             KM_HIP(c, hipEventElapsedTime(&ms, c->ev[2 * b], c->ev[2 * b + 1]));
             c->iter_ms += ms;
         }
-        c->iter_kernels = launched;
+        c->iter_kernels = persisted ? T : launched;
     }
     const int nh = T < c->hist_cap ? T : c->hist_cap;
     if (nh > 0) {

@@ -61,6 +61,51 @@ __device__ double sum_partials(const double* __restrict__ jpart, int nb, double*
     return tot;
 }
 
+// For every entry i < nr: the integer sum over q < n of the partial P(q, i),
+// into out[i] (LDS).  The loads are spread over the whole block -- each
+// thread takes a slice of q for one entry, 8 device-coherent loads in
+// flight at a time -- and the slices are added in LDS (integer sums: the
+// order does not matter).  scr: LDS scratch of BLOCK values.
+template <typename F>
+__device__ __forceinline__ void sum_entries(int n, int nr, F P, unsigned long long* out,
+                            unsigned long long* scr) {
+    const int tid = threadIdx.x;
+    const int S = BLOCK / nr;                 // slices per entry (nr <= BLOCK)
+    const int slice = tid / nr, i = tid - slice * nr;
+    unsigned long long s = 0ull;
+    if (slice < S) {
+        const int per = (n + S - 1) / S;
+        const int q0 = slice * per;
+        const int q1 = q0 + per < n ? q0 + per : n;
+        for (int qb = q0; qb < q1; qb += 8) {
+            unsigned long long t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t[u] = qb + u < q1 ? P(qb + u, i) : 0ull;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += t[u];
+        }
+    }
+    scr[tid] = s;
+    __syncthreads();
+    for (int j = tid; j < nr; j += BLOCK) {
+        unsigned long long t = 0ull;
+        for (int sl = 0; sl < S; ++sl) t += scr[sl * nr + j];
+        out[j] = t;
+    }
+    __syncthreads();
+}
+
+// Sum of the n float64 values p[0..n) in index order (all loads in flight at
+// once, the additions by thread 0 from LDS); the result is valid in thread 0.
+__device__ __forceinline__ double sum_in_order(int n, const double* p, double* sj) {
+    for (int q = threadIdx.x; q < n; q += BLOCK) sj[q] = ld_agent(&p[q]);
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int q = 0; q < n; ++q) s += sj[q];
+    return s;
+}
+
 // Two-level reduction of the block partials (integer sums | counts, and the
 // objective).  Every block publishes its partial; the last block of each
 // group of GROUP blocks adds the group's partials; the last group adds the
@@ -69,8 +114,11 @@ __device__ double sum_partials(const double* __restrict__ jpart, int nb, double*
 // address, so there is no contention; the integer sums are exact in any order
 // and the objective is added in block, then group, order.  Partials move as
 // device-coherent stores and loads (see lloyd_device.h).
-__device__ bool reduce_grid(State* __restrict__ st, const unsigned long long* blk, int nr,
+__device__ __forceinline__ bool reduce_grid(State* __restrict__ st, const unsigned long long* blk, int nr,
                             double jb, unsigned long long* tot, double* jtot, int* sflag) {
+    __shared__ unsigned long long scr[BLOCK];
+    __shared__ unsigned long long gsum[PART];
+    __shared__ double sj[MAX_GROUPS];
     const int tid = threadIdx.x;
     const int b = blockIdx.x, nb = gridDim.x;
     unsigned long long* mine = st->part + (size_t)b * PART;
@@ -88,15 +136,13 @@ __device__ bool reduce_grid(State* __restrict__ st, const unsigned long long* bl
     __syncthreads();
     if (!*sflag) return false;
     // last block of its group
-    for (int i = tid; i < nr; i += BLOCK) {
-        unsigned long long s = 0ull;
-        for (int q = 0; q < gn; ++q) s += ld_agent(&st->part[(size_t)(g0 + q) * PART + i]);
-        st_agent(&st->gpart[(size_t)grp * PART + i], s);
-    }
+    const unsigned long long* part = st->part;
+    sum_entries(gn, nr, [&](int q, int i) { return ld_agent(&part[(size_t)(g0 + q) * PART + i]); },
+                gsum, scr);
+    for (int i = tid; i < nr; i += BLOCK) st_agent(&st->gpart[(size_t)grp * PART + i], gsum[i]);
+    const double jg = sum_in_order(gn, st->jpart + g0, sj);
     if (tid == 0) {
-        double j = 0.0;
-        for (int q = 0; q < gn; ++q) j += ld_agent(&st->jpart[g0 + q]);
-        st_agent(&st->gjpart[grp], j);
+        st_agent(&st->gjpart[grp], jg);
         st_agent(&st->gticket[grp], 0u);
     }
     wait_mem();
@@ -110,15 +156,12 @@ __device__ bool reduce_grid(State* __restrict__ st, const unsigned long long* bl
     __syncthreads();
     if (!*sflag) return false;
     // the final block
-    for (int i = tid; i < nr; i += BLOCK) {
-        unsigned long long s = 0ull;
-        for (int q = 0; q < ng; ++q) s += ld_agent(&st->gpart[(size_t)q * PART + i]);
-        tot[i] = s;
-    }
+    const unsigned long long* gpart = st->gpart;
+    sum_entries(ng, nr, [&](int q, int i) { return ld_agent(&gpart[(size_t)q * PART + i]); },
+                tot, scr);
+    const double jt = sum_in_order(ng, st->gjpart, sj);
     if (tid == 0) {
-        double j = 0.0;
-        for (int q = 0; q < ng; ++q) j += ld_agent(&st->gjpart[q]);
-        *jtot = j;
+        *jtot = jt;
         st_agent(&st->ticket, 0u);
     }
     __syncthreads();
@@ -193,38 +236,71 @@ __device__ __forceinline__ void scan_points(const float* __restrict__ X, int64_t
 }
 
 // ---------------------------------------------------------------- lloyd_iter
-template <int D, bool VEC, int KT>
-__global__ __launch_bounds__(BLOCK) void lloyd_iter(State* __restrict__ st) {
-    if (st->done) return;
-    constexpr int R = D + 1;  // per cluster: D sums, 1 count
-    __shared__ float4 scand[KPAD];
-    __shared__ float4 smu[KMAX];
-    __shared__ unsigned long long sacc[NW][KMAX * R];
-    __shared__ unsigned long long stot[KMAX * R];
-    __shared__ float4 squeue[NW][QCAP];
-    __shared__ double sred[NW];
-    __shared__ double sE[KMAX];
-    __shared__ int sEmpty[KMAX];
-    __shared__ float sc[KPAD];
-    __shared__ float sa[3 * KPAD];
-    __shared__ double sJ;
-    __shared__ int sflag;
+// LDS of one update.
+struct IterSmem {
+    float4 scand[KPAD];
+    float4 smu[KMAX];
+    unsigned long long sacc[NW][KMAX * (DMAX + 1)];
+    unsigned long long stot[KMAX * (DMAX + 1)];
+    float4 squeue[NW][QCAP];
+    double sred[NW];
+    double sE[KMAX];
+    int sEmpty[KMAX];
+    float sc[KPAD];
+    float sa[3 * KPAD];
+    float4 sbnd;
+    double sJ;
+    int sflag;
+    int sdone;
+};
 
+// float4 through four device-coherent 32-bit accesses (lloyd_device.h).
+__device__ __forceinline__ void st4_agent(float4* p, float4 v) {
+    float* f = reinterpret_cast<float*>(p);
+    st_agent(&f[0], v.x); st_agent(&f[1], v.y); st_agent(&f[2], v.z); st_agent(&f[3], v.w);
+}
+__device__ __forceinline__ float4 ld4_agent(const float4* p) {
+    const float* f = reinterpret_cast<const float*>(p);
+    return make_float4(ld_agent(&f[0]), ld_agent(&f[1]), ld_agent(&f[2]), ld_agent(&f[3]));
+}
+
+// Plain accesses for state that only later kernels (or the host) read, and
+// device-coherent ones for state that other blocks of the same (persistent)
+// kernel read.
+template <bool COH, typename T>
+__device__ __forceinline__ T rd(const T* p) {
+    if constexpr (COH) return ld_agent(p);
+    else return *p;
+}
+template <bool COH, typename T>
+__device__ __forceinline__ void wr(T* p, T v) {
+    if constexpr (COH) st_agent(p, v);
+    else *p = v;
+}
+template <bool COH>
+__device__ __forceinline__ void wr4(float4* p, float4 v) {
+    if constexpr (COH) st4_agent(p, v);
+    else *p = v;
+}
+
+// One reassignment + accumulation pass over the grid's points against the
+// centre tables in sm (the paper's reassignment step and the numerators and
+// denominators of its mean step), reduced across the grid.  Returns true in
+// the one final block, with the grid's integer sums | counts in sm.sacc[0]
+// and the objective of this pass in sm.sJ.
+template <int D, bool VEC, int KT>
+__device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm, int K, int G, int ntri,
+                            float4 bnd, float ninf) {
+    constexpr int R = D + 1;  // per cluster: D sums, 1 count
     const int tid = threadIdx.x, w = tid >> 6;
-    const int K = st->K;
-    const int G = st->G;
     const int64_t N = st->N, ld = st->ld;
     const float* __restrict__ X = st->X;
-    const float4 bnd = st->bnd;
-    const float ninf = st->minus_inf;
-
-    const int ntri = stage_centres(st, K, scand, smu);
-    for (int i = tid; i < NW * KMAX * R; i += BLOCK) (&sacc[0][0])[i] = 0ull;
+    for (int i = tid; i < NW * KMAX * (DMAX + 1); i += BLOCK) (&sm.sacc[0][0])[i] = 0ull;
     __syncthreads();
 
     double jl = 0.0;
-    unsigned long long* myacc = sacc[w];
-    scan_points<D, VEC, KT>(X, ld, N, scand, smu, K, ntri, bnd, ninf, squeue[w],
+    unsigned long long* myacc = sm.sacc[w];
+    scan_points<D, VEC, KT>(X, ld, N, sm.scand, sm.smu, K, ntri, bnd, ninf, sm.squeue[w],
                             [&](int64_t, float x0, float x1, float x2, int k, float dist) {
         unsigned long long* a = &myacc[k * R];
         const float xs[3] = {x0, x1, x2};
@@ -238,22 +314,32 @@ __global__ __launch_bounds__(BLOCK) void lloyd_iter(State* __restrict__ st) {
         jl += (double)dist;
     });
     jl = wave_sum(jl);
-    if ((tid & 63) == 0) sred[w] = jl;
+    if ((tid & 63) == 0) sm.sred[w] = jl;
     __syncthreads();
     for (int i = tid; i < K * R; i += BLOCK) {
         unsigned long long s = 0ull;
 #pragma unroll
-        for (int v = 0; v < NW; ++v) s += sacc[v][i];
-        stot[i] = s;
+        for (int v = 0; v < NW; ++v) s += sm.sacc[v][i];
+        sm.stot[i] = s;
     }
     double jb = 0.0;
 #pragma unroll
-    for (int v = 0; v < NW; ++v) jb += sred[v];
+    for (int v = 0; v < NW; ++v) jb += sm.sred[v];
     __syncthreads();
-    if (!reduce_grid(st, stot, K * R, jb, &sacc[0][0], &sJ, &sflag)) return;
+    return reduce_grid(st, sm.stot, K * R, jb, &sm.sacc[0][0], &sm.sJ, &sm.sflag);
+}
 
-    // ---- final block: the update of the paper's mean-calculation step ----
-    const unsigned long long* tot = &sacc[0][0];
+// The final block's update (the paper's mean-calculation step, its error E
+// and tolerance test): new float64 centres (an empty cluster keeps its
+// centre), E, the history, t and done; and the next pass's centre tables,
+// left in sm (smu, scand, sbnd, sdone) and stored to the state.  COH: the
+// state is also read by other blocks of a persistent kernel, so every access
+// to it is device-coherent.
+template <int D, bool COH>
+__device__ __forceinline__ void finalize_update(State* __restrict__ st, IterSmem& sm, int K, int G) {
+    constexpr int R = D + 1;
+    const int tid = threadIdx.x;
+    const unsigned long long* tot = &sm.sacc[0][0];
     if (tid < K) {
         const int k = tid;
         const unsigned long long cnt = tot[k * R + D];
@@ -262,31 +348,112 @@ __global__ __launch_bounds__(BLOCK) void lloyd_iter(State* __restrict__ st) {
 #pragma unroll
         for (int j = 0; j < D; ++j) {
             const long long s = (long long)tot[k * R + j];
-            const double old = st->mu64[k * D + j];
+            const double old = rd<COH>(&st->mu64[k * D + j]);
             const double v = cnt ? ldexp((double)s, -G) / (double)cnt : old;
             const double sh = v - old;
             e = fma(sh, sh, e);
-            st->mu64[k * D + j] = v;
+            wr<COH>(&st->mu64[k * D + j], v);
             m32[j] = (float)v;
         }
         const float4 m = make_float4(m32[0], m32[1], m32[2], 0.0f);
-        st->mu32[k] = m;
-        smu[k] = m;
-        sE[k] = e;
-        sEmpty[k] = cnt == 0ull;
+        wr4<COH>(&st->mu32[k], m);
+        sm.smu[k] = m;
+        sm.sE[k] = e;
+        sm.sEmpty[k] = cnt == 0ull;
     }
     __syncthreads();
-    prep_centres(smu, K, st->cand, &st->bnd, sc, sa);
+    prep_centres(sm.smu, K, sm.scand, &sm.sbnd, sm.sc, sm.sa);
+    const int ntri = (K + 2) / 3;
+    for (int i = tid; i < 3 * ntri; i += BLOCK) wr4<COH>(&st->cand[i], sm.scand[i]);
     if (tid == 0) {
+        wr4<COH>(&st->bnd, sm.sbnd);
         double E = 0.0;
         int emp = 0;
-        for (int k = 0; k < K; ++k) { E += sE[k]; emp += sEmpty[k]; }
-        const int t = st->t;
-        if (t < st->hist_cap) { st->E_hist[t] = E; st->J_hist[t] = sJ; }
-        st->t = t + 1;
-        st->E = E;
-        st->empty_events += emp;
-        st->done = (E < st->tol || t + 1 >= st->max_iter) ? 1 : 0;
+        for (int k = 0; k < K; ++k) { E += sm.sE[k]; emp += sm.sEmpty[k]; }
+        const int t = rd<COH>(&st->t);
+        if (t < st->hist_cap) { st->E_hist[t] = E; st->J_hist[t] = sm.sJ; }
+        const int done = (E < st->tol || t + 1 >= st->max_iter) ? 1 : 0;
+        wr<COH>(&st->t, t + 1);
+        wr<COH>(&st->E, E);
+        wr<COH>(&st->empty_events, rd<COH>(&st->empty_events) + emp);
+        wr<COH>(&st->done, done);
+        sm.sdone = done;
+    }
+    __syncthreads();
+}
+
+// One update per launch (replayed from a graph): the update's pass, then the
+// final block's update of the centres.
+template <int D, bool VEC, int KT>
+__global__ __launch_bounds__(BLOCK) void lloyd_iter(State* __restrict__ st) {
+    if (st->done) return;
+    __shared__ IterSmem sm;
+    const int K = st->K;
+    const int ntri = stage_centres(st, K, sm.scand, sm.smu);
+    __syncthreads();
+    if (!update_pass<D, VEC, KT>(st, sm, K, st->G, ntri, st->bnd, st->minus_inf)) return;
+    finalize_update<D, false>(st, sm, K, st->G);
+}
+
+// The whole fit in one cooperative launch (every block resident), for small
+// N where a launch per update would cost more than the update.  Each update:
+// the same pass and final-block update as lloyd_iter; the final block then
+// publishes the round number, and every other block waits for it and
+// reloads the new centre tables (device-coherent loads) before the next
+// pass.  The wait is bounded: a block that polls for about a second records
+// FLAG_TIMEOUT and returns, as do the others once they see it, so no wave
+// spins forever.
+constexpr uint32_t PERSIST_SPIN_LIMIT = 1u << 21;
+
+template <int D, bool VEC, int KT>
+__global__ __launch_bounds__(BLOCK) void lloyd_persist(State* __restrict__ st) {
+    if (st->done) return;
+    __shared__ IterSmem sm;
+    const int tid = threadIdx.x;
+    const int K = st->K;
+    const int G = st->G;
+    const float ninf = st->minus_inf;
+    const int ntri = stage_centres(st, K, sm.scand, sm.smu);
+    float4 bnd = st->bnd;
+    __syncthreads();
+    for (uint32_t round = 1;; ++round) {
+        if (update_pass<D, VEC, KT>(st, sm, K, G, ntri, bnd, ninf)) {
+            finalize_update<D, true>(st, sm, K, G);
+            wait_mem();
+            __syncthreads();
+            if (tid == 0) st_agent(&st->gen, round);
+        } else {
+            if (tid == 0) {
+                int ok = 1;
+                uint32_t spins = 0;
+                while (ld_agent(&st->gen) < round) {
+                    __builtin_amdgcn_s_sleep(4);
+                    ++spins;
+                    if ((spins & 255u) == 0 && (ld_agent(&st->flags) & FLAG_TIMEOUT)) {
+                        ok = 0;
+                        break;
+                    }
+                    if (spins > PERSIST_SPIN_LIMIT) {
+                        __hip_atomic_fetch_or(&st->flags, (int32_t)FLAG_TIMEOUT, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                        ok = 0;
+                        break;
+                    }
+                }
+                sm.sflag = ok;
+            }
+            __syncthreads();
+            if (!sm.sflag) return;
+            for (int i = tid; i < 3 * ntri; i += BLOCK) sm.scand[i] = ld4_agent(&st->cand[i]);
+            for (int k = tid; k < K; k += BLOCK) sm.smu[k] = ld4_agent(&st->mu32[k]);
+            if (tid == 0) {
+                sm.sbnd = ld4_agent(&st->bnd);
+                sm.sdone = ld_agent(&st->done);
+            }
+        }
+        __syncthreads();
+        if (sm.sdone) break;
+        bnd = sm.sbnd;
     }
 }
 
@@ -376,6 +543,28 @@ hipError_t launch_iter(State* st, int d, bool vec, int keys, int grid, hipStream
     if (grid < 1 || grid > MAX_BLOCKS) return hipErrorInvalidValue;
     KM_DISPATCH_SCAN(lloyd_iter, grid, s, st);
     return hipGetLastError();
+}
+
+hipError_t launch_persist(State* st, int d, bool vec, int grid, hipStream_t s) {
+    if (grid < 1 || grid > MAX_BLOCKS) return hipErrorInvalidValue;
+    void* args[] = {&st};
+    const void* f = nullptr;
+    if (d == 2 && vec) f = reinterpret_cast<const void*>(lloyd_persist<2, true, 0>);
+    else if (d == 2) f = reinterpret_cast<const void*>(lloyd_persist<2, false, 0>);
+    else if (d == 3 && vec) f = reinterpret_cast<const void*>(lloyd_persist<3, true, 0>);
+    else if (d == 3) f = reinterpret_cast<const void*>(lloyd_persist<3, false, 0>);
+    else return hipErrorInvalidValue;
+    return hipLaunchCooperativeKernel(f, dim3(grid), dim3(BLOCK), args, 0, s);
+}
+
+int persist_max_blocks_per_cu(int d, bool vec) {
+    const void* f = d == 2 ? (vec ? reinterpret_cast<const void*>(lloyd_persist<2, true, 0>)
+                                  : reinterpret_cast<const void*>(lloyd_persist<2, false, 0>))
+                           : (vec ? reinterpret_cast<const void*>(lloyd_persist<3, true, 0>)
+                                  : reinterpret_cast<const void*>(lloyd_persist<3, false, 0>));
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, BLOCK, 0) != hipSuccess) return 0;
+    return n;
 }
 
 hipError_t launch_label(State* st, int32_t* labels, int d, bool vec, int keys, int grid,

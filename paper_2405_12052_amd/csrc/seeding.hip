@@ -142,8 +142,9 @@ __device__ __forceinline__ unsigned long long wave_incl_scan(unsigned long long 
 
 // In one wave: among n consecutive terms term(0..n), find the first index
 // whose inclusive prefix sum exceeds R (0 <= R < the total).  Each lane owns a
-// consecutive run of ceil(n/64) terms; the lane whose run holds the crossing
-// walks it.  Returns the index in every lane.
+// consecutive run of ceil(n/64) terms, read 8 at a time so that the loads of
+// a run overlap; the lane whose run holds the crossing walks it.  Returns the
+// index in every lane.
 template <typename F>
 __device__ int64_t wave_find(int64_t n, unsigned long long R, F term) {
     const int lane = threadIdx.x & 63;
@@ -151,16 +152,30 @@ __device__ int64_t wave_find(int64_t n, unsigned long long R, F term) {
     const int64_t b = (int64_t)lane * q;
     const int64_t e = b + q < n ? b + q : n;
     unsigned long long tot = 0;
-    for (int64_t i = b; i < e; ++i) tot += term(i);
+    for (int64_t i0 = b; i0 < e; i0 += 8) {
+        unsigned long long t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = i0 + u < e ? term(i0 + u) : 0ull;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) tot += t[u];
+    }
     const unsigned long long incl = wave_incl_scan(tot);
     const unsigned long long hit = __ballot(incl > R);
     const int owner = hit ? __builtin_ctzll(hit) : 63;
     int64_t found = -1;
     if (lane == owner) {
         unsigned long long p = incl - tot;
-        for (int64_t i = b; i < e; ++i) {
-            p += term(i);
-            if (p > R) { found = i; break; }
+        for (int64_t i0 = b; i0 < e && found < 0; i0 += 8) {
+            unsigned long long t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t[u] = i0 + u < e ? term(i0 + u) : 0ull;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (found < 0 && i0 + u < e) {
+                    p += t[u];
+                    if (p > R) found = i0 + u;
+                }
+            }
         }
         if (found < 0) found = n - 1;   // unreachable with R < total
     }
@@ -177,6 +192,7 @@ __global__ __launch_bounds__(PB) void pp_select(PPArgs a, int j) {
     if (mb < 0x7f800000u)
         for (int64_t i = lo + threadIdx.x; i < hi; i += PB) s += weight(a.d2[i], G);
     __shared__ unsigned long long ws[PB / 64];
+    __shared__ unsigned long long sb[PP_MAX_BLOCKS];
     __shared__ bool last;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
@@ -195,7 +211,7 @@ __global__ __launch_bounds__(PB) void pp_select(PPArgs a, int j) {
         last = old == (uint32_t)(gridDim.x - 1);
     }
     __syncthreads();
-    if (!last || threadIdx.x >= 64) return;
+    if (!last) return;
     if (mb >= 0x7f800000u) {               // NaN or infinity among the D^2
         if (threadIdx.x == 0) {
             *a.flag = 1;
@@ -203,13 +219,27 @@ __global__ __launch_bounds__(PB) void pp_select(PPArgs a, int j) {
         }
         return;
     }
-    const unsigned long long* bsum = a.bsum;
+    // the block sums into LDS, all loads of a thread in flight together
+    {
+        unsigned long long v[PP_MAX_BLOCKS / PB];
+#pragma unroll
+        for (int u = 0; u < PP_MAX_BLOCKS / PB; ++u) {
+            const int b = threadIdx.x + u * PB;
+            v[u] = b < a.nb ? __hip_atomic_load(&a.bsum[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                            : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < PP_MAX_BLOCKS / PB; ++u) {
+            const int b = threadIdx.x + u * PB;
+            if (b < a.nb) sb[b] = v[u];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x >= 64) return;
     unsigned long long S = 0;
     {
-        const int lane = threadIdx.x;
         unsigned long long t = 0;
-        for (int b = lane; b < a.nb; b += 64)
-            t += __hip_atomic_load(&bsum[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int b = threadIdx.x; b < a.nb; b += 64) t += sb[b];
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) t += __shfl_xor(t, o, 64);
         S = t;
@@ -224,11 +254,8 @@ __global__ __launch_bounds__(PB) void pp_select(PPArgs a, int j) {
         unsigned long long R = f < (double)S ? (unsigned long long)f : S - 1;
         if (R > S - 1) R = S - 1;
         unsigned long long before = 0;
-        const int64_t blk = wave_find(a.nb, R, [&](int64_t b) {
-            return __hip_atomic_load(&bsum[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        });
-        for (int64_t b = threadIdx.x; b < blk; b += 64)
-            before += __hip_atomic_load(&bsum[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int64_t blk = wave_find(a.nb, R, [&](int64_t b) { return sb[b]; });
+        for (int64_t b = threadIdx.x; b < blk; b += 64) before += sb[b];
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) before += __shfl_xor(before, o, 64);
         const int64_t b0 = blk * a.chunk;

@@ -283,3 +283,40 @@ def test_timing_counts_iteration_kernels(km):
     km.set_option(KM_OPT_TIMING, 0)
     assert n == 20 and ms > 0
     log(f"C5-size iteration: {ms / n * 1e3:.1f} us/iter, {s.N * n / ms * 1e3:.3e} pt-it/s")
+
+
+# ------------------------------------------------------- persistent fit
+@pytest.mark.parametrize("name,kw", [("C1", {}), ("C5", {"N": 400_001}), ("C2", {"N": 77, "K": 9}),
+                                     ("C3", {"N": 300_007}), ("C2", {"N": 1, "K": 1})])
+def test_persistent_fit_equals_per_update_launches(km, name, kw):
+    """The one-launch persistent fit and the graph-replayed launch per update
+    give bit-identical centres, labels, E, T, history and objective."""
+    from paper_2405_12052_amd import KM_OPT_PERSIST
+    log(f"persist {name} {kw}")
+    s, X, Xd = data(name, **kw)
+    mu0 = datagen.init_sample(X, s.N, s.K, s.init_seed)
+    out = []
+    for mode in (1, 2):
+        km.set_option(KM_OPT_PERSIST, mode)
+        r = km.fit(Xd, mu0, tol=1e-6, max_iter=60)
+        out.append((r, km.history()))
+    km.set_option(KM_OPT_PERSIST, 0)
+    (a, ha), (b, hb) = out
+    assert a.iters == b.iters
+    assert np.array_equal(a.centroids, b.centroids)
+    assert a.E == b.E and a.objective == b.objective
+    assert np.array_equal(a.labels.cpu().numpy(), b.labels.cpu().numpy())
+    assert np.array_equal(ha[0], hb[0]) and np.array_equal(ha[1], hb[1])
+
+
+def test_persistent_fit_timing_counts_updates(km):
+    from paper_2405_12052_amd import KM_OPT_PERSIST, KM_OPT_TIMING
+    s, X, Xd = data("C5", N=200_000)
+    mu0 = datagen.init_sample(X, s.N, s.K, s.init_seed)
+    km.set_option(KM_OPT_PERSIST, 2)
+    km.set_option(KM_OPT_TIMING, 1)
+    r = km.fit(Xd, mu0, tol=0.0, max_iter=25, labels=False)
+    ms, n = km.timing()
+    km.set_option(KM_OPT_TIMING, 0)
+    km.set_option(KM_OPT_PERSIST, 0)
+    assert r.iters == 25 and n == 25 and ms > 0
