@@ -175,7 +175,7 @@ def time_to_converge(km, X, Xd, N, K, seed, method, weights=None, repeats=3):
             mu0 = km.pp_init(Xd, K, seed=seed)
         elif method == "learned":
             rng = np.random.Generator(np.random.PCG64(seed))
-            idx = torch.from_numpy(rng.choice(N, size=4096, replace=False).astype(np.int32)).to(
+            idx = torch.from_numpy(rng.integers(0, N, size=4096).astype(np.int32)).to(
                 Xd.device, non_blocking=True)
             try:
                 mu0 = km.init_learned(Xd, K, weights, idx=idx)

@@ -285,10 +285,14 @@ int kmeans_initnet_train_step(kmeans_ctx *ctx, const float *pts, const float *ta
                               float *adam_v, float lr, int32_t step, double *loss_out);
 
 /* Initial centres of one 3-D instance (X as in kmeans_fit, d = 3) from the P
- * sample points idx[0..P) (device int32 indices into [0, N)): gather,
- * normalise, forward pass, de-normalise, into centroids_out (host, K*3
- * float64).  Returns KM_EINVAL if the network yields a non-finite centre
- * (callers then fall back to a seeded sample of data points). */
+ * sample points idx[0..P) (device int32 indices into [0, N); P a multiple of
+ * 32 in [32, 4096]): gather, normalise, forward pass, de-normalise, into
+ * centroids_out (host, K*3 float64).  The per-point layers run as up to 16
+ * equal slices of the sample in parallel, pooled together (mean of the slice
+ * means, max of the slice maxima), so the result equals kmeans_initnet_forward
+ * on the normalised sample up to float32 summation order.  Returns KM_EINVAL
+ * if the network yields a non-finite centre (callers then fall back to a
+ * seeded sample of data points). */
 int kmeans_init_learned(kmeans_ctx *ctx, const float *X, int64_t N, int64_t ld, int32_t K,
                         const int32_t *idx, int32_t P, const float *params,
                         double *centroids_out);

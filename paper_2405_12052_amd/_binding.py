@@ -304,15 +304,14 @@ class KMeans:
 
     def init_learned(self, X, K, params, N=None, P=4096, seed=0, idx=None):
         """K x 3 initial centres proposed by the network from a seeded sample
-        of P points of X (float64, host).  Raises KMeansError if the network
-        yields a non-finite centre."""
+        of P points of X (drawn with replacement; float64, host).  Raises
+        KMeansError if the network yields a non-finite centre."""
         ptr, n, ld, d = self._points(X, N)
         if d != 3:
             raise ValueError("the learned initialiser takes 3-D points")
         if idx is None:
             rng = np.random.Generator(np.random.PCG64(seed))
-            idx = self._torch.from_numpy(
-                rng.choice(n, size=min(P, n), replace=False).astype(np.int32)).to(X.device)
+            idx = self._torch.from_numpy(rng.integers(0, n, size=P).astype(np.int32)).to(X.device)
         out = np.empty((K, 3), np.float64)
         self._check(self._lib.kmeans_init_learned(self._ctx, ptr, n, ld, K, idx.data_ptr(),
                                                   idx.numel(), params.data_ptr(), _dptr(out)))

@@ -58,6 +58,11 @@ hipError_t launch_reduce(int B, int K, const float* part, const HeadOut& ho, flo
                          float* params, float* m, float* v, const AdamArgs& adam, hipStream_t s);
 hipError_t launch_gather(const float* X, int64_t ld, int64_t N, const int32_t* idx, int P,
                          float* pts, double* stats, hipStream_t s);
+// Inference of one instance pooled as S equal slices (launch_points_fwd with
+// B = S): head over the combined pool into pred [3K]; z: scratch of NZ floats.
+hipError_t launch_infer_head(const float* part, int S, int K, const float* params, float* z,
+                             float* pred, hipStream_t s);
+constexpr int GATHER_MAX = 4096;   // largest sample launch_gather takes
 
 }  // namespace net
 }  // namespace km

@@ -243,6 +243,7 @@ int kmeans_init_learned(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, in
     if (!c) return KM_EINVAL;
     c->err.clear();
     int rc = check_shape(c, 1, P, K);
+    if (!rc && P > net::GATHER_MAX) rc = fail(c, KM_EINVAL, "P=%d > %d", P, net::GATHER_MAX);
     if (!rc && (N < 1 || ld < N)) rc = fail(c, KM_EINVAL, "N=%lld, ld=%lld", (long long)N, (long long)ld);
     if (!rc && !centroids_out) rc = fail(c, KM_EINVAL, "centroids_out is NULL");
     if (!rc) rc = check_dev(c, X, "X");
@@ -250,12 +251,17 @@ int kmeans_init_learned(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, in
     if (!rc) rc = check_dev(c, params, "params");
     if (rc) return rc;
     KM_HIP(c, hipSetDevice(c->device));
-    rc = ensure_net(c, 1, P);
+    // the sample's per-point layers run as S equal slices in parallel blocks
+    // (S the largest of 16, 8, 4, 2, 1 with P/S a multiple of 32), pooled
+    // together by the inference head
+    int S = 16;
+    while (S > 1 && P % (32 * S)) S /= 2;
+    rc = ensure_net(c, S, P);
     if (rc) return rc;
     km::NetWS* w = c->nws;
     KM_HIP(c, net::launch_gather(X, ld, N, idx, P, w->gpts, w->stats, c->stream));
-    rc = run_net(c, w->gpts, nullptr, 1, P, K, params, w->pred);
-    if (rc) return rc;
+    KM_HIP(c, net::launch_points_fwd(w->gpts, S, P / S, params, w->pool, nullptr, c->stream));
+    KM_HIP(c, net::launch_infer_head(w->pool, S, K, params, w->zbf, w->pred, c->stream));
     KM_HIP(c, hipMemcpyAsync(w->pred_h, w->pred, sizeof(float) * 3 * K, hipMemcpyDeviceToHost, c->stream));
     KM_HIP(c, hipMemcpyAsync(w->stats_h, w->stats, sizeof(double) * 4, hipMemcpyDeviceToHost, c->stream));
     KM_HIP(c, hipStreamSynchronize(c->stream));

@@ -493,60 +493,141 @@ __global__ __launch_bounds__(256) void net_reduce(int B, int K, const float* __r
 
 // ------------------------------------------------------------ net_gather
 // One block: gathers the P sample points idx[0..P) of X (d = 3 rows, stride
-// ld), normalises them by their mean and scalar standard deviation (float64
-// sums in a fixed order) and writes pts [P][3] and stats {mean0..2, s}.
+// ld), normalises them by their mean and scalar standard deviation and writes
+// pts [P][3] and stats {mean0..2, s}.  Each thread keeps its points in
+// registers (up to GATHER_PER points, all loads in flight together); float64
+// sums per thread, then across each wave by a fixed butterfly and across
+// the waves in order, so the result repeats bit for bit.
+constexpr int GATHER_PER = GATHER_MAX / NT;
+static_assert(GATHER_PER * NT == GATHER_MAX, "the sample must split evenly over the block");
+
+__device__ __forceinline__ double block_sum_fixed(double v, double* sw) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) t += sw[w];
+    return t;
+}
+
 __global__ __launch_bounds__(NT) void net_gather(const float* __restrict__ X, int64_t ld,
                                                  int64_t N, const int32_t* __restrict__ idx,
                                                  int P, float* __restrict__ pts,
                                                  double* __restrict__ stats) {
-    __shared__ double sred[NT];
-    __shared__ double smean[3];
+    __shared__ double sw[NW];
     const int tid = threadIdx.x;
+    float v[GATHER_PER][3];
+#pragma unroll
+    for (int u = 0; u < GATHER_PER; ++u) {
+        const int i = tid + u * NT;
+        int64_t k = i < P ? idx[i] : 0;
+        k = k < 0 ? 0 : (k >= N ? N - 1 : k);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) v[u][q] = i < P ? X[q * ld + k] : 0.0f;
+    }
+    double mean[3];
+#pragma unroll
     for (int q = 0; q < 3; ++q) {
         double s = 0.0;
-        for (int i = tid; i < P; i += NT) {
-            int64_t k = idx[i];
-            k = k < 0 ? 0 : (k >= N ? N - 1 : k);
-            s += (double)X[q * ld + k];
-        }
-        sred[tid] = s;
-        __syncthreads();
-        if (tid == 0) {
-            double t = 0.0;
-            for (int i = 0; i < NT; ++i) t += sred[i];
-            smean[q] = t / (double)P;
-        }
-        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < GATHER_PER; ++u) s += (double)v[u][q];
+        mean[q] = block_sum_fixed(s, sw) / (double)P;
     }
     double s2 = 0.0;
-    for (int i = tid; i < P; i += NT) {
-        int64_t k = idx[i];
-        k = k < 0 ? 0 : (k >= N ? N - 1 : k);
-        for (int q = 0; q < 3; ++q) {
-            const double dv = (double)X[q * ld + k] - smean[q];
-            s2 += dv * dv;
-        }
-    }
-    sred[tid] = s2;
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < GATHER_PER; ++u)
+        if (tid + u * NT < P)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const double dv = (double)v[u][q] - mean[q];
+                s2 += dv * dv;
+            }
+    double sd = sqrt(block_sum_fixed(s2, sw) / (3.0 * (double)P));
+    if (!(sd > 0.0)) sd = 1.0;
     if (tid == 0) {
-        double t = 0.0;
-        for (int i = 0; i < NT; ++i) t += sred[i];
-        double sd = sqrt(t / (3.0 * (double)P));
-        if (!(sd > 0.0)) sd = 1.0;
-        sred[0] = sd;
-        stats[0] = smean[0];
-        stats[1] = smean[1];
-        stats[2] = smean[2];
+        stats[0] = mean[0];
+        stats[1] = mean[1];
+        stats[2] = mean[2];
         stats[3] = sd;
     }
+#pragma unroll
+    for (int u = 0; u < GATHER_PER; ++u) {
+        const int i = tid + u * NT;
+        if (i < P)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) pts[(size_t)i * 3 + q] = (float)(((double)v[u][q] - mean[q]) / sd);
+    }
+}
+
+// ------------------------------------------------------------ inference head
+// Inference of one instance whose P points were pooled as S equal slices
+// (net_points_fwd with B = S): pool = [mean of the slice means, max of the
+// slice maxima].  net_infer_z: block b computes z[j] for the 16 outputs
+// j in [16 b, 16 b + 16), 16 threads per output each summing 8 of the 128
+// inputs (all 8 weight loads in flight), combined by a fixed butterfly.
+// net_infer_y: one block, y = z W4 + b4, the outputs' inputs split the same
+// way.  Operands rounded to bfloat16 as in net_head.
+__global__ __launch_bounds__(NT) void net_infer_z(const float* __restrict__ part, int S,
+                                                  const float* __restrict__ params,
+                                                  float* __restrict__ z) {
+    __shared__ float sp[2 * NH];
+    const int tid = threadIdx.x;
+    if (tid < 2 * NH) {
+        float a;
+        if (tid < NH) {
+            a = 0.0f;
+            for (int s = 0; s < S; ++s) a += part[(size_t)s * 2 * NH + tid];
+            a /= (float)S;
+        } else {
+            a = -INFINITY;
+            for (int s = 0; s < S; ++s) a = fmaxf(a, part[(size_t)s * 2 * NH + tid]);
+        }
+        sp[tid] = bfr(a);
+    }
     __syncthreads();
-    const double sd = sred[0];
-    for (int i = tid; i < P; i += NT) {
-        int64_t k = idx[i];
-        k = k < 0 ? 0 : (k >= N ? N - 1 : k);
-        for (int q = 0; q < 3; ++q)
-            pts[(size_t)i * 3 + q] = (float)(((double)X[q * ld + k] - smean[q]) / sd);
+    const int j = blockIdx.x * 16 + (tid >> 4), l = tid & 15;
+    const float* W3 = params + OFF_W3;
+    float w[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) w[u] = W3[(size_t)(8 * l + u) * NZ + j];
+    float acc = 0.0f;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = fmaf(sp[8 * l + u], bfr(w[u]), acc);
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 16);
+    if (l == 0) z[j] = bfr(fmaxf(acc + params[OFF_B3 + j], 0.0f));
+}
+
+__global__ __launch_bounds__(NT) void net_infer_y(const float* __restrict__ z, int K,
+                                                  const float* __restrict__ params,
+                                                  float* __restrict__ pred) {
+    __shared__ float sz[NZ];
+    __shared__ float sacc[NT];
+    const int tid = threadIdx.x;
+    const int O = 3 * K;
+    sz[tid] = z[tid];                        // NT == NZ
+    __syncthreads();
+    // 4 threads per output (O <= 48 <= 64), 64 inputs each
+    const int o = tid >> 2, l = tid & 3;
+    const float* W4 = params + OFF_W4;
+    float acc = 0.0f;
+    if (o < O) {
+        for (int j0 = 64 * l; j0 < 64 * l + 64; j0 += 16) {
+            float w[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) w[u] = W4[(size_t)(j0 + u) * O + o];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc = fmaf(sz[j0 + u], bfr(w[u]), acc);
+        }
+    }
+    sacc[tid] = acc;
+    __syncthreads();
+    if (tid < O) {
+        const float* a = &sacc[4 * tid];
+        pred[tid] = ((a[0] + a[1]) + (a[2] + a[3])) + params[off_b4(K) + tid];
     }
 }
 
@@ -577,6 +658,13 @@ hipError_t launch_reduce(int B, int K, const float* part, const HeadOut& ho, flo
     const int n = param_count(K);
     hipLaunchKernelGGL(net_reduce, dim3((n + 255) / 256), dim3(256), 0, s, B, K, part, ho, grad,
                        params, m, v, adam);
+    return hipGetLastError();
+}
+
+hipError_t launch_infer_head(const float* part, int S, int K, const float* params, float* z,
+                             float* pred, hipStream_t s) {
+    hipLaunchKernelGGL(net_infer_z, dim3(NZ / 16), dim3(NT), 0, s, part, S, params, z);
+    hipLaunchKernelGGL(net_infer_y, dim3(1), dim3(NT), 0, s, z, K, params, pred);
     return hipGetLastError();
 }
 
