@@ -456,14 +456,17 @@ int kmeans_tune_batched(kmeans_ctx* c, int32_t n_inst, km_instance* inst, double
         return KM_OK;
     }
     // candidates: no teams, or teams of 4/8/16 blocks for the top 5/15/30 % of
-    // the instances by work; one or two resident blocks per compute unit
+    // the instances by work; one to four resident blocks per compute unit (as
+    // many as fit)
     std::vector<double> work(n_inst);
     for (int i = 0; i < n_inst; ++i)
         work[i] = (double)inst[i].N * inst[i].K * inst[i].n_restarts;
     std::sort(work.begin(), work.end());
     auto q = [&](double f) { return work[(size_t)(f * (double)(n_inst - 1))]; };
+    const int occ = km::batched_max_blocks_per_cu();
     std::vector<km_schedule> cand;
-    for (int bpc : {1, 2}) {
+    for (int bpc : {1, 2, 3, 4}) {
+        if (bpc > occ && bpc > 1) break;
         cand.push_back({1, bpc, 0.0});
         for (int S : {4, 8, 16})
             for (double f : {0.70, 0.85, 0.95}) cand.push_back({S, bpc, std::max(1.0, q(f))});
