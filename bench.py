@@ -351,6 +351,14 @@ def main():
             "alg_flops_per_launch": flops,
             "alg_bytes_per_launch": alg_bytes_per_point(s.d) * s.N,
             "hbm_gbs_alg": alg_bytes_per_point(s.d) * s.N / avg_kernel_s / 1e9}
+    # measured issue rates of the scan's instructions and the HBM read rate
+    peaks = km.measure_peaks()
+    roof["frac_of_measured_nonpacked_fma_peak"] = achieved / (2.0 * peaks["fma_lane_ops_per_s"] / 1e12)
+    measured = {"fp32_fma_nonpacked_tflops": 2.0 * peaks["fma_lane_ops_per_s"] / 1e12,
+                "v_min3_tops": peaks["min3_lane_ops_per_s"] / 1e12,
+                "v_med3_tops": peaks["med3_lane_ops_per_s"] / 1e12,
+                "hbm_read_gbs": peaks["hbm_read_bytes_per_s"] / 1e9}
+    log(f"measured peaks: {measured}")
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
@@ -368,6 +376,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "measured_peaks": measured,
     }
     print(json.dumps(out), flush=True)
     km.close()

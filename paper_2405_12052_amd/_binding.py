@@ -94,6 +94,7 @@ def load_library():
                                           vp, f64p]),
         "kmeans_pp_init": (C.c_int, [vp, f32p, C.c_int64, C.c_int64, C.c_int32, C.c_int32, f64p,
                                      f64p, C.POINTER(C.c_int64)]),
+        "kmeans_measure_peaks": (C.c_int, [vp, f64p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -332,6 +333,14 @@ class KMeans:
         self._check(self._lib.kmeans_pp_init(self._ctx, ptr, n, ld, d, K, _dptr(u), _dptr(out),
                                              idx.ctypes.data_as(C.POINTER(C.c_int64))))
         return (out, idx) if return_index else out
+
+    def measure_peaks(self):
+        """Measured rates on this device: non-packed FP32 FMA, v_min3 and
+        v_med3 in lane-operations/s, and the HBM read rate in bytes/s."""
+        r = np.zeros(4, np.float64)
+        self._check(self._lib.kmeans_measure_peaks(self._ctx, _dptr(r)))
+        return {"fma_lane_ops_per_s": r[0], "min3_lane_ops_per_s": r[1],
+                "med3_lane_ops_per_s": r[2], "hbm_read_bytes_per_s": r[3]}
 
     def history(self, cap: int = 1 << 20):
         E = np.empty(cap, np.float64)
