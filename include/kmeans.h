@@ -145,7 +145,10 @@ int kmeans_assign(kmeans_ctx *ctx, const float *X, int64_t N, int64_t ld,
  * Writes the final centres to centroids_out (host, K*d float64), the labels
  * against those final centres to labels_out (device, may be NULL) and the
  * outcome to *res (may be NULL).
- * tol must be finite and >= 0 (tol = 0 runs exactly max_iter updates);
+ * tol must be finite and >= 0 (tol = 0 runs exactly max_iter updates;
+ * tol = 4.9e-324, the smallest positive double, stops at the first update
+ * with E == 0: the per-cluster sums are exact, so this is the update after
+ * the indicators stopped changing -- the paper's convergence criterion);
  * max_iter >= 1.  Returns KM_EINVAL (after the run) if X holds a NaN or an
  * infinity.
  */

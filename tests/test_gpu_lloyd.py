@@ -320,3 +320,16 @@ def test_persistent_fit_timing_counts_updates(km):
     km.set_option(KM_OPT_TIMING, 0)
     km.set_option(KM_OPT_PERSIST, 0)
     assert r.iters == 25 and n == 25 and ms > 0
+
+
+def test_indicator_stability_stop_matches_oracle(km):
+    """tol = the smallest positive double: stop when an update leaves every
+    centre unchanged (E == 0), i.e. once the indicators stop changing."""
+    s, X, Xd = data("C1", N=50_000, seed=78)
+    mu0 = datagen.init_sample(X, s.N, s.K, 4)
+    r = km.fit(Xd, mu0, tol=5e-324, max_iter=1000)
+    o = oracle.fit(X, mu0, tol=5e-324, max_iter=1000)
+    assert r.converged and r.E == 0.0
+    assert r.iters == o["T"]
+    centre_check(r.centroids, o["mu"])
+    label_check(r.labels.cpu().numpy(), X, r.centroids, s.N)

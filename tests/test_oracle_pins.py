@@ -307,3 +307,23 @@ def test_scipy_kmeans2_same_iterates():
             ref, _ = kmeans2(X.T.astype(np.float64), mu0.copy(), iter=T, minit="matrix",
                              missing="raise")
             assert np.allclose(r["mu"], ref, rtol=1e-11, atol=1e-11), (seed, T)
+
+
+# ---------------------------------------- the paper's other stopping rule
+def test_smallest_positive_tol_is_the_indicator_stability_rule():
+    # The Lloyd's Algorithm section calls the method converged when no
+    # indicator changes any more.  With sums taken in a fixed order, unchanged
+    # indicators give bit-identical means, so E == 0 exactly; and E == 0 (same
+    # centres) gives unchanged indicators.  E < 5e-324 is the test E == 0.
+    s = datagen.spec("C1", N=20_000, seed=77)
+    X, _ = datagen.generate(s)
+    mu0 = datagen.init_sample(X, s.N, s.K, 3)
+    f = oracle.fit(X, mu0, tol=5e-324, max_iter=1000)
+    T = f["T"]
+    assert f["converged"] and f["E"] == 0.0 and T >= 2
+    assert f["E_hist"][T - 2] > 0.0                # it did not stop before
+    prev = oracle.fit(X, mu0, tol=0.0, max_iter=T - 1)
+    # the centres the last update started from already had stable indicators
+    assert np.array_equal(prev["labels"], f["labels"])
+    nxt = oracle.step(X, f["mu"])
+    assert nxt["E"] == 0.0 and np.array_equal(nxt["labels"], f["labels"])
