@@ -254,6 +254,89 @@ def bench_learned(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_configs(args):
+    """Time-to-converge on the small and medium workloads (N=1e5 2-D K=4;
+    N=1e7 3-D K=16; N=1e6 3-D K=16) and on the shapes of the paper's timing
+    tables (2-D N=5e5 and 3-D N=1e6 with K = 4, 8, 11; 2-D K=8 with N = 1e5,
+    2e5, 5e5; 3-D K=4 with N = 1e5 .. 1e6), on synthetic stand-ins of its
+    unpublished Gaussian-mixture datasets: GPU (kmeans_fit, points resident)
+    beside the float64 CPU oracle with 1 .. all host threads.  E < 1e-6, as the
+    paper's tolerance, or the workload's cap."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import oracle
+    from paper_2405_12052_amd import KMeans
+
+    km = KMeans(0)
+    all_threads = oracle.threads()
+    thread_counts = sorted({t for t in (1, 2, 4, 8, 16, all_threads) if t <= all_threads})
+
+    def gpu_time(Xd, mu0, max_iter):
+        times = []
+        for _ in range(4):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = km.fit(Xd, mu0, tol=1e-6, max_iter=max_iter, labels=False)
+            times.append(time.perf_counter() - t)
+        return float(np.median(times[1:])), r.iters, r.objective
+
+    def oracle_time(X, mu0, max_iter, p, updates_cap=None):
+        oracle.threads(p)
+        mi = max_iter if updates_cap is None else min(max_iter, updates_cap)
+        t = time.perf_counter()
+        f = oracle.fit(X, mu0, tol=1e-6, max_iter=mi, labels=False)
+        return time.perf_counter() - t, f["T"], f["J"]
+
+    rows = []
+    cases = [("N=1e5, d=2, K=4 (isotropic, equal weights)", datagen.spec("C1"), 100),
+             ("N=1e6, d=3, K=16 (axis-aligned, Dirichlet, 1% noise)", datagen.spec("C5"), 300),
+             ("N=1e7, d=3, K=16 (axis-aligned, Dirichlet, 1% noise)", datagen.spec("C2"), 300)]
+    for K in (4, 8, 11):
+        cases.append((f"paper Table 1 shape: N=5e5, d=2, K={K}",
+                      datagen.spec("C1", N=500_000, K=K, seed=31000 + K), 1000))
+        cases.append((f"paper Table 1 shape: N=1e6, d=3, K={K}",
+                      datagen.spec("C2", N=1_000_000, K=K, seed=32000 + K), 1000))
+    for N in (100_000, 200_000):
+        cases.append((f"paper Table 2 shape: N={N}, d=2, K=8",
+                      datagen.spec("C1", N=N, K=8, seed=33000 + N // 1000), 1000))
+    for N in (100_000, 200_000, 400_000, 800_000):
+        cases.append((f"paper Table 3 shape: N={N}, d=3, K=4",
+                      datagen.spec("C2", N=N, K=4, seed=34000 + N // 1000), 1000))
+    for name, s, max_iter in cases:
+        X, _ = datagen.generate(s)
+        Xd = torch.from_numpy(X).cuda()
+        mu0 = datagen.init_sample(X, s.N, s.K, s.init_seed)
+        g_s, g_T, g_J = gpu_time(Xd, mu0, max_iter)
+        row = {"workload": name, "N": s.N, "d": s.d, "K": s.K, "T": g_T,
+               "gpu_ms": g_s * 1e3, "gpu_point_updates_per_s": s.N * g_T / g_s, "oracle": {}}
+        big = s.N * s.K > 5e7
+        for p in thread_counts:
+            # a bounded number of updates on one thread for the largest case
+            cap = 5 if (big and p == 1) else None
+            o_s, o_T, o_J = oracle_time(X, mu0, max_iter, p, cap)
+            row["oracle"][str(p)] = {"s": o_s, "T": o_T, "point_updates_per_s": s.N * o_T / o_s}
+            if cap is None:
+                # the same run: same number of updates, same objective
+                row["oracle"][str(p)]["same_T"] = o_T == g_T
+                row["oracle"][str(p)]["J_rel_diff"] = abs(o_J - g_J) / max(abs(o_J), 1e-300)
+        rows.append(row)
+        log(f"{name}: T={g_T} GPU {g_s * 1e3:.2f} ms, oracle {all_threads} threads "
+            f"{row['oracle'][str(all_threads)]['s'] * 1e3:.1f} ms")
+        del Xd
+    oracle.threads(all_threads)
+    km.close()
+    res = {"metric": "time-to-converge (E < 1e-6), GPU vs CPU oracle", "value": rows[0]["gpu_ms"],
+           "unit": "ms", "n_gpus": 1, "steps": len(rows), "warmup": 1,
+           "ms_per_step": rows[0]["gpu_ms"], "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "configs and the shapes of the paper's timing tables",
+                      "oracle_threads": thread_counts, "parallelism": "single GPU"},
+           "rows": rows, "roofline": None, "cpu_baseline": None}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -263,9 +346,11 @@ def main():
     ap.add_argument("--N", type=int, default=None, help="override N (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=20_000_000)
-    ap.add_argument("--workload", choices=["hbm", "batched", "learned"], default="hbm",
+    ap.add_argument("--workload", choices=["hbm", "batched", "learned", "configs"], default="hbm",
                     help="hbm: the N=2e8, K=64 fit (default); batched: 4096 instances; "
-                         "learned: learned init vs seeded sample and k-means++ on N=1e6, K=16")
+                         "learned: learned init vs seeded sample and k-means++ on N=1e6, K=16; "
+                         "configs: time-to-converge on smaller workloads and the paper's table "
+                         "shapes, GPU beside the CPU oracle")
     ap.add_argument("--instances", type=int, default=None,
                     help="instances (batched: 4096, learned: 100)")
     ap.add_argument("--repeats", type=int, default=3)
@@ -302,6 +387,9 @@ def main():
     if args.workload == "learned":
         args.instances = args.instances or 100
         bench_learned(args)
+        return
+    if args.workload == "configs":
+        bench_configs(args)
         return
 
     import numpy as np
