@@ -106,22 +106,21 @@ __device__ void points_pass(const BInst& in, int rank, int S, int mask, int G, f
     float4* __restrict__ wq = sm.queue[w];
     int qn = 0;  // this wave's queue length (the same in every lane)
 
+    // add a point's fixed-point coordinates q (|q| < 2^30, see scale_exponent)
+    // and a count of one to cluster k of restart r
+    auto acc_add = [&](int r, int k, int q0, int q1, int q2) {
+        unsigned long long* a = &sm.acc[(r * K + k) * (D + 1)];
+        const int qs[3] = {q0, q1, q2};
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+            __hip_atomic_fetch_add(&a[j], (unsigned long long)(long long)qs[j], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(&a[D], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
     auto take = [&](int r, int64_t i, float x0, float x1, float x2, int k, float dist) {
         if constexpr (MODE == MODE_ACC) {
-            unsigned long long* a = &sm.acc[(r * K + k) * (D + 1)];
-            // the coordinates are the same for every restart of the point; the
-            // empty constraint keeps the compiler from hoisting their 64-bit
-            // fixed-point forms out of the restart loop (24 registers live
-            // across the whole scan)
-            asm volatile("" : "+v"(x0), "+v"(x1), "+v"(x2));
-            const float xs[3] = {x0, x1, x2};
-#pragma unroll
-            for (int j = 0; j < D; ++j) {
-                const long long q = (long long)__float2int_rn(ldexpf(xs[j], G));
-                __hip_atomic_fetch_add(&a[j], (unsigned long long)q, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
-            __hip_atomic_fetch_add(&a[D], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            acc_add(r, k, __float2int_rn(ldexpf(x0, G)), __float2int_rn(ldexpf(x1, G)),
+                    D == 3 ? __float2int_rn(ldexpf(x2, G)) : 0);
         } else if constexpr (MODE == MODE_LABEL) {
             in.labels[i] = k;
         }
@@ -156,6 +155,14 @@ __device__ void points_pass(const BInst& in, int rank, int S, int mask, int G, f
 #pragma unroll
                 for (int p = 0; p < 4; ++p) x[j][p] = 0.0f;
         }
+        // the points' fixed-point coordinates, shared by every restart
+        int qx[D][4];
+        if constexpr (MODE == MODE_ACC) {
+#pragma unroll
+            for (int j = 0; j < D; ++j)
+#pragma unroll
+                for (int p = 0; p < 4; ++p) qx[j][p] = __float2int_rn(ldexpf(x[j][p], G));
+        }
 #pragma unroll 1
         for (int r = 0; r < BK_RMAX; ++r) {
             if (!((mask >> r) & 1)) continue;
@@ -167,7 +174,12 @@ __device__ void points_pass(const BInst& in, int rank, int S, int mask, int G, f
             for (int p = 0; p < 4; ++p) {
                 const float x2 = D == 3 ? x[D - 1][p] : 0.0f;
                 const bool valid = p < n;
-                if (valid && ok[p]) take(r, g * 4 + p, x[0][p], x[1][p], x2, arg[p], best[p]);
+                if (valid && ok[p]) {
+                    if constexpr (MODE == MODE_ACC)
+                        acc_add(r, arg[p], qx[0][p], qx[1][p], D == 3 ? qx[D - 1][p] : 0);
+                    else
+                        take(r, g * 4 + p, x[0][p], x[1][p], x2, arg[p], best[p]);
+                }
                 const bool f = valid && !ok[p];
                 const uint64_t m = __ballot(f);
                 if (m) {
