@@ -83,8 +83,8 @@ def cpu_baseline(X, mu0, n_sample: int, target_s: float = 12.0):
     assert r["T"] == iters
     return {"value": n_sample * iters / el, "unit": "point-iters/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"first {n_sample} of the {X.shape[1]} points, same K=64 initial "
-                      f"centres, {iters} float64 updates + final labels, {el:.1f} s"}
+            "sample": f"first {n_sample} of the {X.shape[1]} points, same K={mu0.shape[0]} "
+                      f"initial centres, {iters} float64 updates + final labels, {el:.1f} s"}
 
 
 def bench_batched(args):
@@ -143,6 +143,80 @@ def bench_batched(args):
         "cpu_baseline": None,
     }
     print(json.dumps(res), flush=True)
+    km.close()
+
+
+def bench_wide(args):
+    """The general-shape workload W1 (beyond the paper's 2-D/3-D problem):
+    N = 1e7 points in 16 dimensions, K = 256, a Gaussian mixture with
+    per-axis spreads and Dirichlet weights, float32 SoA (640 MB); one step =
+    one kmeans_fit from a seeded sample of K points, exactly 20 updates
+    (tol = 0), then the final labels.  Each update is two kernels
+    (wide_update: reassignment and per-block sums; wide_reduce: totals and the
+    float64 mean step); their time per update comes from HIP events around
+    the graph replays on the library's stream."""
+    import torch
+
+    import datagen
+    from paper_2405_12052_amd import KM_OPT_TIMING, KMeans
+
+    s = datagen.spec("W1") if args.N is None else datagen.spec("W1", N=args.N)
+    iters = s.max_iter
+    t0 = time.time()
+    X, _ = datagen.generate(s)
+    mu0 = datagen.init_sample(X, s.N, s.K, s.init_seed)
+    log(f"generated N={s.N} d={s.d} K={s.K} in {time.time() - t0:.1f}s")
+    Xd = torch.from_numpy(X).cuda()
+    torch.cuda.synchronize()
+    km = KMeans(0)
+    km.set_option(KM_OPT_TIMING, 1)
+    for i in range(args.warmup):
+        r = km.fit(Xd, mu0, tol=0.0, max_iter=iters)
+        log(f"warmup {i}: T={r.iters} J={r.objective:.6e}")
+    torch.cuda.synchronize()
+    kern_ms, kern_n = 0.0, 0
+    t = time.perf_counter()
+    for i in range(args.steps):
+        r = km.fit(Xd, mu0, tol=0.0, max_iter=iters)
+        ms, n = km.timing()
+        kern_ms += ms
+        kern_n += n
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    assert r.iters == iters
+    per_update_s = kern_ms / kern_n / 1e3
+    log(f"timed {args.steps} fits in {el:.3f}s; {per_update_s * 1e6:.1f} us per update "
+        f"(wide_update + wide_reduce)")
+    flops = alg_flops_per_point(s.d, s.K) * s.N
+    achieved = flops / per_update_s / 1e12
+    peaks = km.measure_peaks()
+    fma_peak = 2.0 * peaks["fma_lane_ops_per_s"] / 1e12
+    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+            "kernel": f"wide_update<{s.d}> + wide_reduce (one update)",
+            "avg_update_us": per_update_s * 1e6, "alg_flops_per_update": flops,
+            "alg_bytes_per_update": alg_bytes_per_point(s.d) * s.N,
+            "frac_of_measured_nonpacked_fma_peak": achieved / fma_peak}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        cpu = cpu_baseline(X, mu0, min(200_000, s.N))
+        log(f"cpu baseline {cpu['value']:.3e} pt-it/s on {cpu['cores']} threads")
+    out = {
+        "metric": "Lloyd point-iters/s (general shape)", "value": s.N * iters * args.steps / el,
+        "unit": "point-iters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"general shape W1: N={s.N}, d={s.d}, K={s.K} Gaussian mixture "
+                               f"(per-axis spreads, Dirichlet weights), float32 SoA, "
+                               f"seeded-sample init, {iters} updates (tol=0) + final labels",
+                   "N": s.N, "d": s.d, "K": s.K, "iterations": iters,
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "measured_peaks": {"fp32_fma_nonpacked_tflops": fma_peak},
+    }
+    print(json.dumps(out), flush=True)
     km.close()
 
 
@@ -346,8 +420,10 @@ def main():
     ap.add_argument("--N", type=int, default=None, help="override N (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=20_000_000)
-    ap.add_argument("--workload", choices=["hbm", "batched", "learned", "configs"], default="hbm",
+    ap.add_argument("--workload", choices=["hbm", "batched", "learned", "configs", "wide"],
+                    default="hbm",
                     help="hbm: the N=2e8, K=64 fit (default); batched: 4096 instances; "
+                         "wide: N=1e7, d=16, K=256 (general-shape kernels); "
                          "learned: learned init vs seeded sample and k-means++ on N=1e6, K=16; "
                          "configs: time-to-converge on smaller workloads and the paper's table "
                          "shapes, GPU beside the CPU oracle")
@@ -390,6 +466,9 @@ def main():
         return
     if args.workload == "configs":
         bench_configs(args)
+        return
+    if args.workload == "wide":
+        bench_wide(args)
         return
 
     import numpy as np

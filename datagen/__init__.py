@@ -78,6 +78,11 @@ CONFIGS = {
     "C5": MixtureSpec("C5", N=1_000_000, d=3, K=16, seed=20240505, box=50.0,
                       std=(0.5, 2.0), axis_aligned=True, dirichlet=True,
                       noise_frac=0.01, init_seed=15, max_iter=300),
+    # beyond the paper's 2-D/3-D problem: 16-D points, K = 256
+    "W1": MixtureSpec("W1", N=10_000_000, d=16, K=256, seed=20240506, box=50.0,
+                      std=(0.5, 2.0), axis_aligned=True, dirichlet=True,
+                      noise_frac=0.01, chunks=16, init_seed=16, max_iter=20,
+                      tol=0.0),
 }
 
 

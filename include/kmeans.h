@@ -23,15 +23,25 @@
  *     fit from its output exact.
  *   - Labels are caller-owned DEVICE int32 arrays of N, 0-based (the paper
  *     numbers clusters 1..K).
- *   - Distances are evaluated in float32 as (x0-m0)^2 + (x1-m1)^2 [+ (x2-m2)^2]
- *     against the centres rounded to float32; ties go to the lowest index.
+ *   - Distances are evaluated in float32 in the direct form
+ *     (x0-m0)^2 + (x1-m1)^2 + ... + (x_{d-1}-m_{d-1})^2, left to right (the
+ *     first term a product, the others fused multiply-adds), against the
+ *     centres rounded to float32; ties go to the lowest index.
  *     Per-cluster sums are exact integer sums of the points on a 2^-G grid,
  *     G chosen from max|x| so that every |x|*2^G < 2^30; the divide, E and the
  *     tolerance test are float64.  Results do not depend on the launch
  *     configuration and repeat bit for bit from run to run.
  *   - An empty cluster keeps its previous centre and is counted.
- *   - Supported shapes: d in {2, 3}; 1 <= K <= 64; K <= N <= 2^31 - 1
- *     (kmeans_fit_batched: K <= 32, N <= 2^27, up to 8 restarts).
+ *   - Supported shapes: 1 <= d <= 32, 1 <= K <= 1024, K <= N <= 2^31 - 1,
+ *     where, outside d in {2, 3} with K <= 64, one block's tables must fit
+ *     in LDS: 8*K*(d+1) (rounded up to 16) + 4*K*s + 32 <= 61440 bytes, s =
+ *     the padded width (d for d <= 4; then 6, 8, 12, 16, 24 or 32) rounded
+ *     up to a multiple of 4.  (d <= 4: K <= 1024; d = 8: K <= 590;
+ *     d = 16: K <= 307; d = 32: K <= 156.)  d in {2, 3} with K <= 64 runs
+ *     the 2-D/3-D kernels, every other shape the general-shape kernels
+ *     (same definitions, same results up to the objective's summation
+ *     order).  kmeans_fit_batched: d in {2, 3}, K <= 32, N <= 2^27, up to 8
+ *     restarts.
  *   - Every call is synchronous with respect to the host: it returns after
  *     its device work on the context's stream has completed.  There is no
  *     host synchronisation between iterations of a fit.
@@ -89,13 +99,17 @@ enum km_option {
                              the vector ALUs), 1 vector ALUs, 2 matrix cores
                              (FP32 MFMA; slower on gfx950, kept selectable).
                              Labels, centres, E and T do not depend on it.     */
-    KM_OPT_PERSIST = 6    /* how kmeans_fit runs its updates: 0 (default)
+    KM_OPT_PERSIST = 6,   /* how kmeans_fit runs its updates: 0 (default)
                              automatic (one persistent cooperative launch for
                              2^22 <= N <= 2^24 with the VALU scan, else graph
                              replays of one launch per update), 1 always one
                              launch per update, 2 persistent whenever the VALU
                              scan is used and the grid fits on the device.
                              Results do not depend on it.                      */
+    KM_OPT_WIDE = 7       /* 1: run kmeans_fit and kmeans_assign on the
+                             general-shape kernels for every shape (a cross-
+                             check of the two implementations); 0 (default):
+                             only for shapes outside d in {2, 3}, K <= 64.     */
 };
 
 /*

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libkmeans_mi355x.so")
 
 KM_OK, KM_EINVAL, KM_ENODEV, KM_EHIP, KM_ENOMEM, KM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 KM_OPT_GRAPH, KM_OPT_UNROLL, KM_OPT_BLOCKS, KM_OPT_TIMING, KM_OPT_KEYS, KM_OPT_PERSIST = 1, 2, 3, 4, 5, 6
+KM_OPT_WIDE = 7
 
 
 class KMeansError(RuntimeError):

@@ -12,7 +12,8 @@ LIB = os.path.join(HERE, "libkmeans_mi355x.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["lloyd_kernels.hip", "batched_kernels.hip", "initnet_kernels.hip", "kmeans_api.hip",
-           "batched_api.hip", "initnet_api.hip", "seeding.hip", "peaks.hip"]
+           "batched_api.hip", "initnet_api.hip", "seeding.hip", "peaks.hip", "wide_kernels.hip",
+           "wide_api.hip"]
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 instructions.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

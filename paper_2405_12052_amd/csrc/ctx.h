@@ -25,6 +25,8 @@ struct NetWS;                        // workspace of the learned initialiser (in
 void net_ws_free(NetWS* w);
 struct SeedWS;                       // workspace of k-means++ seeding (seeding.hip)
 void seed_ws_free(SeedWS* w);
+struct WideWS;                       // workspace of the general-shape fit (wide_api.hip)
+void wide_ws_free(WideWS* w);
 
 }  // namespace km
 
@@ -66,6 +68,9 @@ struct kmeans_ctx {
     km::NetWS* nws = nullptr;
     // k-means++ seeding
     km::SeedWS* sws = nullptr;
+    // general-shape fit
+    km::WideWS* wws = nullptr;
+    int wide = 0;                      // KM_OPT_WIDE
 };
 
 namespace km {
@@ -73,6 +78,20 @@ namespace km {
 // return `code`.
 int fail(kmeans_ctx* c, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
 int check_device_ptr(kmeans_ctx* c, const void* p, const char* what);
+// Device history of E and J with room for cap updates (kmeans_api.hip).
+int ensure_hist(kmeans_ctx* c, int cap);
+// At least n timing events in c->ev (kmeans_api.hip).
+int ensure_events(kmeans_ctx* c, size_t n);
+// True when (d, K) takes the general-shape fit: d not in {2, 3}, K > KMAX,
+// or KM_OPT_WIDE set (kmeans_api.hip).
+bool wide_shape(const kmeans_ctx* c, int d, int K);
+// The general-shape fit and reassignment (wide_api.hip); same contract as
+// kmeans_fit / kmeans_assign after argument validation.
+int wide_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, int K,
+             const double* init, double tol, int max_iter, double* centroids_out,
+             int32_t* labels_out, km_result* res);
+int wide_assign(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, int K,
+                const double* centroids, int32_t* labels, double* objective);
 }  // namespace km
 
 #define KM_HIP(ctx, call)                                                                   \

@@ -2,6 +2,7 @@
 // validation, device workspace, the iteration loop (hipGraph replays with one
 // status read-back per batch of iterations) and result read-back.
 #include "ctx.h"
+#include "wide.h"
 
 #include <math.h>
 #include <stdarg.h>
@@ -17,6 +18,8 @@ using km::State;
 
 using km::fail;
 using km::check_device_ptr;
+using km::ensure_hist;
+using km::ensure_events;
 
 namespace {
 thread_local std::string g_create_error;
@@ -45,29 +48,7 @@ int km::check_device_ptr(kmeans_ctx* c, const void* p, const char* what) {
     return KM_OK;
 }
 
-namespace {
-
-int validate(kmeans_ctx* c, int64_t N, int64_t ld, int32_t d, int32_t K, double tol,
-             int32_t max_iter) {
-    if (N < 1 || N > 2147483647LL) return fail(c, KM_EINVAL, "N=%lld out of [1, 2^31-1]", (long long)N);
-    if (ld < N) return fail(c, KM_EINVAL, "ld=%lld < N=%lld", (long long)ld, (long long)N);
-    if (d != 2 && d != 3) return fail(c, KM_EUNSUPPORTED, "d=%d: only 2-D and 3-D points are implemented", d);
-    if (K < 1) return fail(c, KM_EINVAL, "K=%d < 1", K);
-    if (K > km::KMAX) return fail(c, KM_EUNSUPPORTED, "K=%d > %d", K, km::KMAX);
-    if (K > N) return fail(c, KM_EINVAL, "K=%d > N=%lld", K, (long long)N);
-    if (!(tol >= 0.0) || !isfinite(tol)) return fail(c, KM_EINVAL, "tol must be finite and >= 0");
-    if (max_iter < 1) return fail(c, KM_EINVAL, "max_iter=%d < 1", max_iter);
-    return KM_OK;
-}
-
-int check_centres(kmeans_ctx* c, const double* m, int K, int d, const char* what) {
-    if (!m) return fail(c, KM_EINVAL, "%s is NULL", what);
-    for (int i = 0; i < K * d; ++i)
-        if (!isfinite(m[i])) return fail(c, KM_EINVAL, "%s[%d] is not finite", what, i);
-    return KM_OK;
-}
-
-int ensure_hist(kmeans_ctx* c, int cap) {
+int km::ensure_hist(kmeans_ctx* c, int cap) {
     if (cap <= c->hist_cap) return KM_OK;
     int n = c->hist_cap ? c->hist_cap : 256;
     while (n < cap) n *= 2;
@@ -90,12 +71,44 @@ int ensure_hist(kmeans_ctx* c, int cap) {
     return KM_OK;
 }
 
-int ensure_events(kmeans_ctx* c, size_t n) {
+int km::ensure_events(kmeans_ctx* c, size_t n) {
     while (c->ev.size() < n) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return fail(c, KM_EHIP, "hipEventCreate failed");
         c->ev.push_back(e);
     }
+    return KM_OK;
+}
+
+bool km::wide_shape(const kmeans_ctx* c, int d, int K) {
+    return c->wide != 0 || (d != 2 && d != 3) || K > km::KMAX;
+}
+
+namespace {
+
+int validate(kmeans_ctx* c, int64_t N, int64_t ld, int32_t d, int32_t K, double tol,
+             int32_t max_iter) {
+    if (N < 1 || N > 2147483647LL) return fail(c, KM_EINVAL, "N=%lld out of [1, 2^31-1]", (long long)N);
+    if (ld < N) return fail(c, KM_EINVAL, "ld=%lld < N=%lld", (long long)ld, (long long)N);
+    if (d < 1) return fail(c, KM_EINVAL, "d=%d < 1", d);
+    if (d > km::WD_MAX) return fail(c, KM_EUNSUPPORTED, "d=%d > %d", d, km::WD_MAX);
+    if (K < 1) return fail(c, KM_EINVAL, "K=%d < 1", K);
+    if (K > km::WK_MAX) return fail(c, KM_EUNSUPPORTED, "K=%d > %d", K, km::WK_MAX);
+    // shapes outside the 2-D/3-D, K <= 64 kernels: the general-shape kernels
+    // keep K*(d+1) int64 sums and K float32 centres of one block in LDS
+    if (km::wide_lds_bytes(d, K) > (size_t)km::WLDS_MAX && !((d == 2 || d == 3) && K <= km::KMAX))
+        return fail(c, KM_EUNSUPPORTED, "d=%d, K=%d: K*(d+1) sums and K centres exceed one block's LDS",
+                    d, K);
+    if (K > N) return fail(c, KM_EINVAL, "K=%d > N=%lld", K, (long long)N);
+    if (!(tol >= 0.0) || !isfinite(tol)) return fail(c, KM_EINVAL, "tol must be finite and >= 0");
+    if (max_iter < 1) return fail(c, KM_EINVAL, "max_iter=%d < 1", max_iter);
+    return KM_OK;
+}
+
+int check_centres(kmeans_ctx* c, const double* m, int K, int d, const char* what) {
+    if (!m) return fail(c, KM_EINVAL, "%s is NULL", what);
+    for (int i = 0; i < K * d; ++i)
+        if (!isfinite(m[i])) return fail(c, KM_EINVAL, "%s[%d] is not finite", what, i);
     return KM_OK;
 }
 
@@ -305,6 +318,7 @@ void kmeans_destroy(kmeans_ctx* c) {
     if (c->bws) km::batched_ws_free(c->bws);
     if (c->nws) km::net_ws_free(c->nws);
     if (c->sws) km::seed_ws_free(c->sws);
+    if (c->wws) km::wide_ws_free(c->wws);
     delete c;
 }
 
@@ -335,6 +349,10 @@ int kmeans_set_option(kmeans_ctx* c, int32_t option, int64_t value) {
             if (value < 0 || value > 2) return fail(c, KM_EINVAL, "KM_OPT_PERSIST takes 0, 1 or 2");
             c->persist = (int)value;
             return KM_OK;
+        case KM_OPT_WIDE:
+            if (value != 0 && value != 1) return fail(c, KM_EINVAL, "KM_OPT_WIDE takes 0 or 1");
+            c->wide = (int)value;
+            return KM_OK;
         default:
             return fail(c, KM_EINVAL, "unknown option %d", option);
     }
@@ -350,6 +368,7 @@ int kmeans_assign(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int32_t 
     if (!rc) rc = check_centres(c, centroids, K, d, "centroids");
     if (rc) return rc;
     KM_HIP(c, hipSetDevice(c->device));
+    if (km::wide_shape(c, d, K)) return km::wide_assign(c, X, N, ld, d, K, centroids, labels, objective);
     const bool vec = vec_ok(X, ld);
     const int grid = grid_for(c, N);
     stage(c, X, N, ld, d, K, centroids, 0.0, 1);
@@ -377,6 +396,8 @@ int kmeans_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int32_t d, 
     if (!rc && !centroids_out) rc = fail(c, KM_EINVAL, "centroids_out is NULL");
     if (rc) return rc;
     KM_HIP(c, hipSetDevice(c->device));
+    if (km::wide_shape(c, d, K))
+        return km::wide_fit(c, X, N, ld, d, K, init, tol, max_iter, centroids_out, labels_out, res);
     rc = ensure_hist(c, max_iter);
     if (rc) return rc;
     const bool vec = vec_ok(X, ld);

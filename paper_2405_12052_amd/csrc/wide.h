@@ -1,0 +1,89 @@
+// wide.h -- device state and launchers of the general-shape fit: any d in
+// [1, WD_MAX] and K in [1, WK_MAX] whose per-block tables fit in LDS (the
+// single-fit kernels of lloyd_kernels.hip cover d in {2, 3}, K <= 64).
+// Internal to libkmeans_mi355x.so; the public interface is include/kmeans.h.
+//
+// The method is the same Lloyd iteration (the paper's "The Lloyd's
+// Algorithm" and "Serial Lloyd's Algorithm"): reassignment by the argmin of
+// the float32 squared distance in the direct form, per-cluster exact integer
+// sums of x * 2^G, the float64 mean step with the empty-cluster rule, E and
+// the tolerance test.  Per update two kernels run: wide_update (reassignment
+// and per-block sums) and wide_reduce (the partials summed into the totals by
+// the whole grid, then the mean step in the last block).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace km {
+
+constexpr int WD_MAX = 32;        // largest d
+constexpr int WK_MAX = 1024;      // largest K
+constexpr int WBLOCK = 256;       // threads per block of the wide kernels
+constexpr int WMAX_GRID = 1024;   // cap of the update grid (rows of partials)
+constexpr int WCHUNK = 32;        // partials summed per thread in wide_reduce
+constexpr int WLDS_MAX = 61440;   // dynamic LDS of one wide_update block
+
+// Compiled point widths: d is padded with zero coordinates up to the next of
+// these (zeros add exactly nothing to a squared distance).
+__host__ __device__ constexpr int wide_width(int d) {
+    return d <= 4 ? d : d <= 6 ? 6 : d <= 8 ? 8 : d <= 12 ? 12 : d <= 16 ? 16 : d <= 24 ? 24 : 32;
+}
+// Floats per centre in LDS (the width rounded up to whole float4s).
+__host__ __device__ constexpr int wide_stride(int D) { return (D + 3) & ~3; }
+
+// LDS bytes of one wide_update block for (d, K): integer sums and counts
+// K * (d + 1) int64 (rounded to 16 bytes), float32 centres K * stride, and
+// the per-wave objective partials.
+__host__ __device__ constexpr size_t wide_lds_bytes(int d, int K) {
+    return (((size_t)K * (d + 1) * 8 + 15) & ~(size_t)15) +
+           (size_t)K * wide_stride(wide_width(d)) * 4 + (WBLOCK / 64) * 8;
+}
+
+struct alignas(16) WState {
+    // ---- problem (host-written) ----
+    const float* X;        // d rows of N float32, row j at X + j*ld
+    int64_t N;
+    int64_t ld;
+    int32_t d;
+    int32_t K;
+    double tol;            // stop once E < tol
+    int32_t max_iter;
+    int32_t hist_cap;      // entries of E_hist / J_hist
+    int32_t grid;          // blocks of wide_update (rows of part)
+    int32_t vec;           // rows 16-byte aligned and ld % 4 == 0
+    double* mu64;          // [K * d] float64 centres, row-major
+    float* mu32;           // [K * stride] the same rounded to float32, zero padded
+    unsigned long long* part;  // [grid][K * (d + 1)] per-block sums | counts
+    unsigned long long* tot;   // [K * (d + 1)] totals (zero between updates)
+    double* jpart;         // [grid] per-block objective partials
+    double* E_hist;        // [hist_cap]
+    double* J_hist;        // [hist_cap]
+    // ---- progress (device-written; read back by the host) ----
+    int32_t t;             // updates performed
+    int32_t done;          // 1: no further update runs
+    int32_t flags;         // FLAG_* (km_internal.h)
+    int32_t pad0;
+    double E;              // E of the last update
+    double J;              // objective of the last reassignment pass
+    int64_t empty_events;  // clusters left empty, summed over updates
+    // ---- device scratch ----
+    uint32_t absmax_bits;  // max |x| over the data, as float bits
+    uint32_t ticket;       // blocks finished in the current kernel
+};
+
+constexpr size_t kWUploadBytes = offsetof(WState, absmax_bits) + 8;
+constexpr size_t kWProgressOffset = offsetof(WState, t);
+constexpr size_t kWProgressBytes = offsetof(WState, absmax_bits) - offsetof(WState, t);
+
+// Launchers (wide_kernels.hip); each returns hipErrorInvalidValue for a
+// shape or grid outside the limits above.
+hipError_t launch_wide_scan(WState* st, int grid, hipStream_t s);
+hipError_t launch_wide_update(WState* st, int d, int K, int grid, hipStream_t s);
+hipError_t launch_wide_reduce(WState* st, int d, int K, int grid_update, hipStream_t s);
+hipError_t launch_wide_label(WState* st, int32_t* labels, int d, int K, int grid,
+                             hipStream_t s);
+// Resident wide_update blocks per compute unit for (d, K); 0 on error.
+int wide_blocks_per_cu(int d, size_t lds);
+
+}  // namespace km

@@ -43,9 +43,17 @@ def test_abi_version():
 @pytest.mark.parametrize("args,code", [
     ((100, 100, 3, 4, 1e-6, 10), km.KM_OK),
     ((100, 128, 2, 64, 0.0, 1), km.KM_OK),
-    ((100, 100, 4, 4, 1e-6, 10), km.KM_EUNSUPPORTED),
-    ((100, 100, 1, 4, 1e-6, 10), km.KM_EUNSUPPORTED),
-    ((100, 100, 3, 65, 1e-6, 10), km.KM_EUNSUPPORTED),
+    ((100, 100, 4, 4, 1e-6, 10), km.KM_OK),
+    ((100, 100, 1, 4, 1e-6, 10), km.KM_OK),
+    ((100, 100, 3, 65, 1e-6, 10), km.KM_OK),
+    ((2000, 2000, 3, 1024, 1e-6, 10), km.KM_OK),
+    ((2000, 2000, 16, 307, 1e-6, 10), km.KM_OK),
+    ((2000, 2000, 16, 308, 1e-6, 10), km.KM_EUNSUPPORTED),
+    ((2000, 2000, 32, 156, 1e-6, 10), km.KM_OK),
+    ((2000, 2000, 32, 157, 1e-6, 10), km.KM_EUNSUPPORTED),
+    ((2000, 2000, 33, 2, 1e-6, 10), km.KM_EUNSUPPORTED),
+    ((2000, 2000, 2, 1025, 1e-6, 10), km.KM_EUNSUPPORTED),
+    ((100, 100, 0, 4, 1e-6, 10), km.KM_EINVAL),
     ((10, 10, 2, 11, 1e-6, 10), km.KM_EINVAL),
     ((0, 0, 2, 1, 1e-6, 10), km.KM_EINVAL),
     ((100, 99, 2, 4, 1e-6, 10), km.KM_EINVAL),

@@ -89,18 +89,18 @@ def test_exact_ties_go_to_lowest_index():
     assert lab.tolist() == [0, 0, 0]
 
 
-def test_assign_brute_force_and_second_distance():
-    rng = np.random.default_rng(5)
-    for d in (2, 3):
-        X = rng.normal(size=(d, 50)).astype(np.float32)
-        mu = rng.normal(size=(7, d))
-        lab, dmin, dsec = oracle.assign(X, mu, assign_f32=False)
-        for i in range(50):
-            D = [math.fsum((float(X[j, i]) - mu[k, j]) ** 2 for j in range(d)) for k in range(7)]
-            order = sorted(range(7), key=lambda k: (D[k], k))
-            assert lab[i] == order[0]
-            assert math.isclose(dmin[i], D[order[0]], rel_tol=1e-14)
-            assert math.isclose(dsec[i], D[order[1]], rel_tol=1e-14)
+@pytest.mark.parametrize("d,K", [(2, 7), (3, 7), (1, 9), (5, 70), (16, 12), (32, 3)])
+def test_assign_brute_force_and_second_distance(d, K):
+    rng = np.random.default_rng(5 + d * 100 + K)
+    X = rng.normal(size=(d, 50)).astype(np.float32)
+    mu = rng.normal(size=(K, d))
+    lab, dmin, dsec = oracle.assign(X, mu, assign_f32=False)
+    for i in range(50):
+        D = [math.fsum((float(X[j, i]) - mu[k, j]) ** 2 for j in range(d)) for k in range(K)]
+        order = sorted(range(K), key=lambda k: (D[k], k))
+        assert lab[i] == order[0]
+        assert math.isclose(dmin[i], D[order[0]], rel_tol=1e-14)
+        assert math.isclose(dsec[i], D[order[1]], rel_tol=1e-14)
 
 
 def test_assign_f32_rounds_only_the_centres():
@@ -296,7 +296,7 @@ def test_well_separated_blobs_recover_sample_means():
 # ----------------------------------------------------------- library cross-check
 def test_scipy_kmeans2_same_iterates():
     from scipy.cluster.vq import kmeans2
-    for seed, d, K in ((0, 2, 4), (1, 3, 7), (2, 3, 16)):
+    for seed, d, K in ((0, 2, 4), (1, 3, 7), (2, 3, 16), (3, 8, 80), (4, 1, 5), (5, 16, 20)):
         s = datagen.spec("C2", N=30_000, d=d, K=K, seed=300 + seed)
         X, _ = datagen.generate(s)
         mu0 = datagen.init_sample(X, s.N, K, seed)
