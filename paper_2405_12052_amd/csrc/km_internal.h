@@ -61,7 +61,7 @@ struct alignas(16) State {
     float4 mu32[KMAX];                 // the same rounded to float32, padded
     // ---- derived from mu32 on the device before each reassignment ----
     float4 cand[KPAD];                 // {-2 m0, -2 m1, -2 m2, fl32(|m|^2)}; pads
-                                       // {0, 0, 0, +inf} up to a whole triple
+                                       // {0, 0, 0, 2^127} up to a whole triple
     float4 bnd;                        // {2^-20 Cmax, 2^-19 A0, 2^-19 A1, 2^-19 A2}
 };
 

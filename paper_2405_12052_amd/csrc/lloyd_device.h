@@ -125,8 +125,81 @@ __device__ __forceinline__ float expanded_key(float x0, float x1, float x2, floa
 // winner is certified, and then arg[p] (its index) and best[p] (the
 // direct-form squared distance to it).  Points with ok[p] == false need the
 // direct-form scan (direct_scan).
+//
+// Per triple of centres the scan keeps, per point, only the smallest key of
+// the triple with the triple's index written into its 5 lowest bits (one
+// and-or), the smallest of those (m1) and the second smallest (m2): four
+// compare-type instructions per triple.  At the end the winning triple's
+// three keys are formed again (bit-identical), giving the exact smallest key
+// t1, its first index, and the triple's second smallest t2.  The second
+// smallest key over all centres is then min(m2, t2) up to the index bits in
+// m2 (at most 31 units in its last place, below 2^-18 |m2|), which the
+// certificate adds to the rounding bound.
+constexpr uint32_t TRI_BITS = 31u;  // ntri <= 32
+
+// v with its 5 lowest bits replaced by the (wave-uniform) index g: one
+// bitfield insert (the mask is an inline constant, g a scalar register).
+__device__ __forceinline__ float with_index(float v, int g) {
+    float r;
+    asm("v_bfi_b32 %0, 31, %1, %2" : "=v"(r) : "s"(g), "v"(v));
+    return r;
+}
+
 template <int D>
 __device__ __forceinline__ void nearest4(const float4* __restrict__ scand,
+                                         const float4* __restrict__ smu, int K, int ntri,
+                                         float4 bnd, float ninf, const float (&x)[D][4],
+                                         float (&best)[4], int (&arg)[4], bool (&ok)[4]) {
+    float m1[4], m2[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) { m1[p] = INFINITY; m2[p] = INFINITY; }
+    for (int g = 0; g < ntri; ++g) {
+        const float4 r0 = scand[3 * g], r1 = scand[3 * g + 1], r2 = scand[3 * g + 2];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const float x2 = D == 3 ? x[D - 1][p] : 0.0f;
+            const float s0 = expanded_key<D>(x[0][p], x[1][p], x2, r0);
+            const float s1 = expanded_key<D>(x[0][p], x[1][p], x2, r1);
+            const float s2 = expanded_key<D>(x[0][p], x[1][p], x2, r2);
+            const float g1 = fminf(fminf(s0, s1), s2);
+            const float gp = with_index(g1, g);
+            m2[p] = __builtin_amdgcn_fmed3f(m1[p], gp, m2[p]);
+            m1[p] = min2(m1[p], gp, ninf);
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const float x0 = x[0][p], x1 = x[1][p], x2 = D == 3 ? x[D - 1][p] : 0.0f;
+        // the winning triple's keys again: exact smallest, its first index,
+        // and the triple's second smallest
+        const int k0 = 3 * (int)(__float_as_uint(m1[p]) & TRI_BITS);
+        const float s0 = expanded_key<D>(x0, x1, x2, scand[k0]);
+        const float s1 = expanded_key<D>(x0, x1, x2, scand[k0 + 1]);
+        const float s2 = expanded_key<D>(x0, x1, x2, scand[k0 + 2]);
+        const float t1 = fminf(fminf(s0, s1), s2);
+        const float t2 = __builtin_amdgcn_fmed3f(s0, s1, s2);
+        const int k = s0 == t1 ? k0 : (s1 == t1 ? k0 + 1 : k0 + 2);
+        // rounding bound of the keys of this point, plus the index bits of m2
+        float b = fmaf(bnd.y, fabsf(x0), bnd.x);
+        b = fmaf(bnd.z, fabsf(x1), b);
+        if constexpr (D == 3) b = fmaf(bnd.w, fabsf(x2), b);
+        const bool other = m2[p] < t2;
+        const float sec = other ? m2[p] : t2;
+        if (other) b += ldexpf(fabsf(m2[p]), -17);
+        ok[p] = sec - t1 > b && k < K;
+        arg[p] = ok[p] ? k : 0;
+        best[p] = direct_dist<D>(x0, x1, x2, smu[arg[p]]);
+    }
+}
+
+// The same certified scan with the winning triple tracked by a compare and a
+// select per triple, and both second-smallest candidates (across and within
+// triples) kept for every triple: seven compare-type instructions per triple
+// instead of four, but less work at the end and fewer live registers.  The
+// batched kernel, whose instances have few centres and whose restarts keep
+// many values live, is faster with this form.
+template <int D>
+__device__ __forceinline__ void nearest4_cmp(const float4* __restrict__ scand,
                                          const float4* __restrict__ smu, int K, int ntri,
                                          float4 bnd, float ninf, const float (&x)[D][4],
                                          float (&best)[4], int (&arg)[4], bool (&ok)[4]) {
@@ -256,7 +329,7 @@ __device__ __forceinline__ void assign_points(const float* __restrict__ X, int64
 }
 
 // Centre tables for the reassignment: records {-2 m, fl32(|m|^2)} padded to
-// whole triples with {0, 0, 0, +inf}, and the bound coefficients
+// whole triples with {0, 0, 0, 2^127}, and the bound coefficients
 //   b(x) = 2^-20 (Cmax + 2 sum_j A_j |x_j|),  Cmax = max_k c_k, A_j = max_k |m_kj|,
 // which exceeds twice the rounding error of any key (<= 4.01 u (Cmax + 2 sum_j
 // A_j |x_j|), u = 2^-24: the rounding of c_k and of three FMAs).  Written to
@@ -267,7 +340,9 @@ __device__ inline void prep_centres(const float4* m32, int K, float4* cand, floa
     const int tid = threadIdx.x;
     const int ntri = (K + 2) / 3;
     if (tid < 3 * ntri) {
-        float4 r = make_float4(0.f, 0.f, 0.f, INFINITY);
+        // pads: a finite key far above any real one (their keys carry index
+        // bits in the scan, which would turn an infinity into a NaN)
+        float4 r = make_float4(0.f, 0.f, 0.f, 0x1p127f);
         float c = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f;
         if (tid < K) {
             const float4 m = m32[tid];
