@@ -346,9 +346,10 @@ int kmeans_pp_init(kmeans_ctx *ctx, const float *X, int64_t N, int64_t ld, int32
  * roofline position against what the hardware sustains rather than only
  * against published peaks: rates[0] non-packed float32 FMA (v_fma_f32),
  * rates[1] v_min3_f32 and rates[2] v_med3_f32, each in lane-operations per
- * second (8 independent chains per lane, 8 waves per SIMD); rates[3] the
- * read rate of a 1 GiB device buffer in bytes per second.  Allocates and
- * frees 1 GiB of device memory; takes about a second.
+ * second (16 independent chains per lane, 16 waves per SIMD, register
+ * operands); rates[3] the read rate of a 1 GiB device buffer in bytes per
+ * second.  Allocates and frees 1 GiB of device memory; takes about a
+ * second.
  */
 int kmeans_measure_peaks(kmeans_ctx *ctx, double rates[4]);
 

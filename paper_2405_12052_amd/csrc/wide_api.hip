@@ -84,7 +84,7 @@ int ensure_part(kmeans_ctx* c, size_t n) {
     return KM_OK;
 }
 
-int points_per_lane(int d) { return wide_width(d) <= 4 ? 4 : 2; }
+int points_per_lane(int d) { return wide_width(d) <= 16 ? 4 : 2; }
 
 int update_grid(kmeans_ctx* c, int d, int K, int64_t N) {
     const size_t lds = wide_lds_bytes(d, K);

@@ -34,7 +34,7 @@ template <int D>
 struct WShape {
     static constexpr int DS = wide_stride(D);  // floats per centre in LDS
     static constexpr int NB = DS / 4;          // float4 reads per centre
-    static constexpr int P = D <= 4 ? 4 : 2;   // points per lane
+    static constexpr int P = D <= 16 ? 4 : 2;  // points per lane
 };
 
 // Load the P consecutive points starting at i0 (n of them exist) into
