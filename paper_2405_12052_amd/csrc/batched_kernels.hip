@@ -107,15 +107,17 @@ __device__ void points_pass(const BInst& in, int rank, int S, int mask, int G, f
     int qn = 0;  // this wave's queue length (the same in every lane)
 
     // add a point's fixed-point coordinates q (|q| < 2^30, see scale_exponent)
-    // and a count of one to cluster k of restart r
+    // and a count of one to cluster k of restart r; slots are coordinate-major
+    // per restart, [(r * (D + 1) + j) * K + k], so that the lanes' clusters
+    // spread over the LDS banks
     auto acc_add = [&](int r, int k, int q0, int q1, int q2) {
-        unsigned long long* a = &sm.acc[(r * K + k) * (D + 1)];
+        unsigned long long* a = &sm.acc[r * (D + 1) * K + k];
         const int qs[3] = {q0, q1, q2};
 #pragma unroll
         for (int j = 0; j < D; ++j)
-            __hip_atomic_fetch_add(&a[j], (unsigned long long)(long long)qs[j], __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-        __hip_atomic_fetch_add(&a[D], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(&a[j * K], (unsigned long long)(long long)qs[j],
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(&a[D * K], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     };
     auto take = [&](int r, int64_t i, float x0, float x1, float x2, int k, float dist) {
         if constexpr (MODE == MODE_ACC) {
@@ -275,14 +277,14 @@ __device__ bool run_instance(BatchState* __restrict__ bs, int inst, int rank, in
         for (int i = tid; i < R * K; i += BLOCK) {
             const int r = i / K, k = i - r * K;
             if (!((active >> r) & 1)) continue;
-            const unsigned long long* a = &sm.acc[(r * K + k) * (D + 1)];
-            const unsigned long long cnt = a[D];
+            const unsigned long long* a = &sm.acc[r * (D + 1) * K + k];
+            const unsigned long long cnt = a[D * K];
             double e = 0.0;
             float m32[3] = {0.f, 0.f, 0.f};
 #pragma unroll
             for (int j = 0; j < D; ++j) {
                 const double old = sm.mu64[r][k * D + j];
-                const double v = cnt ? ldexp((double)(long long)a[j], -G) / (double)cnt : old;
+                const double v = cnt ? ldexp((double)(long long)a[j * K], -G) / (double)cnt : old;
                 const double sh = v - old;
                 e = fma(sh, sh, e);
                 sm.mu64[r][k * D + j] = v;

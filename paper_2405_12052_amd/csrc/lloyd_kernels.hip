@@ -240,7 +240,7 @@ __device__ __forceinline__ void scan_points(const float* __restrict__ X, int64_t
 struct IterSmem {
     float4 scand[KPAD];
     float4 smu[KMAX];
-    unsigned long long sacc[NW][KMAX * (DMAX + 1)];
+    unsigned long long sacc[NW][KMAX * (DMAX + 1)];  // per wave, coordinate-major: [j][k]
     unsigned long long stot[KMAX * (DMAX + 1)];
     float4 squeue[NW][QCAP];
     double sred[NW];
@@ -302,24 +302,28 @@ __device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm
     unsigned long long* myacc = sm.sacc[w];
     scan_points<D, VEC, KT>(X, ld, N, sm.scand, sm.smu, K, ntri, bnd, ninf, sm.squeue[w],
                             [&](int64_t, float x0, float x1, float x2, int k, float dist) {
-        unsigned long long* a = &myacc[k * R];
+        // coordinate-major slots [j * KMAX + k]: the 64 lanes' clusters spread
+        // over the LDS banks (a cluster-major stride of 4 int64 would put
+        // every cluster on one of a few bank groups)
+        unsigned long long* a = &myacc[k];
         const float xs[3] = {x0, x1, x2};
 #pragma unroll
         for (int j = 0; j < D; ++j) {
             const long long q = (long long)__float2int_rn(ldexpf(xs[j], G));
-            __hip_atomic_fetch_add(&a[j], (unsigned long long)q, __ATOMIC_RELAXED,
+            __hip_atomic_fetch_add(&a[j * KMAX], (unsigned long long)q, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
         }
-        __hip_atomic_fetch_add(&a[D], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(&a[D * KMAX], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         jl += (double)dist;
     });
     jl = wave_sum(jl);
     if ((tid & 63) == 0) sm.sred[w] = jl;
     __syncthreads();
-    for (int i = tid; i < K * R; i += BLOCK) {
+    for (int i = tid; i < K * R; i += BLOCK) {  // block totals, cluster-major [k * R + j]
+        const int k = i / R, j = i - k * R;
         unsigned long long s = 0ull;
 #pragma unroll
-        for (int v = 0; v < NW; ++v) s += sm.sacc[v][i];
+        for (int v = 0; v < NW; ++v) s += sm.sacc[v][j * KMAX + k];
         sm.stot[i] = s;
     }
     double jb = 0.0;

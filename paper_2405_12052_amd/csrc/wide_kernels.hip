@@ -12,8 +12,9 @@
 // P points of every lane.
 //
 // Mean step: the points' coordinates as integers rint(x * 2^G) (|x| * 2^G <
-// 2^30) and a count of one are added to their cluster's int64 slots in LDS;
-// each block writes its K * (d + 1) slots as one row of partials.
+// 2^30) and a count of one are added to their cluster's int64 slots in LDS
+// (coordinate-major, slot j * K + k); each block writes its K * (d + 1) slots
+// as one row of partials.
 // wide_reduce sums the rows over the grid, WCHUNK rows per thread, and adds
 // the chunk sums to the totals with device-scope integer atomics; integer
 // addition is exact, so the totals do not depend on the order.  The last
@@ -78,7 +79,6 @@ __device__ __forceinline__ void wide_points(const WState* __restrict__ st, const
     const int64_t N = st->N, ld = st->ld;
     const float* __restrict__ X = st->X;
     const bool vec = st->vec != 0;
-    const int R = d + 1;
     const int64_t ngroups = (N + P - 1) / P;
     const float4* cm4 = reinterpret_cast<const float4*>(cm);
     for (int64_t g = (int64_t)blockIdx.x * WBLOCK + threadIdx.x; g < ngroups;
@@ -119,16 +119,18 @@ __device__ __forceinline__ void wide_points(const WState* __restrict__ st, const
             if (p < n) {
                 jl += (double)best[p];
                 if constexpr (MODE == WMODE_ACC) {
-                    unsigned long long* a = acc + arg[p] * R;
+                    // coordinate-major slots [j * K + k]: the lanes' clusters
+                    // spread over the LDS banks
+                    unsigned long long* a = acc + arg[p];
 #pragma unroll
                     for (int j = 0; j < D; ++j) {
                         if (j < d) {
                             const long long q = (long long)__float2int_rn(ldexpf(x[p][j], G));
-                            __hip_atomic_fetch_add(&a[j], (unsigned long long)q, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                            __hip_atomic_fetch_add(&a[j * K], (unsigned long long)q,
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                         }
                     }
-                    __hip_atomic_fetch_add(&a[d], 1ull, __ATOMIC_RELAXED,
+                    __hip_atomic_fetch_add(&a[d * K], 1ull, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
                 } else {
                     if (labels) labels[i0 + p] = arg[p];
@@ -233,7 +235,7 @@ __global__ __launch_bounds__(WBLOCK) void wide_reduce(WState* __restrict__ st) {
     __shared__ int sempty;
     if (st->done) return;
     const int tid = threadIdx.x;
-    const int d = st->d, K = st->K, R = d + 1, nacc = K * R, gu = st->grid;
+    const int d = st->d, K = st->K, nacc = K * (d + 1), gu = st->grid;
     unsigned long long* tot = st->tot;
     {
         const int i = blockIdx.x * WBLOCK + tid;
@@ -287,12 +289,12 @@ __global__ __launch_bounds__(WBLOCK) void wide_reduce(WState* __restrict__ st) {
     const int DS = wide_stride(wide_width(d));
     int emp = 0;
     for (int k = tid; k < K; k += WBLOCK) {
-        const unsigned long long* a = stot + k * R;
-        const unsigned long long cnt = a[d];
+        const unsigned long long* a = stot + k;   // slots [j * K + k]
+        const unsigned long long cnt = a[d * K];
         double e = 0.0;
         for (int j = 0; j < d; ++j) {
             const double old = st->mu64[k * d + j];
-            const double v = cnt ? ldexp((double)(long long)a[j], -G) / (double)cnt : old;
+            const double v = cnt ? ldexp((double)(long long)a[j * K], -G) / (double)cnt : old;
             const double sh = v - old;
             e = fma(sh, sh, e);
             st->mu64[k * d + j] = v;
