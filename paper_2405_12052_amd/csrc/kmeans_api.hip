@@ -116,10 +116,14 @@ bool vec_ok(const float* X, int64_t ld) {
     return (reinterpret_cast<uintptr_t>(X) & 15u) == 0 && (ld & 3) == 0;
 }
 
+// Grid of the per-update kernels: enough blocks for one group of 4 points
+// per thread, at most 16 per compute unit.  About 5 blocks per compute unit
+// are resident at K = 64 (LDS-limited); at N = 2e8 a grid of 16 per unit
+// measured 5 % faster per update than 8 per unit, and 8 faster than 5.
 int grid_for(kmeans_ctx* c, int64_t N) {
     const int64_t groups = (N + 3) / 4;
     const int64_t need = (groups + km::BLOCK - 1) / km::BLOCK;
-    int64_t cap = c->blocks > 0 ? c->blocks : (int64_t)c->n_cu * 8;
+    int64_t cap = c->blocks > 0 ? c->blocks : (int64_t)c->n_cu * 16;
     if (cap > km::MAX_BLOCKS) cap = km::MAX_BLOCKS;
     int64_t g = need < cap ? need : cap;
     return (int)(g < 1 ? 1 : g);
