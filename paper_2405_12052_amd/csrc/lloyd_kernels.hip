@@ -237,10 +237,15 @@ __device__ __forceinline__ void scan_points(const float* __restrict__ X, int64_t
 
 // ---------------------------------------------------------------- lloyd_iter
 // LDS of one update.
+// Copies of the block's per-cluster accumulators in LDS: wave w adds to copy
+// w % ACC_COPIES.  Fewer copies mean less LDS per block, hence more resident
+// blocks; more copies mean fewer waves adding to the same slots.
+constexpr int ACC_COPIES = 2;
+
 struct IterSmem {
     float4 scand[KPAD];
     float4 smu[KMAX];
-    unsigned long long sacc[NW][KMAX * (DMAX + 1)];  // per wave, coordinate-major: [j][k]
+    unsigned long long sacc[ACC_COPIES][KMAX * (DMAX + 1)];  // coordinate-major: [j][k]
     unsigned long long stot[KMAX * (DMAX + 1)];
     float4 squeue[NW][QCAP];
     double sred[NW];
@@ -295,11 +300,11 @@ __device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm
     const int tid = threadIdx.x, w = tid >> 6;
     const int64_t N = st->N, ld = st->ld;
     const float* __restrict__ X = st->X;
-    for (int i = tid; i < NW * KMAX * (DMAX + 1); i += BLOCK) (&sm.sacc[0][0])[i] = 0ull;
+    for (int i = tid; i < ACC_COPIES * KMAX * (DMAX + 1); i += BLOCK) (&sm.sacc[0][0])[i] = 0ull;
     __syncthreads();
 
     double jl = 0.0;
-    unsigned long long* myacc = sm.sacc[w];
+    unsigned long long* myacc = sm.sacc[w % ACC_COPIES];
     scan_points<D, VEC, KT>(X, ld, N, sm.scand, sm.smu, K, ntri, bnd, ninf, sm.squeue[w],
                             [&](int64_t, float x0, float x1, float x2, int k, float dist) {
         // coordinate-major slots [j * KMAX + k]: the 64 lanes' clusters spread
@@ -323,7 +328,7 @@ __device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm
         const int k = i / R, j = i - k * R;
         unsigned long long s = 0ull;
 #pragma unroll
-        for (int v = 0; v < NW; ++v) s += sm.sacc[v][j * KMAX + k];
+        for (int v = 0; v < ACC_COPIES; ++v) s += sm.sacc[v][j * KMAX + k];
         sm.stot[i] = s;
     }
     double jb = 0.0;
