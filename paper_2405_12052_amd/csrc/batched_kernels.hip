@@ -267,8 +267,14 @@ __device__ bool run_instance(BatchState* __restrict__ bs, int inst, int rank, in
             if (!team_barrier(bs, tm, nbar, S, &sm.flag)) return false;
             const unsigned long long* src = tpart + (size_t)par * S * BK_PART;
             for (int i = tid; i < nacc; i += BLOCK) {
+                // all S device-coherent loads in flight before the first add
+                unsigned long long v[BK_TEAM_MAX];
+#pragma unroll
+                for (int q = 0; q < BK_TEAM_MAX; ++q)
+                    v[q] = q < S ? ld_agent(&src[(size_t)q * BK_PART + i]) : 0ull;
                 unsigned long long s = 0ull;
-                for (int q = 0; q < S; ++q) s += ld_agent(&src[(size_t)q * BK_PART + i]);
+#pragma unroll
+                for (int q = 0; q < BK_TEAM_MAX; ++q) s += v[q];
                 sm.acc[i] = s;
             }
             __syncthreads();
@@ -329,8 +335,13 @@ __device__ bool run_instance(BatchState* __restrict__ bs, int inst, int rank, in
             if (!team_barrier(bs, tm, nbar, S, &sm.flag)) return false;
             const double* src = tjpart + (size_t)par * S * BK_RMAX;
             if (tid < R) {
+                double v[BK_TEAM_MAX];
+#pragma unroll
+                for (int q = 0; q < BK_TEAM_MAX; ++q)
+                    v[q] = q < S ? ld_agent(&src[(size_t)q * BK_RMAX + tid]) : 0.0;
                 double s = 0.0;
-                for (int q = 0; q < S; ++q) s += ld_agent(&src[(size_t)q * BK_RMAX + tid]);
+#pragma unroll
+                for (int q = 0; q < BK_TEAM_MAX; ++q) s += v[q];  // rank order
                 sm.J[tid] = s;
             }
             __syncthreads();
