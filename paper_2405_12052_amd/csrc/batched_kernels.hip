@@ -30,13 +30,27 @@ namespace {
 
 enum { MODE_ACC = 0, MODE_OBJ = 1, MODE_LABEL = 2 };
 constexpr int BK_ACC = BK_RMAX * BK_KMAX * (DMAX + 1);
+// LDS slots for the accumulators: room for 2 copies at the largest shape and
+// up to ACC_COPY_MAX copies at small ones (acc_copies).
+constexpr int BK_ACC_SLOTS = 2 * BK_ACC;
+constexpr int ACC_COPY_MAX = 16;
+
+// Copies of an instance's accumulators (a power of two): lane l adds to copy
+// l % copies.  With few clusters, many of a wave's 64 lanes add to the same
+// slot and their LDS atomics serialise; separate copies for lane groups cut
+// that, and the copies are summed once per update.
+__device__ __forceinline__ int acc_copies(int nacc) {
+    int c = 1;
+    while (c < ACC_COPY_MAX && 2 * c * nacc <= BK_ACC_SLOTS) c *= 2;
+    return c;
+}
 
 struct BSmem {
     float4 scand[BK_RMAX][BK_KPAD];
     float4 smu[BK_RMAX][BK_KMAX];
     float4 sbnd[BK_RMAX];
     double mu64[BK_RMAX][BK_KMAX * DMAX];
-    unsigned long long acc[BK_ACC];
+    unsigned long long acc[BK_ACC_SLOTS];
     float4 queue[NW][QCAP];
     double jw[NW][BK_RMAX];
     double J[BK_RMAX];
@@ -110,8 +124,10 @@ __device__ void points_pass(const BInst& in, int rank, int S, int mask, int G, f
     // and a count of one to cluster k of restart r; slots are coordinate-major
     // per restart, [(r * (D + 1) + j) * K + k], so that the lanes' clusters
     // spread over the LDS banks
+    const int nacc = in.R * K * (D + 1);
+    unsigned long long* const myacc = &sm.acc[(lane & (acc_copies(nacc) - 1)) * nacc];
     auto acc_add = [&](int r, int k, int q0, int q1, int q2) {
-        unsigned long long* a = &sm.acc[r * (D + 1) * K + k];
+        unsigned long long* a = &myacc[r * (D + 1) * K + k];
         const int qs[3] = {q0, q1, q2};
 #pragma unroll
         for (int j = 0; j < D; ++j)
@@ -256,10 +272,19 @@ __device__ bool run_instance(BatchState* __restrict__ bs, int inst, int rank, in
     for (;;) {
         const int active = __builtin_amdgcn_readfirstlane(sm.active);
         if (!active) break;
-        for (int i = tid; i < nacc; i += BLOCK) sm.acc[i] = 0ull;
+        const int copies = acc_copies(nacc);
+        for (int i = tid; i < copies * nacc; i += BLOCK) sm.acc[i] = 0ull;
         __syncthreads();
         points_pass<D, MODE_ACC>(in, rank, S, active, G, ninf, sm, jl);
         __syncthreads();
+        if (copies > 1) {  // the copies summed into the first
+            for (int i = tid; i < nacc; i += BLOCK) {
+                unsigned long long s = sm.acc[i];
+                for (int c = 1; c < copies; ++c) s += sm.acc[c * nacc + i];
+                sm.acc[i] = s;
+            }
+            __syncthreads();
+        }
         if (S > 1) {
             const uint32_t par = nbar & 1u;
             unsigned long long* dst = tpart + ((size_t)par * S + rank) * BK_PART;
