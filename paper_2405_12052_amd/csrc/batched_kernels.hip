@@ -30,19 +30,18 @@ namespace {
 
 enum { MODE_ACC = 0, MODE_OBJ = 1, MODE_LABEL = 2 };
 constexpr int BK_ACC = BK_RMAX * BK_KMAX * (DMAX + 1);
-// LDS slots for the accumulators: room for 2 copies at the largest shape and
+// LDS slots for the accumulators: room for 3 copies at the largest shape and
 // up to ACC_COPY_MAX copies at small ones (acc_copies).
-constexpr int BK_ACC_SLOTS = 2 * BK_ACC;
+constexpr int BK_ACC_SLOTS = 3 * BK_ACC;
 constexpr int ACC_COPY_MAX = 16;
 
-// Copies of an instance's accumulators (a power of two): lane l adds to copy
-// l % copies.  With few clusters, many of a wave's 64 lanes add to the same
-// slot and their LDS atomics serialise; separate copies for lane groups cut
-// that, and the copies are summed once per update.
+// Copies of an instance's accumulators: lane l adds to copy l % copies.
+// With few clusters, many of a wave's 64 lanes add to the same slot and their
+// LDS atomics serialise; separate copies for lane groups cut that, and the
+// copies are summed once per update.
 __device__ __forceinline__ int acc_copies(int nacc) {
-    int c = 1;
-    while (c < ACC_COPY_MAX && 2 * c * nacc <= BK_ACC_SLOTS) c *= 2;
-    return c;
+    const int c = BK_ACC_SLOTS / nacc;
+    return c < ACC_COPY_MAX ? c : ACC_COPY_MAX;
 }
 
 struct BSmem {
@@ -125,7 +124,7 @@ __device__ void points_pass(const BInst& in, int rank, int S, int mask, int G, f
     // per restart, [(r * (D + 1) + j) * K + k], so that the lanes' clusters
     // spread over the LDS banks
     const int nacc = in.R * K * (D + 1);
-    unsigned long long* const myacc = &sm.acc[(lane & (acc_copies(nacc) - 1)) * nacc];
+    unsigned long long* const myacc = &sm.acc[(lane % acc_copies(nacc)) * nacc];
     auto acc_add = [&](int r, int k, int q0, int q1, int q2) {
         unsigned long long* a = &myacc[r * (D + 1) * K + k];
         const int qs[3] = {q0, q1, q2};
