@@ -237,15 +237,19 @@ __device__ __forceinline__ void scan_points(const float* __restrict__ X, int64_t
 
 // ---------------------------------------------------------------- lloyd_iter
 // LDS of one update.
-// Copies of the block's per-cluster accumulators in LDS: wave w adds to copy
-// w % ACC_COPIES.  Fewer copies mean less LDS per block, hence more resident
-// blocks; more copies mean fewer waves adding to the same slots.
-constexpr int ACC_COPIES = 2;
+// The block's per-cluster accumulators in LDS: ACC_SLOTS int64 slots hold
+// `copies` = min(ACC_COPY_MAX, ACC_SLOTS / (K (d+1))) copies of the K (d+1)
+// sums and counts, and thread t adds to copy t % copies.  With few clusters
+// many lanes of a wave would add to the same slot, and LDS atomics on one
+// slot serialise; the copies spread them, and are summed once per pass.
+constexpr int ACC_SLOTS = 2 * KMAX * (DMAX + 1);
+constexpr int ACC_COPY_MAX = 16;
 
 struct IterSmem {
     float4 scand[KPAD];
     float4 smu[KMAX];
-    unsigned long long sacc[ACC_COPIES][KMAX * (DMAX + 1)];  // coordinate-major: [j][k]
+    // copy c at [c * K * (d+1)], coordinate-major inside: slot j * K + k
+    unsigned long long sacc[ACC_SLOTS];
     unsigned long long stot[KMAX * (DMAX + 1)];
     float4 squeue[NW][QCAP];
     double sred[NW];
@@ -291,7 +295,7 @@ __device__ __forceinline__ void wr4(float4* p, float4 v) {
 // One reassignment + accumulation pass over the grid's points against the
 // centre tables in sm (the paper's reassignment step and the numerators and
 // denominators of its mean step), reduced across the grid.  Returns true in
-// the one final block, with the grid's integer sums | counts in sm.sacc[0]
+// the one final block, with the grid's integer sums | counts in sm.sacc
 // and the objective of this pass in sm.sJ.
 template <int D, bool VEC, int KT>
 __device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm, int K, int G, int ntri,
@@ -300,14 +304,16 @@ __device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm
     const int tid = threadIdx.x, w = tid >> 6;
     const int64_t N = st->N, ld = st->ld;
     const float* __restrict__ X = st->X;
-    for (int i = tid; i < ACC_COPIES * KMAX * (DMAX + 1); i += BLOCK) (&sm.sacc[0][0])[i] = 0ull;
+    const int KR = K * R;
+    const int copies = ACC_SLOTS / KR < ACC_COPY_MAX ? ACC_SLOTS / KR : ACC_COPY_MAX;
+    for (int i = tid; i < copies * KR; i += BLOCK) sm.sacc[i] = 0ull;
     __syncthreads();
 
     double jl = 0.0;
-    unsigned long long* myacc = sm.sacc[w % ACC_COPIES];
+    unsigned long long* myacc = &sm.sacc[(tid % copies) * KR];
     scan_points<D, VEC, KT>(X, ld, N, sm.scand, sm.smu, K, ntri, bnd, ninf, sm.squeue[w],
                             [&](int64_t, float x0, float x1, float x2, int k, float dist) {
-        // coordinate-major slots [j * KMAX + k]: the 64 lanes' clusters spread
+        // coordinate-major slots [j * K + k]: the 64 lanes' clusters spread
         // over the LDS banks (a cluster-major stride of 4 int64 would put
         // every cluster on one of a few bank groups)
         unsigned long long* a = &myacc[k];
@@ -315,10 +321,10 @@ __device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm
 #pragma unroll
         for (int j = 0; j < D; ++j) {
             const long long q = (long long)__float2int_rn(ldexpf(xs[j], G));
-            __hip_atomic_fetch_add(&a[j * KMAX], (unsigned long long)q, __ATOMIC_RELAXED,
+            __hip_atomic_fetch_add(&a[j * K], (unsigned long long)q, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
         }
-        __hip_atomic_fetch_add(&a[D * KMAX], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(&a[D * K], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         jl += (double)dist;
     });
     jl = wave_sum(jl);
@@ -327,15 +333,14 @@ __device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm
     for (int i = tid; i < K * R; i += BLOCK) {  // block totals, cluster-major [k * R + j]
         const int k = i / R, j = i - k * R;
         unsigned long long s = 0ull;
-#pragma unroll
-        for (int v = 0; v < ACC_COPIES; ++v) s += sm.sacc[v][j * KMAX + k];
+        for (int c = 0; c < copies; ++c) s += sm.sacc[c * KR + j * K + k];
         sm.stot[i] = s;
     }
     double jb = 0.0;
 #pragma unroll
     for (int v = 0; v < NW; ++v) jb += sm.sred[v];
     __syncthreads();
-    return reduce_grid(st, sm.stot, K * R, jb, &sm.sacc[0][0], &sm.sJ, &sm.sflag);
+    return reduce_grid(st, sm.stot, K * R, jb, sm.sacc, &sm.sJ, &sm.sflag);
 }
 
 // The final block's update (the paper's mean-calculation step, its error E
@@ -348,7 +353,7 @@ template <int D, bool COH>
 __device__ __forceinline__ void finalize_update(State* __restrict__ st, IterSmem& sm, int K, int G) {
     constexpr int R = D + 1;
     const int tid = threadIdx.x;
-    const unsigned long long* tot = &sm.sacc[0][0];
+    const unsigned long long* tot = sm.sacc;
     if (tid < K) {
         const int k = tid;
         const unsigned long long cnt = tot[k * R + D];
