@@ -5,11 +5,13 @@
 //
 // The method is the same Lloyd iteration (the paper's "The Lloyd's
 // Algorithm" and "Serial Lloyd's Algorithm"): reassignment by the argmin of
-// the float32 squared distance in the direct form, per-cluster exact integer
-// sums of x * 2^G, the float64 mean step with the empty-cluster rule, E and
-// the tolerance test.  Per update two kernels run: wide_update (reassignment
-// and per-block sums) and wide_reduce (the partials summed into the totals by
-// the whole grid, then the mean step in the last block).
+// the float32 squared distance in the direct form (found through a certified
+// expanded key, see wide_kernels.hip), per-cluster exact integer sums of
+// x * 2^G, the float64 mean step with the empty-cluster rule, E and the
+// tolerance test.  Per update two kernels run: wide_update (reassignment and
+// per-block sums) and wide_reduce (the partials summed into the totals by the
+// whole grid, then the mean step and the next pass's key tables in the last
+// block).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -22,7 +24,8 @@ constexpr int WK_MAX = 1024;      // largest K
 constexpr int WBLOCK = 256;       // threads per block of the wide kernels
 constexpr int WMAX_GRID = 1024;   // cap of the update grid (rows of partials)
 constexpr int WCHUNK = 32;        // partials summed per thread in wide_reduce
-constexpr int WLDS_MAX = 61440;   // dynamic LDS of one wide_update block
+constexpr int WLDS_MAX = 65536;   // dynamic LDS of one wide_update block
+constexpr int WQCAP = 128;        // re-scan queue entries per wave
 
 // Compiled point widths: d is padded with zero coordinates up to the next of
 // these (zeros add exactly nothing to a squared distance).
@@ -32,12 +35,23 @@ __host__ __device__ constexpr int wide_width(int d) {
 // Floats per centre in LDS (the width rounded up to whole float4s).
 __host__ __device__ constexpr int wide_stride(int D) { return (D + 3) & ~3; }
 
+// Centres padded to whole triples (the scan takes them three at a time).
+__host__ __device__ constexpr int wide_kpad(int K) { return 3 * ((K + 2) / 3); }
+
+// LDS of the key tables and queues, shared by wide_update and wide_label:
+// float32 centres Kpad * stride, the keys' constants Kpad (rounded to 16
+// bytes), the bound coefficients (WD_MAX + 1, padded to 36), the per-wave
+// re-scan queues and the per-wave objective partials.
+__host__ __device__ constexpr size_t wide_table_bytes(int d, int K) {
+    return (size_t)wide_kpad(K) * wide_stride(wide_width(d)) * 4 +
+           (((size_t)wide_kpad(K) * 4 + 15) & ~(size_t)15) + 36 * 4 +
+           (size_t)(WBLOCK / 64) * WQCAP * 4 + (WBLOCK / 64) * 8;
+}
+
 // LDS bytes of one wide_update block for (d, K): integer sums and counts
-// K * (d + 1) int64 (rounded to 16 bytes), float32 centres K * stride, and
-// the per-wave objective partials.
+// K * (d + 1) int64 (rounded to 16 bytes), then the tables.
 __host__ __device__ constexpr size_t wide_lds_bytes(int d, int K) {
-    return (((size_t)K * (d + 1) * 8 + 15) & ~(size_t)15) +
-           (size_t)K * wide_stride(wide_width(d)) * 4 + (WBLOCK / 64) * 8;
+    return (((size_t)K * (d + 1) * 8 + 15) & ~(size_t)15) + wide_table_bytes(d, K);
 }
 
 struct alignas(16) WState {
@@ -54,6 +68,8 @@ struct alignas(16) WState {
     int32_t vec;           // rows 16-byte aligned and ld % 4 == 0
     double* mu64;          // [K * d] float64 centres, row-major
     float* mu32;           // [K * stride] the same rounded to float32, zero padded
+    float* hh;             // [Kpad] -|m_k|^2 / 2 of the float32 centres (pads: -2^127)
+    float* amax;           // [WD_MAX + 1] max_k |m_kj| for j < d; [WD_MAX]: max_k |m_k|^2
     unsigned long long* part;  // [grid][K * (d + 1)] per-block sums | counts
     unsigned long long* tot;   // [K * (d + 1)] totals (zero between updates)
     double* jpart;         // [grid] per-block objective partials
@@ -67,6 +83,8 @@ struct alignas(16) WState {
     double E;              // E of the last update
     double J;              // objective of the last reassignment pass
     int64_t empty_events;  // clusters left empty, summed over updates
+    float plus_inf;        // +infinity, read at run time by the kernels
+    int32_t pad1;
     // ---- device scratch ----
     uint32_t absmax_bits;  // max |x| over the data, as float bits
     uint32_t ticket;       // blocks finished in the current kernel

@@ -25,6 +25,8 @@ struct WideWS {
     unsigned long long* part = nullptr;
     unsigned long long* tot = nullptr;
     double* jpart = nullptr;
+    float* hh = nullptr;       // key constants, WK_MAX + 4 floats
+    float* amax = nullptr;     // bound coefficients, WD_MAX + 1 floats
     size_t part_cap = 0;       // int64 slots of part
     std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;  // (d, K, grid, unroll)
     std::map<std::pair<int, size_t>, int> bpc;  // (width, LDS bytes) -> blocks per CU
@@ -41,6 +43,8 @@ void wide_ws_free(WideWS* w) {
     if (w->part) (void)hipFree(w->part);
     if (w->tot) (void)hipFree(w->tot);
     if (w->jpart) (void)hipFree(w->jpart);
+    if (w->hh) (void)hipFree(w->hh);
+    if (w->amax) (void)hipFree(w->amax);
     delete w;
 }
 
@@ -59,7 +63,9 @@ int ensure_ws(kmeans_ctx* c) {
         hipMalloc(&w->mu64, sizeof(double) * kMu64Max) != hipSuccess ||
         hipMalloc(&w->mu32, sizeof(float) * kMu32Max) != hipSuccess ||
         hipMalloc(&w->tot, sizeof(unsigned long long) * kTotMax) != hipSuccess ||
-        hipMalloc(&w->jpart, sizeof(double) * WMAX_GRID) != hipSuccess) {
+        hipMalloc(&w->jpart, sizeof(double) * WMAX_GRID) != hipSuccess ||
+        hipMalloc(&w->hh, sizeof(float) * (WK_MAX + 4)) != hipSuccess ||
+        hipMalloc(&w->amax, sizeof(float) * (WD_MAX + 1)) != hipSuccess) {
         wide_ws_free(w);
         return fail(c, KM_ENOMEM, "allocation of the general-shape workspace failed");
     }
@@ -132,6 +138,9 @@ int stage_upload(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, in
     h->part = w->part;
     h->tot = w->tot;
     h->jpart = w->jpart;
+    h->hh = w->hh;
+    h->amax = w->amax;
+    h->plus_inf = INFINITY;
     h->E_hist = c->hist;
     h->J_hist = c->hist + c->hist_cap;
     h->E = INFINITY;

@@ -29,8 +29,6 @@ namespace {
 
 static_assert(WBLOCK == BLOCK, "the wide kernels use the block helpers of lloyd_device.h");
 
-enum { WMODE_ACC = 0, WMODE_LABEL = 1 };
-
 template <int D>
 struct WShape {
     static constexpr int DS = wide_stride(D);  // floats per centre in LDS
@@ -66,78 +64,248 @@ __device__ __forceinline__ void wide_load(const float* __restrict__ X, int64_t l
     }
 }
 
+// One point's direct-form distance to centre row c (zero padded to D).
+template <int D>
+__device__ __forceinline__ float wide_direct(const float (&x)[D], const float4* __restrict__ c) {
+    float s = 0.0f;
+#pragma unroll
+    for (int b = 0; b < (D + 3) / 4; ++b) {
+        const float4 m = c[b];
+        const float mv[4] = {m.x, m.y, m.z, m.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = 4 * b + u;
+            if (j < D) {
+                const float t = x[j] - mv[u];
+                s = j == 0 ? t * t : fmaf(t, t, s);
+            }
+        }
+    }
+    return s;
+}
+
 // Reassignment of this thread's grid-stride share of the points against the
-// K centres cm (LDS, stride DS, zero padded).  MODE_ACC adds each point to
-// its cluster's slots in acc (K x (d + 1)); MODE_LABEL writes labels (if not
-// null).  Both add the direct-form distance to the chosen centre to jl.
-template <int D, int MODE>
+// K centres cm (LDS, Kpad rows of stride DS, zero padded) with the key
+// constants hh and the bound coefficients amax (see the file header).
+// Certified points go to sink(x, i, k, dist) at once; the others are queued
+// in the wave's LDS queue wq (point indices) and re-scanned in the direct
+// form 64 at a time, one per lane.
+template <int D, typename Sink>
 __device__ __forceinline__ void wide_points(const WState* __restrict__ st, const float* cm,
-                                            int K, int d, int G, unsigned long long* acc,
-                                            int32_t* __restrict__ labels, double& jl) {
+                                            const float* hh, const float* amax, int K, int d,
+                                            int* __restrict__ wq, Sink&& sink) {
     using S = WShape<D>;
     constexpr int P = S::P, NB = S::NB;
     const int64_t N = st->N, ld = st->ld;
     const float* __restrict__ X = st->X;
     const bool vec = st->vec != 0;
-    const int64_t ngroups = (N + P - 1) / P;
+    const float pinf = st->plus_inf;
+    const int ntri = (K + 2) / 3;
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
     const float4* cm4 = reinterpret_cast<const float4*>(cm);
-    for (int64_t g = (int64_t)blockIdx.x * WBLOCK + threadIdx.x; g < ngroups;
-         g += (int64_t)gridDim.x * WBLOCK) {
+    // twice the rounding bounds (gamma_n <= n 2^-23 here) of the two keys of
+    // a comparison and of the direct form
+    const float kc = (float)(d + 1) * 0x1p-22f;
+    const float dc = (float)(d + 2) * 0x1p-22f;
+    const float hmax = 0.5f * amax[WD_MAX];
+    int qn = 0;  // this wave's queue length (the same in every lane)
+
+    auto drain = [&](int cnt) {
+        __builtin_amdgcn_wave_barrier();
+        if (lane < cnt) {
+            const int64_t i = wq[qn - cnt + lane];
+            float xr[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) xr[j] = j < d ? X[(int64_t)j * ld + i] : 0.0f;
+            float bd = INFINITY;
+            int bk = 0;
+            for (int k = 0; k < K; ++k) {
+                const float dk = wide_direct<D>(xr, cm4 + k * NB);
+                if (dk < bd) { bd = dk; bk = k; }
+            }
+            sink(xr, i, bk, bd);
+        }
+        __builtin_amdgcn_wave_barrier();
+        qn -= cnt;
+    };
+
+    const int64_t ngroups = (N + P - 1) / P;
+    // the loop runs over whole waves (the queue and its ballots need every
+    // lane); lanes past the end carry no points
+    for (int64_t gw = (int64_t)blockIdx.x * WBLOCK + (threadIdx.x & ~63); gw < ngroups;
+         gw += (int64_t)gridDim.x * WBLOCK) {
+        const int64_t g = gw + lane;
         const int64_t i0 = g * P;
-        const int n = (N - i0) < P ? (int)(N - i0) : P;
+        const int n = g < ngroups ? ((N - i0) < P ? (int)(N - i0) : P) : 0;
         float x[P][D];
-        wide_load<D, P>(X, ld, d, vec, i0, n, x);
-        float best[P];
-        int arg[P];
+        if (n > 0) {
+            wide_load<D, P>(X, ld, d, vec, i0, n, x);
+        } else {
 #pragma unroll
-        for (int p = 0; p < P; ++p) { best[p] = INFINITY; arg[p] = 0; }
-        for (int k = 0; k < K; ++k) {
-            float s[P];
+            for (int p = 0; p < P; ++p)
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const float4 m = cm4[k * NB + b];
-                const float mv[4] = {m.x, m.y, m.z, m.w};
+                for (int j = 0; j < D; ++j) x[p][j] = 0.0f;
+        }
+        // keys m_k . x - |m_k|^2 / 2 (the largest is the nearest centre),
+        // triples of centres, 32 triples to a chunk (5 index bits)
+        float g1v[P], g2v[P];
+        int gch[P];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int j = 4 * b + u;
-                    if (j < D) {
+        for (int p = 0; p < P; ++p) { g1v[p] = -INFINITY; g2v[p] = -INFINITY; gch[p] = 0; }
+        for (int c0 = 0; c0 < ntri; c0 += 32) {
+            const int c1 = c0 + 32 < ntri ? c0 + 32 : ntri;
+            float m1[P], m2[P];
 #pragma unroll
-                        for (int p = 0; p < P; ++p) {
-                            const float t = x[p][j] - mv[u];
-                            s[p] = j == 0 ? t * t : fmaf(t, t, s[p]);
+            for (int p = 0; p < P; ++p) { m1[p] = -INFINITY; m2[p] = -INFINITY; }
+            for (int t = c0; t < c1; ++t) {
+                float sk[3][P];
+#pragma unroll
+                for (int u = 0; u < 3; ++u) {
+                    const int k = 3 * t + u;
+                    const float h = hh[k];
+#pragma unroll
+                    for (int p = 0; p < P; ++p) sk[u][p] = h;
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        const float4 m = cm4[k * NB + b];
+                        const float mv[4] = {m.x, m.y, m.z, m.w};
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int j = 4 * b + v;
+                            if (j < D) {
+#pragma unroll
+                                for (int p = 0; p < P; ++p) sk[u][p] = fmaf(x[p][j], mv[v], sk[u][p]);
+                            }
                         }
                     }
+                }
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    const float gmax = fmaxf(fmaxf(sk[0][p], sk[1][p]), sk[2][p]);
+                    const float gp = with_index(gmax, t - c0);
+                    m2[p] = __builtin_amdgcn_fmed3f(m1[p], gp, m2[p]);
+                    m1[p] = __builtin_amdgcn_fmed3f(m1[p], gp, pinf);
                 }
             }
 #pragma unroll
             for (int p = 0; p < P; ++p) {
-                if (s[p] < best[p]) { best[p] = s[p]; arg[p] = k; }
+                // merge the chunk's two largest into the running two largest
+                const float hi2 = fmaxf(g2v[p], m2[p]);
+                g2v[p] = __builtin_amdgcn_fmed3f(g1v[p], m1[p], hi2);
+                gch[p] = m1[p] > g1v[p] ? c0 : gch[p];
+                g1v[p] = fmaxf(g1v[p], m1[p]);
             }
         }
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            if (p < n) {
-                jl += (double)best[p];
-                if constexpr (MODE == WMODE_ACC) {
-                    // coordinate-major slots [j * K + k]: the lanes' clusters
-                    // spread over the LDS banks
-                    unsigned long long* a = acc + arg[p];
+            // the winning triple's keys again (bit-identical): its largest, the
+            // first index attaining it, and the triple's second largest
+            const int t = gch[p] + (int)(__float_as_uint(g1v[p]) & TRI_BITS);
+            const int k0 = 3 * t;
+            float s3[3];
 #pragma unroll
-                    for (int j = 0; j < D; ++j) {
-                        if (j < d) {
-                            const long long q = (long long)__float2int_rn(ldexpf(x[p][j], G));
-                            __hip_atomic_fetch_add(&a[j * K], (unsigned long long)q,
-                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                        }
+            for (int u = 0; u < 3; ++u) {
+                float v = hh[k0 + u];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const float4 m = cm4[(k0 + u) * NB + b];
+                    const float mv[4] = {m.x, m.y, m.z, m.w};
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) {
+                        const int j = 4 * b + w;
+                        if (j < D) v = fmaf(x[p][j], mv[w], v);
                     }
-                    __hip_atomic_fetch_add(&a[d * K], 1ull, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-                } else {
-                    if (labels) labels[i0 + p] = arg[p];
                 }
+                s3[u] = v;
+            }
+            const float t1 = fmaxf(fmaxf(s3[0], s3[1]), s3[2]);
+            const float t2 = __builtin_amdgcn_fmed3f(s3[0], s3[1], s3[2]);
+            const int k = s3[0] == t1 ? k0 : (s3[1] == t1 ? k0 + 1 : k0 + 2);
+            // certificate: the gap to the runner-up exceeds the rounding of
+            // both keys, the index bits of a packed runner-up, and the
+            // rounding of the direct form (so that it, too, ranks them so)
+            const bool other = g2v[p] > t2;
+            const float sec = other ? g2v[p] : t2;
+            const float gap = t1 - sec;
+            float mag = hmax, xx = 0.0f;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const float a = j < d ? amax[j] : 0.0f;
+                mag = fmaf(a, fabsf(x[p][j]), mag);
+                xx = fmaf(x[p][j], x[p][j], xx);
+            }
+            float bound = fmaf(kc, mag, dc * fmaxf(xx - 2.0f * t1 + gap, 0.0f));
+            if (other) bound = fmaf(0x1p-17f, fabsf(sec), bound);
+            const bool valid = p < n;
+            const bool ok = gap > bound && k < K;
+            if (valid && ok) sink(x[p], i0 + p, k, wide_direct<D>(x[p], cm4 + k * NB));
+            const bool f = valid && !ok;
+            const uint64_t mq = __ballot(f);
+            if (mq) {
+                if (f) wq[qn + __popcll(mq & below)] = (int)(i0 + p);
+                qn += __popcll(mq);
+                if (qn >= 64) drain(64);
             }
         }
     }
+    if (qn > 0) drain(qn);
+}
+
+// Key tables of the float32 centres mu32 (K rows of stride DS): hh[k] =
+// -fl32(sum_j m_kj^2) / 2 (the sum of squares in float64 FMAs, rounded
+// once), pads up to a whole triple -2^127; amax[j] = max_k |m_kj| (j < d),
+// amax[WD_MAX] = max_k fl32(sum_j m_kj^2).  Whole block.
+__device__ void key_tables(const float* __restrict__ mu32, int K, int d, int DS,
+                           float* __restrict__ hh, float* __restrict__ amax, uint32_t* sred) {
+    const int tid = threadIdx.x;
+    const int kp = wide_kpad(K);
+    uint32_t cmx = 0;
+    for (int k = tid; k < kp; k += WBLOCK) {
+        if (k < K) {
+            double q = 0.0;
+            for (int j = 0; j < d; ++j) {
+                const double m = mu32[k * DS + j];
+                q = fma(m, m, q);
+            }
+            const float c = (float)q;
+            hh[k] = -0.5f * c;
+            cmx = __float_as_uint(c) > cmx ? __float_as_uint(c) : cmx;
+        } else {
+            hh[k] = -0x1p127f;
+        }
+    }
+    for (int j = -1; j < d; ++j) {
+        uint32_t m = 0;
+        if (j < 0) {
+            m = cmx;
+        } else {
+            for (int k = tid; k < K; k += WBLOCK) {
+                const uint32_t b = __float_as_uint(mu32[k * DS + j]) & 0x7fffffffu;
+                m = b > m ? b : m;
+            }
+        }
+        m = wave_max(m);
+        if ((tid & 63) == 0) sred[tid >> 6] = m;
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t r = 0;
+            for (int w = 0; w < NW; ++w) r = sred[w] > r ? sred[w] : r;
+            amax[j < 0 ? WD_MAX : j] = __uint_as_float(r);
+        }
+        __syncthreads();
+    }
+}
+
+// Stage the centres, key constants and bound coefficients in LDS.
+template <int D>
+__device__ __forceinline__ void stage_tables(const WState* __restrict__ st, int K, float* cm,
+                                             float* hh, float* amax) {
+    constexpr int DS = WShape<D>::DS;
+    const int kp = wide_kpad(K);
+    for (int i = threadIdx.x; i < kp * DS; i += WBLOCK) cm[i] = i < K * DS ? st->mu32[i] : 0.0f;
+    for (int i = threadIdx.x; i < kp; i += WBLOCK) hh[i] = st->hh[i];
+    for (int i = threadIdx.x; i <= WD_MAX; i += WBLOCK) amax[i] = st->amax[i];
 }
 
 // Sum of v over the block, waves added in index order; valid in every thread.
@@ -175,9 +343,13 @@ __device__ __forceinline__ double ordered_sum(int n, F v, double* sw) {
 // ------------------------------------------------------------------ kernels
 
 // Once per fit: max |x| over the data (fixed-point exponent; NaN/Inf stops
-// the fit) and zeroed totals.
+// the fit), zeroed totals, and (block 0) the key tables of the initial
+// centres.
 __global__ __launch_bounds__(WBLOCK) void wide_scan(WState* __restrict__ st) {
+    __shared__ uint32_t sred[NW];
     const int tid = threadIdx.x;
+    if (blockIdx.x == 0)
+        key_tables(st->mu32, st->K, st->d, wide_stride(wide_width(st->d)), st->hh, st->amax, sred);
     const int d = st->d;
     const int64_t N = st->N, ld = st->ld;
     const int nacc = st->K * (d + 1);
@@ -211,15 +383,34 @@ __global__ __launch_bounds__(WBLOCK) void wide_update(WState* __restrict__ st) {
     using S = WShape<D>;
     const int tid = threadIdx.x;
     const int d = st->d, K = st->K, nacc = K * (d + 1);
+    const int kp = wide_kpad(K);
     unsigned long long* acc = reinterpret_cast<unsigned long long*>(wsm);
     float* cm = reinterpret_cast<float*>(wsm + (((size_t)nacc * 8 + 15) & ~(size_t)15));
-    double* sw = reinterpret_cast<double*>(cm + (size_t)K * S::DS);
+    float* hh = cm + (size_t)kp * S::DS;
+    float* amax = hh + ((kp + 3) & ~3);
+    int* wq = reinterpret_cast<int*>(amax + 36) + (tid >> 6) * WQCAP;
+    double* sw = reinterpret_cast<double*>(reinterpret_cast<int*>(amax + 36) + NW * WQCAP);
     const int G = scale_exponent(st->absmax_bits);
-    for (int i = tid; i < K * S::DS; i += WBLOCK) cm[i] = st->mu32[i];
+    stage_tables<D>(st, K, cm, hh, amax);
     for (int i = tid; i < nacc; i += WBLOCK) acc[i] = 0ull;
     __syncthreads();
     double jl = 0.0;
-    wide_points<D, WMODE_ACC>(st, cm, K, d, G, acc, nullptr, jl);
+    wide_points<D>(st, cm, hh, amax, K, d, wq,
+                   [&](const float (&xr)[D], int64_t, int k, float dist) {
+        jl += (double)dist;
+        // coordinate-major slots [j * K + k]: the lanes' clusters spread over
+        // the LDS banks
+        unsigned long long* a = acc + k;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            if (j < d) {
+                const long long q = (long long)__float2int_rn(ldexpf(xr[j], G));
+                __hip_atomic_fetch_add(&a[j * K], (unsigned long long)q, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+        __hip_atomic_fetch_add(&a[d * K], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    });
     const double jb = block_sum(jl, sw);  // also orders the LDS atomics before the copy-out
     unsigned long long* row = st->part + (size_t)blockIdx.x * nacc;
     for (int i = tid; i < nacc; i += WBLOCK) row[i] = acc[i];
@@ -305,6 +496,7 @@ __global__ __launch_bounds__(WBLOCK) void wide_reduce(WState* __restrict__ st) {
     }
     if (emp) atomicAdd(&sempty, emp);
     __syncthreads();
+    key_tables(st->mu32, K, d, DS, st->hh, st->amax, reinterpret_cast<uint32_t*>(sw));
     const double E = ordered_sum(K, [&](int k) { return se[k]; }, sw);
     __syncthreads();
     const double* jp = st->jpart;
@@ -334,12 +526,19 @@ __global__ __launch_bounds__(WBLOCK) void wide_label(WState* __restrict__ st,
     using S = WShape<D>;
     const int tid = threadIdx.x;
     const int d = st->d, K = st->K;
+    const int kp = wide_kpad(K);
     float* cm = reinterpret_cast<float*>(wsm);
-    const int G = scale_exponent(st->absmax_bits);
-    for (int i = tid; i < K * S::DS; i += WBLOCK) cm[i] = st->mu32[i];
+    float* hh = cm + (size_t)kp * S::DS;
+    float* amax = hh + ((kp + 3) & ~3);
+    int* wq = reinterpret_cast<int*>(amax + 36) + (tid >> 6) * WQCAP;
+    stage_tables<D>(st, K, cm, hh, amax);
     __syncthreads();
     double jl = 0.0;
-    wide_points<D, WMODE_LABEL>(st, cm, K, d, G, nullptr, labels, jl);
+    wide_points<D>(st, cm, hh, amax, K, d, wq,
+                   [&](const float (&)[D], int64_t i, int k, float dist) {
+        jl += (double)dist;
+        if (labels) labels[i] = k;
+    });
     const double jb = block_sum(jl, sw);
     if (tid == 0) {
         st_agent(&st->jpart[blockIdx.x], jb);
@@ -407,7 +606,7 @@ hipError_t launch_wide_reduce(WState* st, int d, int K, int grid_update, hipStre
 
 hipError_t launch_wide_label(WState* st, int32_t* labels, int d, int K, int grid,
                              hipStream_t s) {
-    const size_t lds = (size_t)K * wide_stride(wide_width(d)) * 4;
+    const size_t lds = wide_table_bytes(d, K);
     if (grid < 1 || grid > WMAX_GRID || d < 1 || d > WD_MAX || K < 1 || K > WK_MAX ||
         lds > (size_t)WLDS_MAX)
         return hipErrorInvalidValue;

@@ -47,10 +47,12 @@ def test_abi_version():
     ((100, 100, 1, 4, 1e-6, 10), km.KM_OK),
     ((100, 100, 3, 65, 1e-6, 10), km.KM_OK),
     ((2000, 2000, 3, 1024, 1e-6, 10), km.KM_OK),
-    ((2000, 2000, 16, 307, 1e-6, 10), km.KM_OK),
-    ((2000, 2000, 16, 308, 1e-6, 10), km.KM_EUNSUPPORTED),
-    ((2000, 2000, 32, 156, 1e-6, 10), km.KM_OK),
-    ((2000, 2000, 32, 157, 1e-6, 10), km.KM_EUNSUPPORTED),
+    ((2000, 2000, 16, 309, 1e-6, 10), km.KM_OK),
+    ((2000, 2000, 16, 310, 1e-6, 10), km.KM_EUNSUPPORTED),
+    ((2000, 2000, 32, 159, 1e-6, 10), km.KM_OK),
+    ((2000, 2000, 32, 160, 1e-6, 10), km.KM_EUNSUPPORTED),
+    ((2000, 2000, 8, 585, 1e-6, 10), km.KM_OK),
+    ((2000, 2000, 8, 586, 1e-6, 10), km.KM_EUNSUPPORTED),
     ((2000, 2000, 33, 2, 1e-6, 10), km.KM_EUNSUPPORTED),
     ((2000, 2000, 2, 1025, 1e-6, 10), km.KM_EUNSUPPORTED),
     ((100, 100, 0, 4, 1e-6, 10), km.KM_EINVAL),

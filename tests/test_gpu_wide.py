@@ -36,7 +36,7 @@ def mixture(N, d, K, seed):
 # --------------------------------------------------------------- reassignment
 @pytest.mark.parametrize("d,K,N", [
     (1, 70, 10_001), (2, 100, 50_003), (3, 1024, 30_001), (4, 65, 20_000), (5, 200, 40_007),
-    (8, 590, 20_003), (12, 300, 10_001), (16, 307, 25_001), (24, 207, 9_999), (32, 156, 12_345),
+    (8, 585, 20_003), (12, 300, 10_001), (16, 309, 25_001), (24, 210, 9_999), (32, 159, 12_345),
     (16, 3, 5), (7, 1, 1), (9, 128, 130)])
 def test_assign_matches_oracle(km, d, K, N):
     log(f"wide assign d={d} K={K} N={N}")
@@ -64,6 +64,21 @@ def test_exact_ties_go_to_the_lowest_index(km):
     assert (dsec == dmin).mean() > 0.1
     assert np.array_equal(lab.cpu().numpy(), ref)
     assert J == pytest.approx(dmin.sum(), rel=1e-12)
+
+
+def test_far_points_and_large_offsets(km):
+    """Data far from the origin and a sprinkle of far outliers in 8-D: the
+    keys are dominated by |m|^2 / 2 and m.x, and the direct form by |x|^2,
+    the regime where the certificate's bounds matter most."""
+    rng = np.random.default_rng(81)
+    d, N, K = 8, 150_001, 150
+    X = (rng.normal(size=(d, N)) * 3 + 1000.0).astype(np.float32)
+    X[:, ::97] += 5000.0
+    mu = rng.normal(size=(K, d)) * 3 + 1000.0
+    lab, J = km.assign(torch.from_numpy(X).cuda(), mu)
+    mism, near, _, dmin = label_check(lab.cpu().numpy(), X, mu)
+    assert abs(J - dmin.sum()) <= gap_for_dim(d) * dmin.sum()
+    log(f"  far/offset 8-D: mismatches vs oracle {mism} (near-ties {near})")
 
 
 # -------------------------------------------------------------- step parity
@@ -236,7 +251,7 @@ def test_error_paths(km):
     X = np.random.default_rng(0).normal(size=(16, 2000)).astype(np.float32)
     Xd = torch.from_numpy(X).cuda()
     with pytest.raises(KMeansError) as e:
-        km.fit(Xd, np.zeros((308, 16)))                  # K*(d+1) sums exceed one block's LDS
+        km.fit(Xd, np.zeros((310, 16)))                  # K*(d+1) sums exceed one block's LDS
     assert e.value.code == KM_EUNSUPPORTED
     X33 = torch.zeros((33, 100), dtype=torch.float32, device="cuda")
     with pytest.raises(KMeansError) as e:
