@@ -34,10 +34,11 @@
  *   - An empty cluster keeps its previous centre and is counted.
  *   - Supported shapes: 1 <= d <= 32, 1 <= K <= 1024, K <= N <= 2^31 - 1,
  *     where, outside d in {2, 3} with K <= 64, one block's tables must fit
- *     in LDS: 8*K*(d+1) (rounded up to 16) + 4*K*s + 32 <= 61440 bytes, s =
- *     the padded width (d for d <= 4; then 6, 8, 12, 16, 24 or 32) rounded
- *     up to a multiple of 4.  (d <= 4: K <= 1024; d = 8: K <= 590;
- *     d = 16: K <= 307; d = 32: K <= 156.)  d in {2, 3} with K <= 64 runs
+ *     in 64 KB of LDS: 8*K*(d+1) + 4*Kp*s + 4*Kp (the first and last rounded
+ *     up to 16) + 2224 <= 65536 bytes, Kp = K rounded up to a multiple of 3,
+ *     s = the padded width (d for d <= 4; then 6, 8, 12, 16, 24 or 32)
+ *     rounded up to a multiple of 4.  (d <= 4: K <= 1024; d = 8: K <= 585;
+ *     d = 16: K <= 309; d = 32: K <= 159.)  d in {2, 3} with K <= 64 runs
  *     the 2-D/3-D kernels, every other shape the general-shape kernels
  *     (same definitions, same results up to the objective's summation
  *     order).  kmeans_fit_batched: d in {2, 3}, K <= 32, N <= 2^27, up to 8
