@@ -186,7 +186,7 @@ __device__ void points_pass(const BInst& in, int rank, int S, int mask, int G, f
             float best[4];
             int arg[4];
             bool ok[4];
-            nearest4_cmp<D>(sm.scand[r], sm.smu[r], K, ntri, sm.sbnd[r], ninf, x, best, arg, ok);
+            nearest4<D>(sm.scand[r], sm.smu[r], K, ntri, sm.sbnd[r], ninf, x, best, arg, ok);
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
                 const float x2 = D == 3 ? x[D - 1][p] : 0.0f;

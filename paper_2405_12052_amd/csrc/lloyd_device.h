@@ -192,54 +192,6 @@ __device__ __forceinline__ void nearest4(const float4* __restrict__ scand,
     }
 }
 
-// The same certified scan with the winning triple tracked by a compare and a
-// select per triple, and both second-smallest candidates (across and within
-// triples) kept for every triple: seven compare-type instructions per triple
-// instead of four, but less work at the end and fewer live registers.  The
-// batched kernel, whose instances have few centres and whose restarts keep
-// many values live, is faster with this form.
-template <int D>
-__device__ __forceinline__ void nearest4_cmp(const float4* __restrict__ scand,
-                                         const float4* __restrict__ smu, int K, int ntri,
-                                         float4 bnd, float ninf, const float (&x)[D][4],
-                                         float (&best)[4], int (&arg)[4], bool (&ok)[4]) {
-    float m1[4], m2[4];
-    int tri[4];
-#pragma unroll
-    for (int p = 0; p < 4; ++p) { m1[p] = INFINITY; m2[p] = INFINITY; tri[p] = 0; }
-    for (int g = 0; g < ntri; ++g) {
-        const float4 r0 = scand[3 * g], r1 = scand[3 * g + 1], r2 = scand[3 * g + 2];
-#pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const float x2 = D == 3 ? x[D - 1][p] : 0.0f;
-            const float s0 = expanded_key<D>(x[0][p], x[1][p], x2, r0);
-            const float s1 = expanded_key<D>(x[0][p], x[1][p], x2, r1);
-            const float s2 = expanded_key<D>(x[0][p], x[1][p], x2, r2);
-            const float g1 = fminf(fminf(s0, s1), s2);
-            const float g2 = __builtin_amdgcn_fmed3f(s0, s1, s2);
-            m2[p] = __builtin_amdgcn_fmed3f(m1[p], g1, min2(m2[p], g2, ninf));
-            tri[p] = g1 < m1[p] ? g : tri[p];
-            m1[p] = min2(m1[p], g1, ninf);
-        }
-    }
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        const float x0 = x[0][p], x1 = x[1][p], x2 = D == 3 ? x[D - 1][p] : 0.0f;
-        // first index of the smallest key inside the winning triple
-        const int k0 = 3 * tri[p];
-        const float s0 = expanded_key<D>(x0, x1, x2, scand[k0]);
-        const float s1 = expanded_key<D>(x0, x1, x2, scand[k0 + 1]);
-        const int k = s0 == m1[p] ? k0 : (s1 == m1[p] ? k0 + 1 : k0 + 2);
-        // rounding bound of the keys of this point
-        float b = fmaf(bnd.y, fabsf(x0), bnd.x);
-        b = fmaf(bnd.z, fabsf(x1), b);
-        if constexpr (D == 3) b = fmaf(bnd.w, fabsf(x2), b);
-        ok[p] = m2[p] - m1[p] > b && k < K;
-        arg[p] = ok[p] ? k : 0;
-        best[p] = direct_dist<D>(x0, x1, x2, smu[arg[p]]);
-    }
-}
-
 // load_group with the alignment known only at run time (uniform branch).
 template <int D>
 __device__ __forceinline__ int load_group_rt(bool vec, const float* __restrict__ X, int64_t ld,
