@@ -238,8 +238,9 @@ __device__ __forceinline__ void scan_points(const float* __restrict__ X, int64_t
 // ---------------------------------------------------------------- lloyd_iter
 // LDS of one update.
 // The block's per-cluster accumulators in LDS: ACC_SLOTS int64 slots hold
-// `copies` = min(ACC_COPY_MAX, ACC_SLOTS / (K (d+1))) copies of the K (d+1)
-// sums and counts, and thread t adds to copy t % copies.  With few clusters
+// `copies` = min(ACC_COPY_MAX, ACC_SLOTS / (K (d+1))) copies of the K d sums
+// (the counts in a parallel 32-bit array: a block never counts 2^32 points),
+// and thread t adds to copy t % copies.  With few clusters
 // many lanes of a wave would add to the same slot, and LDS atomics on one
 // slot serialise; the copies spread them, and are summed once per pass.
 constexpr int ACC_SLOTS = 2 * KMAX * (DMAX + 1);
@@ -250,6 +251,7 @@ struct IterSmem {
     float4 smu[KMAX];
     // copy c at [c * K * (d+1)], coordinate-major inside: slot j * K + k
     unsigned long long sacc[ACC_SLOTS];
+    unsigned int scnt[ACC_SLOTS / 2];  // counts, 32-bit: copy c at [c * K], slot k
     unsigned long long stot[KMAX * (DMAX + 1)];
     float4 squeue[NW][QCAP];
     double sred[NW];
@@ -307,10 +309,12 @@ __device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm
     const int KR = K * R;
     const int copies = ACC_SLOTS / KR < ACC_COPY_MAX ? ACC_SLOTS / KR : ACC_COPY_MAX;
     for (int i = tid; i < copies * KR; i += BLOCK) sm.sacc[i] = 0ull;
+    for (int i = tid; i < copies * K; i += BLOCK) sm.scnt[i] = 0u;
     __syncthreads();
 
     double jl = 0.0;
     unsigned long long* myacc = &sm.sacc[(tid % copies) * KR];
+    unsigned int* mycnt = &sm.scnt[(tid % copies) * K];
     scan_points<D, VEC, KT>(X, ld, N, sm.scand, sm.smu, K, ntri, bnd, ninf, sm.squeue[w],
                             [&](int64_t, float x0, float x1, float x2, int k, float dist) {
         // coordinate-major slots [j * K + k]: the 64 lanes' clusters spread
@@ -324,7 +328,7 @@ __device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm
             __hip_atomic_fetch_add(&a[j * K], (unsigned long long)q, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
         }
-        __hip_atomic_fetch_add(&a[D * K], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(&mycnt[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         jl += (double)dist;
     });
     jl = wave_sum(jl);
@@ -333,7 +337,10 @@ __device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm
     for (int i = tid; i < K * R; i += BLOCK) {  // block totals, cluster-major [k * R + j]
         const int k = i / R, j = i - k * R;
         unsigned long long s = 0ull;
-        for (int c = 0; c < copies; ++c) s += sm.sacc[c * KR + j * K + k];
+        if (j < D)
+            for (int c = 0; c < copies; ++c) s += sm.sacc[c * KR + j * K + k];
+        else
+            for (int c = 0; c < copies; ++c) s += sm.scnt[c * K + k];
         sm.stot[i] = s;
     }
     double jb = 0.0;
