@@ -255,10 +255,11 @@ __device__ __forceinline__ void wide_points(const WState* __restrict__ st, const
 // Key tables of the float32 centres mu32 (K rows of stride DS): hh[k] =
 // -fl32(sum_j m_kj^2) / 2 (the sum of squares in float64 FMAs, rounded
 // once), pads up to a whole triple -2^127; amax[j] = max_k |m_kj| (j < d),
-// amax[WD_MAX] = max_k fl32(sum_j m_kj^2).  Whole block.
+// amax[WD_MAX] = max_k fl32(sum_j m_kj^2).  Whole block; sred: LDS scratch of
+// NW * (WD_MAX + 1) words.
 __device__ void key_tables(const float* __restrict__ mu32, int K, int d, int DS,
                            float* __restrict__ hh, float* __restrict__ amax, uint32_t* sred) {
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, w = tid >> 6;
     const int kp = wide_kpad(K);
     uint32_t cmx = 0;
     for (int k = tid; k < kp; k += WBLOCK) {
@@ -275,26 +276,26 @@ __device__ void key_tables(const float* __restrict__ mu32, int K, int d, int DS,
             hh[k] = -0x1p127f;
         }
     }
-    for (int j = -1; j < d; ++j) {
+    // per-wave maxima (non-negative floats order as their bits), then across
+    // the waves: one barrier
+    cmx = wave_max(cmx);
+    if ((tid & 63) == 0) sred[w * (WD_MAX + 1) + WD_MAX] = cmx;
+    for (int j = 0; j < d; ++j) {
         uint32_t m = 0;
-        if (j < 0) {
-            m = cmx;
-        } else {
-            for (int k = tid; k < K; k += WBLOCK) {
-                const uint32_t b = __float_as_uint(mu32[k * DS + j]) & 0x7fffffffu;
-                m = b > m ? b : m;
-            }
+        for (int k = tid; k < K; k += WBLOCK) {
+            const uint32_t b = __float_as_uint(mu32[k * DS + j]) & 0x7fffffffu;
+            m = b > m ? b : m;
         }
         m = wave_max(m);
-        if ((tid & 63) == 0) sred[tid >> 6] = m;
-        __syncthreads();
-        if (tid == 0) {
-            uint32_t r = 0;
-            for (int w = 0; w < NW; ++w) r = sred[w] > r ? sred[w] : r;
-            amax[j < 0 ? WD_MAX : j] = __uint_as_float(r);
-        }
-        __syncthreads();
+        if ((tid & 63) == 0) sred[w * (WD_MAX + 1) + j] = m;
     }
+    __syncthreads();
+    if (tid <= WD_MAX && (tid < d || tid == WD_MAX)) {
+        uint32_t r = 0;
+        for (int v = 0; v < NW; ++v) r = sred[v * (WD_MAX + 1) + tid] > r ? sred[v * (WD_MAX + 1) + tid] : r;
+        amax[tid] = __uint_as_float(r);
+    }
+    __syncthreads();
 }
 
 // Stage the centres, key constants and bound coefficients in LDS.
@@ -346,7 +347,7 @@ __device__ __forceinline__ double ordered_sum(int n, F v, double* sw) {
 // the fit), zeroed totals, and (block 0) the key tables of the initial
 // centres.
 __global__ __launch_bounds__(WBLOCK) void wide_scan(WState* __restrict__ st) {
-    __shared__ uint32_t sred[NW];
+    __shared__ uint32_t sred[NW * (WD_MAX + 1)];
     const int tid = threadIdx.x;
     if (blockIdx.x == 0)
         key_tables(st->mu32, st->K, st->d, wide_stride(wide_width(st->d)), st->hh, st->amax, sred);
@@ -422,6 +423,7 @@ __global__ __launch_bounds__(WBLOCK) void wide_update(WState* __restrict__ st) {
 __global__ __launch_bounds__(WBLOCK) void wide_reduce(WState* __restrict__ st) {
     extern __shared__ __align__(16) unsigned char wsm[];
     __shared__ double sw[64];
+    __shared__ uint32_t sred[NW * (WD_MAX + 1)];
     __shared__ int sflag;
     __shared__ int sempty;
     if (st->done) return;
@@ -496,7 +498,7 @@ __global__ __launch_bounds__(WBLOCK) void wide_reduce(WState* __restrict__ st) {
     }
     if (emp) atomicAdd(&sempty, emp);
     __syncthreads();
-    key_tables(st->mu32, K, d, DS, st->hh, st->amax, reinterpret_cast<uint32_t*>(sw));
+    key_tables(st->mu32, K, d, DS, st->hh, st->amax, sred);
     const double E = ordered_sum(K, [&](int k) { return se[k]; }, sw);
     __syncthreads();
     const double* jp = st->jpart;
