@@ -241,8 +241,11 @@ int kmeans_get_batched_schedule(kmeans_ctx *ctx, km_schedule *s);
 
 /*
  * Autotuner of the batched schedule: times kmeans_fit_batched on `inst`
- * (typically a sample of the workload) for each candidate schedule (team
- * size, grid occupancy, team threshold), keeps the fastest on the context and
+ * (the workload itself, or a sample of it: the end of a launch, when the last
+ * large instances run on single blocks, depends on the number of instances
+ * per block, so a small sample can mislead) for each candidate schedule (team
+ * size 1, 4, 8, 16; teams for the top 30/50/70/90 % of instances by N*K*R;
+ * 2-4 blocks per compute unit), keeps the fastest on the context and
  * writes it to *best (may be NULL).  If cache_path is not NULL the result is
  * looked up first and stored afterwards in that JSON file, keyed by a coarse
  * signature of the batch (restarts, d mix, K and N ranges).  Results of the
