@@ -101,12 +101,11 @@ enum km_option {
                              (FP32 MFMA; slower on gfx950, kept selectable).
                              Labels, centres, E and T do not depend on it.     */
     KM_OPT_PERSIST = 6,   /* how kmeans_fit runs its updates: 0 (default)
-                             automatic (one persistent cooperative launch for
-                             2^22 <= N <= 2^24 with the VALU scan, else graph
-                             replays of one launch per update), 1 always one
-                             launch per update, 2 persistent whenever the VALU
-                             scan is used and the grid fits on the device.
-                             Results do not depend on it.                      */
+                             and 1: graph replays of one launch per update
+                             (measured as fast or faster at every size); 2:
+                             one persistent cooperative launch whenever the
+                             VALU scan is used and the grid fits on the
+                             device.  Results do not depend on it.             */
     KM_OPT_WIDE = 7       /* 1: run kmeans_fit and kmeans_assign on the
                              general-shape kernels for every shape (a cross-
                              check of the two implementations); 0 (default):

@@ -116,16 +116,27 @@ bool vec_ok(const float* X, int64_t ld) {
     return (reinterpret_cast<uintptr_t>(X) & 15u) == 0 && (ld & 3) == 0;
 }
 
-// Grid of the per-update kernels: enough blocks for one group of 4 points
-// per thread, at most 16 per compute unit.  About 5 blocks per compute unit
-// are resident at K = 64 (LDS-limited); at N = 2e8 a grid of 16 per unit
-// measured 5 % faster per update than 8 per unit, and 8 faster than 5.
+// Grid of the per-update kernels: about one block per 8192 points, at least
+// 2 and at most 16 per compute unit, and never more blocks than groups of 4
+// points per thread.  Each block has a fixed cost per update (staging the
+// centre tables, clearing its accumulators, its partial and its share of the
+// reduction), so blocks with few points lose: measured per update at K = 16,
+// N = 4e6: 512 blocks 37.2 us, 3907 blocks 46.9 us; N = 1e7: 1024 blocks
+// 52.9 us, 4096 blocks 64.7 us; at N = 2e8, K = 64 the 16 per unit cap
+// (4096 blocks) is best.
 int grid_for(kmeans_ctx* c, int64_t N) {
     const int64_t groups = (N + 3) / 4;
     const int64_t need = (groups + km::BLOCK - 1) / km::BLOCK;
-    int64_t cap = c->blocks > 0 ? c->blocks : (int64_t)c->n_cu * 16;
+    int64_t cap;
+    if (c->blocks > 0) {
+        cap = c->blocks;
+    } else {
+        const int64_t lo = (int64_t)c->n_cu * 2, hi = (int64_t)c->n_cu * 16;
+        const int64_t want = (N + 8191) / 8192;
+        cap = want < lo ? lo : (want > hi ? hi : want);
+    }
     if (cap > km::MAX_BLOCKS) cap = km::MAX_BLOCKS;
-    int64_t g = need < cap ? need : cap;
+    const int64_t g = need < cap ? need : cap;
     return (int)(g < 1 ? 1 : g);
 }
 
@@ -208,16 +219,15 @@ int run_iterations(kmeans_ctx* c, int d, bool vec, int keys, int grid, int n_ite
 // (measured: no co-execution cycles), so the matrix-core scan pays its MFMA
 // time on top of its remaining VALU work and is slower at K = 64 (2.44 ms vs
 // 2.00 ms per update at N = 2e8).  It stays selectable.
-// Persistent fit: selected (KM_OPT_PERSIST = 2), or automatically with the
-// VALU scan for 2^22 <= N <= 2^24.  Measured per update (K = 16): below 2^22
-// the launch per update is as fast or faster (15 vs 17 us at N = 1e5, 25 vs
-// 27 us at 1e6: both are bound by the same chain of device-wide round trips
-// of the reduction, not by the launches); from 4e6 to 1e7 the persistent fit
-// is 3-5 % faster; above 2^24 the two are equal within noise.
+// Persistent fit: only when selected (KM_OPT_PERSIST = 2).  With the grid
+// of grid_for, the launch per update is as fast or faster at every size
+// measured (K = 16, per update: N = 1e6 22.3 vs 26.0 us, 4e6 37.3 vs 41.0 us,
+// 1e7 58.8 vs 60.1 us, 1.6e7 82.6 vs 83.1 us, 4e7 181 vs 184 us): both are
+// bound by the same chain of device-wide round trips of the reduction, and
+// the persistent fit adds a grid-wide wait per update.
 bool use_persist(kmeans_ctx* c, int64_t N, int keys) {
-    if (keys != 0 || c->persist == 1) return false;
-    if (c->persist == 2) return true;
-    return N >= (1LL << 22) && N <= (1LL << 24);
+    (void)N;
+    return keys == 0 && c->persist == 2;
 }
 
 int scan_keys(kmeans_ctx* c, int K) {
