@@ -106,10 +106,15 @@ __device__ __forceinline__ double sum_in_order(int n, const double* p, double* s
     return s;
 }
 
+// Partials handled by the last block alone when it can load them in two
+// batches per thread (one-level reduction).
+constexpr int ONE_LEVEL_LOADS = 16 * BLOCK;
+
 // Two-level reduction of the block partials (integer sums | counts, and the
 // objective).  Every block publishes its partial; the last block of each
 // group of GROUP blocks adds the group's partials; the last group adds the
-// group sums.  Returns true in that one final block, with the grid totals in
+// group sums.  With at most MAX_GROUPS blocks and ONE_LEVEL_LOADS partial
+// entries in all, the last block of the grid adds the partials directly.  Returns true in that one final block, with the grid totals in
 // tot[0..nr) (LDS) and the objective in *jtot.  No two blocks add to the same
 // address, so there is no contention; the integer sums are exact in any order
 // and the objective is added in block, then group, order.  Partials move as
@@ -126,6 +131,27 @@ __device__ __forceinline__ bool reduce_grid(State* __restrict__ st, const unsign
     if (tid == 0) st_agent(&st->jpart[b], jb);
     wait_mem();
     __syncthreads();
+    if (nb <= MAX_GROUPS && nb * nr <= ONE_LEVEL_LOADS) {
+        // few partials: the last block of the grid adds them all (one round
+        // trip of device-coherent exchanges fewer)
+        if (tid == 0) {
+            const uint32_t old = __hip_atomic_fetch_add(&st->ticket, 1u, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+            *sflag = (old == (uint32_t)nb - 1);
+        }
+        __syncthreads();
+        if (!*sflag) return false;
+        const unsigned long long* part = st->part;
+        sum_entries(nb, nr, [&](int q, int i) { return ld_agent(&part[(size_t)q * PART + i]); },
+                    tot, scr);
+        const double jt = sum_in_order(nb, st->jpart, sj);
+        if (tid == 0) {
+            *jtot = jt;
+            st_agent(&st->ticket, 0u);
+        }
+        __syncthreads();
+        return true;
+    }
     const int grp = b / GROUP, g0 = grp * GROUP;
     const int gn = (nb - g0) < GROUP ? (nb - g0) : GROUP;
     if (tid == 0) {
