@@ -26,12 +26,15 @@
  *   - Reassignment compares squared distances to the centres rounded to
  *     float32.  A point whose nearest centre wins by more than the rounding
  *     of the computation (a certified bound) gets that centre; near-ties are
- *     decided by the float32 direct form (x0-m0)^2 + (x1-m1)^2 + ... +
- *     (x_{d-1}-m_{d-1})^2, left to right (the first term a product, the
- *     others fused multiply-adds), first index of the minimum.  (The
- *     general-shape kernels' bound also covers the direct form's rounding,
- *     so their labels are exactly the direct form's argmin.)  The objective
- *     sums the direct-form distances to the chosen centres in float64.
+ *     decided by the direct form (x0-m0)^2 + (x1-m1)^2 + ... +
+ *     (x_{d-1}-m_{d-1})^2 evaluated in float64 (each difference, square and
+ *     partial sum rounded to float64, left to right), first index of the
+ *     minimum.  A certified margin is far above float64 rounding, so every
+ *     label is the first-index minimum of that float64 distance, whichever
+ *     scan (KM_OPT_KEYS, KM_OPT_WIDE) ran and whichever points it certified.
+ *     The objective sums, in float64, the float32 direct-form distances
+ *     (left to right, the first term a product, the others fused
+ *     multiply-adds) to the chosen centres.
  *     Per-cluster sums are exact integer sums of the points on a 2^-G grid,
  *     G chosen from max|x| so that every |x|*2^G < 2^30; the divide, E and the
  *     tolerance test are float64.  Results do not depend on the launch

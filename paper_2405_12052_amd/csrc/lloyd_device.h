@@ -11,9 +11,9 @@
 // the two smallest differ by more than b(x), the first index attaining the
 // smallest s is the exact argmin of the squared distance to the float32
 // centres.  Otherwise (points within b(x) of a tie) the point is re-scanned
-// with the direct form (x0-m0)^2 + (x1-m1)^2 [+ (x2-m2)^2] in float32, first
-// index of the minimum.  The distance reported (objective) is always the
-// direct form to the chosen centre.
+// with the direct form (x0-m0)^2 + (x1-m1)^2 [+ (x2-m2)^2] evaluated in
+// float64, first index of the minimum.  The distance reported (objective) is
+// always the float32 direct form to the chosen centre.
 #pragma once
 
 #include "km_internal.h"
@@ -199,17 +199,39 @@ __device__ __forceinline__ int load_group_rt(bool vec, const float* __restrict__
     return vec ? load_group<D, true>(X, ld, N, g, x) : load_group<D, false>(X, ld, N, g, x);
 }
 
-// Direct-form scan of one point over all K centres: first index of the
-// minimum of the float32 squared distance (the near-tie path).
+// Squared distance evaluated in float64: each coordinate's difference,
+// square and the running sum rounded to float64, left to right (no fused
+// operations).
+template <int D>
+__device__ __forceinline__ double direct_dist64(float x0, float x1, float x2, float4 c) {
+    const double d0 = (double)x0 - (double)c.x;
+    const double d1 = (double)x1 - (double)c.y;
+    double s = __dadd_rn(__dmul_rn(d0, d0), __dmul_rn(d1, d1));
+    if constexpr (D == 3) {
+        const double d2 = (double)x2 - (double)c.z;
+        s = __dadd_rn(s, __dmul_rn(d2, d2));
+    }
+    return s;
+}
+
+// Near-tie scan of one point over all K centres: first index of the minimum
+// of the float64 squared distance (a certified winner is also that minimum,
+// its margin being far above float64 rounding, so labels do not depend on
+// which points were certified).  bd: the float32 direct-form distance to
+// the chosen centre (the objective's term).
 template <int D>
 __device__ __forceinline__ void direct_scan(const float4* __restrict__ smu, int K, float x0,
                                             float x1, float x2, float& bd, int& bk) {
-    bd = INFINITY;
+    double best = INFINITY;
     bk = 0;
+    // rare path: kept rolled, so that its float64 registers do not set the
+    // register budget of the kernels that inline it
+#pragma unroll 1
     for (int q = 0; q < K; ++q) {
-        const float dq = direct_dist<D>(x0, x1, x2, smu[q]);
-        if (dq < bd) { bd = dq; bk = q; }
+        const double dq = direct_dist64<D>(x0, x1, x2, smu[q]);
+        if (dq < best) { best = dq; bk = q; }
     }
+    bd = direct_dist<D>(x0, x1, x2, smu[bk]);
 }
 
 // Reassignment of every point of the grid-stride share of this thread.
@@ -282,13 +304,19 @@ __device__ __forceinline__ void assign_points(const float* __restrict__ X, int64
 
 // Centre tables for the reassignment: records {-2 m, fl32(|m|^2)} padded to
 // whole triples with {0, 0, 0, 2^127}, and the bound coefficients
-//   b(x) = 2^-20 (Cmax + 2 sum_j A_j |x_j|),  Cmax = max_k c_k, A_j = max_k |m_kj|,
-// which exceeds twice the rounding error of any key (<= 4.01 u (Cmax + 2 sum_j
-// A_j |x_j|), u = 2^-24: the rounding of c_k and of three FMAs).  Written to
-// cand[0 .. 3*ceil(K/3)) and *bnd (global or LDS).  Called by one whole block;
-// sc and sa are LDS scratch of KPAD and 3*KPAD floats.
+//   b(x) = 2^-20 (Cmax + 2 sum_j A_j |x_j|) + 2^-46 xmax sum_j |x_j|,
+//   Cmax = max_k c_k, A_j = max_k |m_kj|, xmax = max |x| over the data
+// (xmax_bits).  The first part exceeds twice the rounding error of any key
+// (<= 4.01 u (Cmax + 2 sum_j A_j |x_j|), u = 2^-24: the rounding of c_k and of
+// three FMAs).  The second covers the float64 evaluation of the direct form
+// used for near-ties: two distances D err by at most 2 (d + 2) 2^-53 D, D <=
+// |x|^2 + |key|, below 2^-49 (|x|^2 + |key|); the key part lies far inside
+// the first term and |x|^2 <= xmax sum_j |x_j|.  A certified winner is
+// therefore also the first-index minimum of the float64 direct form.
+// Written to cand[0 .. 3*ceil(K/3)) and *bnd (global or LDS).  Called by one
+// whole block; sc and sa are LDS scratch of KPAD and 3*KPAD floats.
 __device__ inline void prep_centres(const float4* m32, int K, float4* cand, float4* bnd,
-                                    float* sc, float* sa) {
+                                    float* sc, float* sa, uint32_t xmax_bits) {
     const int tid = threadIdx.x;
     const int ntri = (K + 2) / 3;
     if (tid < 3 * ntri) {
@@ -316,7 +344,9 @@ __device__ inline void prep_centres(const float4* m32, int K, float4* cand, floa
             cm = fmaxf(cm, sc[k]);
             am0 = fmaxf(am0, sa[3 * k]); am1 = fmaxf(am1, sa[3 * k + 1]); am2 = fmaxf(am2, sa[3 * k + 2]);
         }
-        *bnd = make_float4(ldexpf(cm, -20), ldexpf(am0, -19), ldexpf(am1, -19), ldexpf(am2, -19));
+        const float e = 0x1p-46f * __uint_as_float(xmax_bits);
+        *bnd = make_float4(ldexpf(cm, -20), ldexpf(am0, -19) + e, ldexpf(am1, -19) + e,
+                           ldexpf(am2, -19) + e);
     }
     __syncthreads();
 }

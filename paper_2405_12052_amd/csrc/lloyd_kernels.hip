@@ -232,10 +232,10 @@ __global__ __launch_bounds__(BLOCK) void km_scan(State* __restrict__ st) {
     }
     __syncthreads();
     if (!slast) return;
-    prep_centres(st->mu32, st->K, st->cand, &st->bnd, sc, sa);
+    const uint32_t a = ld_agent(&st->absmax_bits);
+    prep_centres(st->mu32, st->K, st->cand, &st->bnd, sc, sa, a);
     for (int i = tid; i < MAX_GROUPS; i += BLOCK) st->gticket[i] = 0u;
     if (tid == 0) {
-        const uint32_t a = ld_agent(&st->absmax_bits);
         st->G = scale_exponent(a);
         if (a >= 0x7f800000u) {  // NaN or infinity in X
             st->flags |= FLAG_NONFINITE;
@@ -253,12 +253,12 @@ template <int D, bool VEC, int KT, typename Sink>
 __device__ __forceinline__ void scan_points(const float* __restrict__ X, int64_t ld, int64_t N,
                                             const float4* __restrict__ scand,
                                             const float4* __restrict__ smu, int K, int ntri,
-                                            float4 bnd, float ninf, float4* __restrict__ wq,
-                                            Sink&& sink) {
+                                            float4 bnd, float ninf, int G,
+                                            float4* __restrict__ wq, Sink&& sink) {
     if constexpr (KT == 0)
         assign_points<D, VEC>(X, ld, N, scand, smu, K, ntri, bnd, ninf, wq, sink);
     else
-        assign_points_mfma<D, VEC, KT>(X, ld, N, scand, smu, K, bnd, ninf, wq, sink);
+        assign_points_mfma<D, VEC, KT>(X, ld, N, scand, smu, K, bnd, ninf, G, wq, sink);
 }
 
 // ---------------------------------------------------------------- lloyd_iter
@@ -341,7 +341,7 @@ __device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm
     double jl = 0.0;
     unsigned long long* myacc = &sm.sacc[(tid % copies) * KR];
     unsigned int* mycnt = &sm.scnt[(tid % copies) * K];
-    scan_points<D, VEC, KT>(X, ld, N, sm.scand, sm.smu, K, ntri, bnd, ninf, sm.squeue[w],
+    scan_points<D, VEC, KT>(X, ld, N, sm.scand, sm.smu, K, ntri, bnd, ninf, G, sm.squeue[w],
                             [&](int64_t, float x0, float x1, float x2, int k, float dist) {
         // coordinate-major slots [j * K + k]: the 64 lanes' clusters spread
         // over the LDS banks (a cluster-major stride of 4 int64 would put
@@ -409,7 +409,7 @@ __device__ __forceinline__ void finalize_update(State* __restrict__ st, IterSmem
         sm.sEmpty[k] = cnt == 0ull;
     }
     __syncthreads();
-    prep_centres(sm.smu, K, sm.scand, &sm.sbnd, sm.sc, sm.sa);
+    prep_centres(sm.smu, K, sm.scand, &sm.sbnd, sm.sc, sm.sa, st->absmax_bits);
     const int ntri = (K + 2) / 3;
     for (int i = tid; i < 3 * ntri; i += BLOCK) wr4<COH>(&st->cand[i], sm.scand[i]);
     if (tid == 0) {
@@ -432,7 +432,7 @@ __device__ __forceinline__ void finalize_update(State* __restrict__ st, IterSmem
 // One update per launch (replayed from a graph): the update's pass, then the
 // final block's update of the centres.
 template <int D, bool VEC, int KT>
-__global__ __launch_bounds__(BLOCK) void lloyd_iter(State* __restrict__ st) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) void lloyd_iter(State* __restrict__ st) {
     if (st->done) return;
     __shared__ IterSmem sm;
     const int K = st->K;
@@ -506,7 +506,7 @@ __global__ __launch_bounds__(BLOCK) void lloyd_persist(State* __restrict__ st) {
 
 // ---------------------------------------------------------------- lloyd_label
 template <int D, bool VEC, int KT>
-__global__ __launch_bounds__(BLOCK) void lloyd_label(State* __restrict__ st,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) void lloyd_label(State* __restrict__ st,
                                                      int32_t* __restrict__ labels) {
     if (st->flags & FLAG_NONFINITE) return;
     __shared__ float4 scand[KPAD];
@@ -523,7 +523,7 @@ __global__ __launch_bounds__(BLOCK) void lloyd_label(State* __restrict__ st,
     const int ntri = stage_centres(st, K, scand, smu);
     __syncthreads();
     double jl = 0.0;
-    scan_points<D, VEC, KT>(X, ld, N, scand, smu, K, ntri, bnd, ninf, squeue[w],
+    scan_points<D, VEC, KT>(X, ld, N, scand, smu, K, ntri, bnd, ninf, st->G, squeue[w],
                             [&](int64_t i, float, float, float, int k, float dist) {
         if (labels) labels[i] = k;
         jl += (double)dist;

@@ -2,14 +2,17 @@
 // (up to WK_MAX), see wide.h.
 //
 // Reassignment (the paper's argmin of the squared Euclidean distance): every
-// point is compared with every centre in the direct form
-//   s_k = (x_0 - m_k0)^2 + (x_1 - m_k1)^2 + ... + (x_{d-1} - m_k,d-1)^2
-// in float32, left to right, the first term a product and the others fused
-// multiply-adds -- the same expression, in the same order, as the direct
-// form of the 2-D/3-D kernels -- and the first k attaining the minimum wins.
-// Each lane holds P consecutive points in registers; the float32 centres sit
-// in LDS and are read as wave-uniform (broadcast) float4s, each serving the
-// P points of every lane.
+// point is scored against every centre with the key m_k . x - |m_k|^2 / 2
+// (d fused multiply-adds; the largest key is the nearest centre), in triples
+// of centres whose best key carries the triple's number in its low bits.  A
+// rounding bound on both keys of the top pair and on the float32 direct form
+// (x_0 - m_k0)^2 + ... + (x_{d-1} - m_k,d-1)^2 certifies the winner when the
+// gap exceeds it; the other points are queued per wave and re-scanned with
+// the direct form evaluated in float64, first index of the minimum (the same
+// near-tie rule as the 2-D/3-D kernels, so both give the same labels).  Each
+// lane holds P consecutive points in registers; the float32 centres sit in
+// LDS and are read as wave-uniform (broadcast) float4s, each serving the P
+// points of every lane.
 //
 // Mean step: the points' coordinates as integers rint(x * 2^G) (|x| * 2^G <
 // 2^30) and a count of one are added to their cluster's int64 slots in LDS
@@ -84,6 +87,27 @@ __device__ __forceinline__ float wide_direct(const float (&x)[D], const float4* 
     return s;
 }
 
+// The same distance evaluated in float64 (differences, squares and the
+// running sum each rounded to float64, left to right): the near-tie rule.
+template <int D>
+__device__ __forceinline__ double wide_direct64(const float (&x)[D], const float4* __restrict__ c) {
+    double s = 0.0;
+#pragma unroll
+    for (int b = 0; b < (D + 3) / 4; ++b) {
+        const float4 m = c[b];
+        const float mv[4] = {m.x, m.y, m.z, m.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = 4 * b + u;
+            if (j < D) {
+                const double t = (double)x[j] - (double)mv[u];
+                s = j == 0 ? __dmul_rn(t, t) : __dadd_rn(s, __dmul_rn(t, t));
+            }
+        }
+    }
+    return s;
+}
+
 // Reassignment of this thread's grid-stride share of the points against the
 // K centres cm (LDS, Kpad rows of stride DS, zero padded) with the key
 // constants hh and the bound coefficients amax (see the file header).
@@ -118,13 +142,14 @@ __device__ __forceinline__ void wide_points(const WState* __restrict__ st, const
             float xr[D];
 #pragma unroll
             for (int j = 0; j < D; ++j) xr[j] = j < d ? X[(int64_t)j * ld + i] : 0.0f;
-            float bd = INFINITY;
+            double bq = INFINITY;
             int bk = 0;
+#pragma unroll 1
             for (int k = 0; k < K; ++k) {
-                const float dk = wide_direct<D>(xr, cm4 + k * NB);
-                if (dk < bd) { bd = dk; bk = k; }
+                const double dk = wide_direct64<D>(xr, cm4 + k * NB);
+                if (dk < bq) { bq = dk; bk = k; }
             }
-            sink(xr, i, bk, bd);
+            sink(xr, i, bk, wide_direct<D>(xr, cm4 + bk * NB));
         }
         __builtin_amdgcn_wave_barrier();
         qn -= cnt;

@@ -109,3 +109,25 @@ def test_unaligned_rows_identical_across_scans(km):
     assert a.iters == b.iters
     assert np.array_equal(a.centroids, b.centroids)
     assert np.array_equal(a.labels.cpu().numpy(), b.labels.cpu().numpy())
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("xs,ms", [(1e-15, 1e-15), (1e-3, 1e-3), (1e4, 1e4), (1e15, 1e15),
+                                   (1.0, 1e6), (1e6, 1.0), (1.0, 0.0)])
+def test_scales_identical_across_scans(km, d, xs, ms):
+    """Data and centres at extreme magnitudes, and centres far larger or
+    smaller than the data: the matrix-core scan scales both operands by
+    powers of two before splitting them, and must still certify only exact
+    winners (ms = 0: every centre at the origin, all keys tie)."""
+    rng = np.random.default_rng(90 + d)
+    N, K = 60_001, 64
+    X = (rng.normal(size=(d, N)) * xs).astype(np.float32)
+    mu = rng.normal(size=(K, d)) * ms
+    log(f"  scales d={d} data {xs:g} centres {ms:g}")
+    Xd = torch.from_numpy(X).cuda()
+    (la, Ja), (lb, Jb) = both(km, lambda: km.assign(Xd, mu))
+    a, b = la.cpu().numpy(), lb.cpu().numpy()
+    assert np.array_equal(a, b)
+    mism, near, _, _ = label_check(b, X, mu, N)
+    log(f"    mismatches vs oracle {mism} (near-ties {near})")
+    assert Jb == pytest.approx(Ja, rel=1e-12)
