@@ -116,10 +116,13 @@ def test_fit_end_to_end(km, name, kw):
         assert abs(r.objective - ref["J"]) <= 1e-6 * ref["J"]
         assert r.empty_events == ref["empty_events"]
     except AssertionError:
-        # Trajectories may part at an excused near-tie; then the first step
-        # where they part must show a label flip inside the near-tie window.
-        t = first_divergence(km, X, Xd, mu0, max(r.iters, ref["T"]))
-        log(f"{name}: trajectories part at update {t}: an excused near-tie flip")
+        # The trajectories may part when the rounding of the sums (a 2^-G grid
+        # on the GPU, compensated float64 in the oracle) moves a centre across
+        # a near-tie of a later update.  Then every update, started from the
+        # GPU's own previous centres, must still match the oracle's update
+        # from those centres: identical labels, centres within tolerance.
+        stepwise_check(km, X, Xd, mu0, max(r.iters, ref["T"]))
+        log(f"{name}: trajectories part; every update matches the oracle's from the same centres")
         return
     label_check(r.labels.cpu().numpy(), X, r.centroids)
     Eh, Jh = km.history()
@@ -128,23 +131,16 @@ def test_fit_end_to_end(km, name, kw):
     assert np.all(np.abs(Jh - ref["J_hist"]) <= 1e-6 * ref["J_hist"])
 
 
-def first_divergence(km, X, Xd, mu0, T):
-    """First update t whose GPU centres leave the oracle's tolerance when both
-    start from the same mu^{t-1}; asserts the step had an excused label flip."""
-    mu_ref = mu0
+def stepwise_check(km, X, Xd, mu0, T):
+    """Updates 1..T of the GPU fit, each against the oracle's update from the
+    GPU's previous centres: identical labels, centres within tolerance."""
     for t in range(1, T + 1):
         g = km.fit(Xd, mu0, tol=0.0, max_iter=t, labels=False).centroids
         prev = km.fit(Xd, mu0, tol=0.0, max_iter=t - 1, labels=False).centroids if t > 1 else mu0
         o = oracle.step(X, prev)
-        try:
-            centre_check(g, o["mu"])
-        except AssertionError:
-            lab, _ = km.assign(Xd, prev)
-            mism, _, _, _ = label_check(lab.cpu().numpy(), X, prev)
-            assert mism > 0, f"update {t} differs without a label flip"
-            return t
-        mu_ref = o["mu"]
-    raise AssertionError("results differ but no step diverges")
+        lab, _ = km.assign(Xd, prev)
+        label_check(lab.cpu().numpy(), X, prev)
+        centre_check(g, o["mu"])
 
 
 # -------------------------------------------------------------- determinism
