@@ -106,8 +106,10 @@ enum km_option {
     KM_OPT_KEYS = 5,      /* how the reassignment scan forms its keys
                              |m|^2 - 2 m.x: 0 (default) automatic (currently
                              the vector ALUs), 1 vector ALUs, 2 matrix cores
-                             (FP32 MFMA; slower on gfx950, kept selectable).
-                             Labels, centres, E and T do not depend on it.     */
+                             (one fp16 MFMA per 32 x 32 keys on hi/lo pieces
+                             of the operands; slower on gfx950, kept
+                             selectable).  Labels, centres, E and T do not
+                             depend on it.                                      */
     KM_OPT_PERSIST = 6,   /* how kmeans_fit runs its updates: 0 (default)
                              and 1: graph replays of one launch per update
                              (measured as fast or faster at every size); 2:
