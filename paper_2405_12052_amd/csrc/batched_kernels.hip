@@ -110,7 +110,6 @@ template <int D, int MODE>
 __device__ void points_pass(const BInst& in, int rank, int S, int mask, int G, float ninf,
                             BSmem& sm, double& jl) {
     const int K = in.K;
-    const int ntri = (K + 2) / 3;
     const int64_t N = in.N, ld = in.ld;
     const float* __restrict__ X = in.X;
     const bool vec = in.vec != 0;
@@ -186,7 +185,7 @@ __device__ void points_pass(const BInst& in, int rank, int S, int mask, int G, f
             float best[4];
             int arg[4];
             bool ok[4];
-            nearest4<D>(sm.scand[r], sm.smu[r], K, ntri, sm.sbnd[r], ninf, x, best, arg, ok);
+            nearest4<D>(sm.scand[r], sm.smu[r], K, sm.sbnd[r], ninf, x, best, arg, ok);
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
                 const float x2 = D == 3 ? x[D - 1][p] : 0.0f;

@@ -120,7 +120,7 @@ __device__ __forceinline__ float expanded_key(float x0, float x1, float x2, floa
 }
 
 // Reassignment scan of the 4 points x[.][p] (see the file header).  scand:
-// the K centre records padded to ntri triples; smu: the float32 centres;
+// the K centre records padded to whole triples; smu: the float32 centres;
 // bnd: the rounding-bound coefficients.  For every point writes ok[p]: the
 // winner is certified, and then arg[p] (its index) and best[p] (the
 // direct-form squared distance to it).  Points with ok[p] == false need the
@@ -147,13 +147,16 @@ __device__ __forceinline__ float with_index(float v, int g) {
 
 template <int D>
 __device__ __forceinline__ void nearest4(const float4* __restrict__ scand,
-                                         const float4* __restrict__ smu, int K, int ntri,
+                                         const float4* __restrict__ smu, int K,
                                          float4 bnd, float ninf, const float (&x)[D][4],
                                          float (&best)[4], int (&arg)[4], bool (&ok)[4]) {
     float m1[4], m2[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) { m1[p] = INFINITY; m2[p] = INFINITY; }
-    for (int g = 0; g < ntri; ++g) {
+    // whole triples; a last triple with one or two real centres (K not a
+    // multiple of 3) is folded on its own below, without its pads' keys
+    const int nfull = K / 3;
+    for (int g = 0; g < nfull; ++g) {
         const float4 r0 = scand[3 * g], r1 = scand[3 * g + 1], r2 = scand[3 * g + 2];
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
@@ -163,6 +166,19 @@ __device__ __forceinline__ void nearest4(const float4* __restrict__ scand,
             const float s2 = expanded_key<D>(x[0][p], x[1][p], x2, r2);
             const float g1 = fminf(fminf(s0, s1), s2);
             const float gp = with_index(g1, g);
+            m2[p] = __builtin_amdgcn_fmed3f(m1[p], gp, m2[p]);
+            m1[p] = min2(m1[p], gp, ninf);
+        }
+    }
+    const int rem = K - 3 * nfull;  // the same in every lane
+    if (rem != 0) {
+        const float4 r0 = scand[3 * nfull], r1 = scand[3 * nfull + 1];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const float x2 = D == 3 ? x[D - 1][p] : 0.0f;
+            float g1 = expanded_key<D>(x[0][p], x[1][p], x2, r0);
+            if (rem == 2) g1 = min2(g1, expanded_key<D>(x[0][p], x[1][p], x2, r1), ninf);
+            const float gp = with_index(g1, nfull);
             m2[p] = __builtin_amdgcn_fmed3f(m1[p], gp, m2[p]);
             m1[p] = min2(m1[p], gp, ninf);
         }
@@ -246,7 +262,7 @@ template <int D, bool VEC, typename Sink>
 __device__ __forceinline__ void assign_points(const float* __restrict__ X, int64_t ld,
                                               int64_t N, const float4* __restrict__ scand,
                                               const float4* __restrict__ smu, int K,
-                                              int ntri, float4 bnd, float ninf,
+                                              float4 bnd, float ninf,
                                               float4* __restrict__ wq, Sink&& sink) {
     const int lane = threadIdx.x & 63;
     const uint64_t below = (1ull << lane) - 1ull;
@@ -282,7 +298,7 @@ __device__ __forceinline__ void assign_points(const float* __restrict__ X, int64
         float best[4];
         int arg[4];
         bool ok[4];
-        nearest4<D>(scand, smu, K, ntri, bnd, ninf, x, best, arg, ok);
+        nearest4<D>(scand, smu, K, bnd, ninf, x, best, arg, ok);
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
             const float x2 = D == 3 ? x[D - 1][p] : 0.0f;

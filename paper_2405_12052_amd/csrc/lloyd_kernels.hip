@@ -252,11 +252,11 @@ __global__ __launch_bounds__(BLOCK) void km_scan(State* __restrict__ st) {
 template <int D, bool VEC, int KT, typename Sink>
 __device__ __forceinline__ void scan_points(const float* __restrict__ X, int64_t ld, int64_t N,
                                             const float4* __restrict__ scand,
-                                            const float4* __restrict__ smu, int K, int ntri,
+                                            const float4* __restrict__ smu, int K,
                                             float4 bnd, float ninf, int G,
                                             float4* __restrict__ wq, Sink&& sink) {
     if constexpr (KT == 0)
-        assign_points<D, VEC>(X, ld, N, scand, smu, K, ntri, bnd, ninf, wq, sink);
+        assign_points<D, VEC>(X, ld, N, scand, smu, K, bnd, ninf, wq, sink);
     else
         assign_points_mfma<D, VEC, KT>(X, ld, N, scand, smu, K, bnd, ninf, G, wq, sink);
 }
@@ -326,7 +326,7 @@ __device__ __forceinline__ void wr4(float4* p, float4 v) {
 // the one final block, with the grid's integer sums | counts in sm.sacc
 // and the objective of this pass in sm.sJ.
 template <int D, bool VEC, int KT>
-__device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm, int K, int G, int ntri,
+__device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm, int K, int G,
                             float4 bnd, float ninf) {
     constexpr int R = D + 1;  // per cluster: D sums, 1 count
     const int tid = threadIdx.x, w = tid >> 6;
@@ -341,7 +341,7 @@ __device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm
     double jl = 0.0;
     unsigned long long* myacc = &sm.sacc[(tid % copies) * KR];
     unsigned int* mycnt = &sm.scnt[(tid % copies) * K];
-    scan_points<D, VEC, KT>(X, ld, N, sm.scand, sm.smu, K, ntri, bnd, ninf, G, sm.squeue[w],
+    scan_points<D, VEC, KT>(X, ld, N, sm.scand, sm.smu, K, bnd, ninf, G, sm.squeue[w],
                             [&](int64_t, float x0, float x1, float x2, int k, float dist) {
         // coordinate-major slots [j * K + k]: the 64 lanes' clusters spread
         // over the LDS banks (a cluster-major stride of 4 int64 would put
@@ -436,9 +436,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) v
     if (st->done) return;
     __shared__ IterSmem sm;
     const int K = st->K;
-    const int ntri = stage_centres(st, K, sm.scand, sm.smu);
+    stage_centres(st, K, sm.scand, sm.smu);
     __syncthreads();
-    if (!update_pass<D, VEC, KT>(st, sm, K, st->G, ntri, st->bnd, st->minus_inf)) return;
+    if (!update_pass<D, VEC, KT>(st, sm, K, st->G, st->bnd, st->minus_inf)) return;
     finalize_update<D, false>(st, sm, K, st->G);
 }
 
@@ -464,7 +464,7 @@ __global__ __launch_bounds__(BLOCK) void lloyd_persist(State* __restrict__ st) {
     float4 bnd = st->bnd;
     __syncthreads();
     for (uint32_t round = 1;; ++round) {
-        if (update_pass<D, VEC, KT>(st, sm, K, G, ntri, bnd, ninf)) {
+        if (update_pass<D, VEC, KT>(st, sm, K, G, bnd, ninf)) {
             finalize_update<D, true>(st, sm, K, G);
             wait_mem();
             __syncthreads();
@@ -520,10 +520,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) v
     const float* __restrict__ X = st->X;
     const float4 bnd = st->bnd;
     const float ninf = st->minus_inf;
-    const int ntri = stage_centres(st, K, scand, smu);
+    stage_centres(st, K, scand, smu);
     __syncthreads();
     double jl = 0.0;
-    scan_points<D, VEC, KT>(X, ld, N, scand, smu, K, ntri, bnd, ninf, st->G, squeue[w],
+    scan_points<D, VEC, KT>(X, ld, N, scand, smu, K, bnd, ninf, st->G, squeue[w],
                             [&](int64_t i, float, float, float, int k, float dist) {
         if (labels) labels[i] = k;
         jl += (double)dist;
