@@ -418,6 +418,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--iters", type=int, default=50)
     ap.add_argument("--N", type=int, default=None, help="override N (testing only)")
+    ap.add_argument("--K", type=int, default=None,
+                    help="default workload only: K centres seeded from the same K=64 mixture "
+                         "(testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=20_000_000)
     ap.add_argument("--workload", choices=["hbm", "batched", "learned", "configs", "wide"],
@@ -478,10 +481,11 @@ def main():
     from paper_2405_12052_amd import KM_OPT_KEYS, KM_OPT_TIMING, KMeans
 
     s = datagen.spec("C3") if args.N is None else datagen.spec("C3", N=args.N)
+    K = s.K if args.K is None else args.K
     t0 = time.time()
     X, _ = datagen.generate(s)
-    mu0 = datagen.init_sample(X, s.N, s.K, s.init_seed)
-    log(f"generated N={s.N} d={s.d} K={s.K} in {time.time() - t0:.1f}s")
+    mu0 = datagen.init_sample(X, s.N, K, s.init_seed)
+    log(f"generated N={s.N} d={s.d} K={K} in {time.time() - t0:.1f}s")
     Xd = torch.from_numpy(X).cuda()
     torch.cuda.synchronize()
 
@@ -507,13 +511,13 @@ def main():
     pt_iters = s.N * args.iters * args.steps
     value = pt_iters / el
     avg_kernel_s = kern_ms / kern_n / 1e3
-    flops = alg_flops_per_point(s.d, s.K) * s.N
+    flops = alg_flops_per_point(s.d, K) * s.N
     achieved = flops / avg_kernel_s / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
             "traffic": (traffic_from_profile("lloyd_iter_C3_traffic.json")
-                        if args.keys != 2 and args.N is None else None),
-            "kernel": f"lloyd_iter<{s.d},true,{0 if args.keys != 2 else (2 if s.K > 32 else 1)}>",
+                        if args.keys != 2 and args.N is None and args.K is None else None),
+            "kernel": f"lloyd_iter<{s.d},true,{0 if args.keys != 2 else (2 if K > 32 else 1)}>",
             "avg_launch_us": avg_kernel_s * 1e6,
             "alg_flops_per_launch": flops,
             "alg_bytes_per_launch": alg_bytes_per_point(s.d) * s.N,
@@ -536,10 +540,10 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"plain Lloyd, HBM scale: N={s.N}, d={s.d}, K={s.K} isotropic "
+        "config": {"workload": f"plain Lloyd, HBM scale: N={s.N}, d={s.d}, K={K} isotropic "
                                f"Gaussian mixture, float32 SoA, seeded-sample init, "
                                f"{args.iters} updates (tol=0) + final labels",
-                   "N": s.N, "d": s.d, "K": s.K, "iterations": args.iters,
+                   "N": s.N, "d": s.d, "K": K, "iterations": args.iters,
                    "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
