@@ -214,11 +214,11 @@ int run_iterations(kmeans_ctx* c, int d, bool vec, int keys, int grid, int n_ite
     return KM_OK;
 }
 
-// Scan variant for K centres.  Automatic = the VALU scan: on gfx950 the FP32
-// matrix-core instructions do not execute alongside VALU instructions
-// (measured: no co-execution cycles), so the matrix-core scan pays its MFMA
-// time on top of its remaining VALU work and is slower at K = 64 (2.44 ms vs
-// 2.00 ms per update at N = 2e8).  It stays selectable.
+// Scan variant for K centres.  Automatic = the VALU scan: the matrix-core
+// scan takes only the FMAs off the VALU, while the compare-type tracking that
+// sets the scan's pace stays; with its MFMA time and lower occupancy it is
+// slower at K = 64 (1781 vs 1556 us per update at N = 2e8 on one box).  It
+// stays selectable.
 // Persistent fit: only when selected (KM_OPT_PERSIST = 2).  With the grid
 // of grid_for, the launch per update is as fast or faster at every size
 // measured (K = 16, per update: N = 1e6 22.3 vs 26.0 us, 4e6 37.3 vs 41.0 us,

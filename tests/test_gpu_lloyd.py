@@ -96,7 +96,7 @@ def test_stepwise_parity(km, name, kw, steps):
         assert r.iters == 1 and r.empty_events == ref["empty"]
         mu = r.centroids
     log(f"{name} {kw}: {steps} steps, max centre err {worst_c:.2e}, max |dE| {worst_e:.2e}, "
-        f"excused label mismatches {total_mism}")
+        f"label mismatches {total_mism}")
 
 
 # ---------------------------------------------------------------- end to end

@@ -105,7 +105,7 @@ def test_stepwise_parity(km, d, K, N, steps):
         assert r.iters == 1 and r.empty_events == ref["empty"]
         mu = r.centroids
     log(f"d={d} K={K}: {steps} steps, max centre err {worst_c:.2e}, max |dE| {worst_e:.2e}, "
-        f"excused label mismatches {total}")
+        f"label mismatches {total}")
 
 
 # ---------------------------------------------------------------- end to end
@@ -136,8 +136,9 @@ def test_fit_end_to_end(km, d, K, N):
                                    (3, 5, 7)])
 def test_general_kernels_equal_the_2d_3d_kernels(km, d, K, N):
     """KM_OPT_WIDE runs the general-shape kernels on a shape the 2-D/3-D
-    kernels also take: both give the direct-form argmin and the same exact
-    integer sums, so labels, centres and T are identical."""
+    kernels also take: both give the first-index minimum of the float64
+    direct form and the same exact integer sums, so labels, centres and T are
+    identical."""
     from paper_2405_12052_amd import KM_OPT_WIDE
     s, X, Xd = mixture(N, d, max(K, 2), 11_000 + d + K + N)
     mu0 = datagen.init_sample(X, N, K, 6)
