@@ -158,6 +158,34 @@ def test_general_kernels_equal_the_2d_3d_kernels(km, d, K, N):
     assert Jb == pytest.approx(Ja, rel=1e-12)
 
 
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("xs,ms", [(1e6, 1.0), (1.0, 1e6), (1e-15, 1e-15), (1e15, 1e15)])
+def test_general_and_2d_3d_labels_equal_at_extreme_scales(km, d, xs, ms):
+    """Data far from small centres (the float32 direct form errs by more than
+    many key gaps), centres far from the data, and extreme magnitudes: the
+    two implementations certify different sets of points, yet both give the
+    first-index float64 minimum, so their labels are identical and equal the
+    oracle's."""
+    from paper_2405_12052_amd import KM_OPT_WIDE
+    rng = np.random.default_rng(120 + d)
+    N, K = 50_001, 64
+    X = (rng.normal(size=(d, N)) * xs).astype(np.float32)
+    mu = rng.normal(size=(K, d)) * ms
+    log(f"  scales d={d} data {xs:g} centres {ms:g}")
+    Xd = torch.from_numpy(X).cuda()
+    la, Ja = km.assign(Xd, mu)
+    km.set_option(KM_OPT_WIDE, 1)
+    try:
+        lb, Jb = km.assign(Xd, mu)
+    finally:
+        km.set_option(KM_OPT_WIDE, 0)
+    a, b = la.cpu().numpy(), lb.cpu().numpy()
+    assert np.array_equal(a, b)
+    _, near, _, _ = label_check(a, X, mu)
+    log(f"    identical, equal to the oracle's ({near} near-ties)")
+    assert Jb == pytest.approx(Ja, rel=1e-12)
+
+
 # -------------------------------------------------------------- determinism
 def test_bitwise_repeat_and_grid_independence(km):
     from paper_2405_12052_amd import KM_OPT_BLOCKS, KM_OPT_GRAPH
