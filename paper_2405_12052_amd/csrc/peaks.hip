@@ -26,7 +26,6 @@ __global__ __launch_bounds__(PB) void issue_probe(float* __restrict__ out, int i
     const float b = b0 + (float)(threadIdx.x & 2) * 1e-7f;
 #pragma unroll
     for (int u = 0; u < CHAINS; ++u) x[u] = (float)(threadIdx.x & 7) * 0.125f + (float)u;
-#pragma unroll 2
     for (int i = 0; i < iters; ++i) {
 #pragma unroll
         for (int u = 0; u < CHAINS; ++u) {
