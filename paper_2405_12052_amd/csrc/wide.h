@@ -4,9 +4,10 @@
 // Internal to libkmeans_mi355x.so; the public interface is include/kmeans.h.
 //
 // The method is the same Lloyd iteration (the paper's "The Lloyd's
-// Algorithm" and "Serial Lloyd's Algorithm"): reassignment by the argmin of
-// the float32 squared distance in the direct form (found through a certified
-// expanded key, see wide_kernels.hip), per-cluster exact integer sums of
+// Algorithm" and "Serial Lloyd's Algorithm"): reassignment by the first-index
+// argmin of the squared distance to the float32 centres in the direct form
+// evaluated in float64 (found through a certified expanded key, see
+// wide_kernels.hip), per-cluster exact integer sums of
 // x * 2^G, the float64 mean step with the empty-cluster rule, E and the
 // tolerance test.  Per update two kernels run: wide_update (reassignment and
 // per-block sums) and wide_reduce (the partials summed into the totals by the

@@ -5,10 +5,10 @@
 // point is scored against every centre with the key m_k . x - |m_k|^2 / 2
 // (d fused multiply-adds; the largest key is the nearest centre), in triples
 // of centres whose best key carries the triple's number in its low bits.  A
-// rounding bound on both keys of the top pair and on the float32 direct form
-// (x_0 - m_k0)^2 + ... + (x_{d-1} - m_k,d-1)^2 certifies the winner when the
-// gap exceeds it; the other points are queued per wave and re-scanned with
-// the direct form evaluated in float64, first index of the minimum (the same
+// rounding bound on both keys of the top pair and on the float64 evaluation
+// of the direct form (x_0 - m_k0)^2 + ... + (x_{d-1} - m_k,d-1)^2 certifies
+// the winner when the gap exceeds it; the other points are queued per wave
+// and re-scanned with that float64 direct form, first index of the minimum (the same
 // near-tie rule as the 2-D/3-D kernels, so both give the same labels).  Each
 // lane holds P consecutive points in registers; the float32 centres sit in
 // LDS and are read as wave-uniform (broadcast) float4s, each serving the P
@@ -129,9 +129,11 @@ __device__ __forceinline__ void wide_points(const WState* __restrict__ st, const
     const uint64_t below = (1ull << lane) - 1ull;
     const float4* cm4 = reinterpret_cast<const float4*>(cm);
     // twice the rounding bounds (gamma_n <= n 2^-23 here) of the two keys of
-    // a comparison and of the direct form
+    // a comparison; and, with a factor of 16 to spare, twice the float64
+    // rounding of the direct form of the two distances (the near-tie rule):
+    // (d + 2) 2^-53 (D1 + D2) with D1 + D2 <= 2 (|x|^2 + 2 |t1| + gap)
     const float kc = (float)(d + 1) * 0x1p-22f;
-    const float dc = (float)(d + 2) * 0x1p-22f;
+    const float dc = (float)(d + 2) * 0x1p-49f;
     const float hmax = 0.5f * amax[WD_MAX];
     int qn = 0;  // this wave's queue length (the same in every lane)
 
@@ -249,7 +251,8 @@ __device__ __forceinline__ void wide_points(const WState* __restrict__ st, const
             const int k = s3[0] == t1 ? k0 : (s3[1] == t1 ? k0 + 1 : k0 + 2);
             // certificate: the gap to the runner-up exceeds the rounding of
             // both keys, the index bits of a packed runner-up, and the
-            // rounding of the direct form (so that it, too, ranks them so)
+            // float64 rounding of the direct form (so that it, too, ranks
+            // them so)
             const bool other = g2v[p] > t2;
             const float sec = other ? g2v[p] : t2;
             const float gap = t1 - sec;
@@ -260,7 +263,7 @@ __device__ __forceinline__ void wide_points(const WState* __restrict__ st, const
                 mag = fmaf(a, fabsf(x[p][j]), mag);
                 xx = fmaf(x[p][j], x[p][j], xx);
             }
-            float bound = fmaf(kc, mag, dc * fmaxf(xx - 2.0f * t1 + gap, 0.0f));
+            float bound = fmaf(kc, mag, dc * (xx + 2.0f * fabsf(t1) + fabsf(gap)));
             if (other) bound = fmaf(0x1p-17f, fabsf(sec), bound);
             const bool valid = p < n;
             const bool ok = gap > bound && k < K;
