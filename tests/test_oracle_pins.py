@@ -103,6 +103,47 @@ def test_assign_brute_force_and_second_distance(d, K):
         assert math.isclose(dsec[i], D[order[1]], rel_tol=1e-14)
 
 
+@pytest.mark.parametrize("d,K,grid", [(1, 5, False), (2, 7, False), (3, 64, False), (7, 9, False),
+                                       (16, 12, False), (2, 6, True), (3, 10, True)])
+def test_assign_f32_is_the_float64_direct_form_on_rounded_centres(d, K, grid):
+    """The reassignment rule the library's labels must match bit for bit:
+    centres rounded to float32, each point's squared distance summed left to
+    right in float64 (every difference, square and partial sum rounded, no
+    fused operations), first index of the minimum.  Written out here with
+    Python floats (IEEE float64, one rounding per operation); the oracle's C
+    code must give the same labels and the same minimum distances exactly,
+    also on an integer grid full of exact ties."""
+    rng = np.random.default_rng(40 + d * 10 + K)
+    N = 60
+    if grid:
+        X = rng.integers(-3, 4, size=(d, N)).astype(np.float32)
+        mu = rng.integers(-3, 3, size=(K, d)).astype(np.float64) + 0.5
+        mu[: K // 2] = np.round(mu[: K // 2] - 0.5)
+        mu[K - 1] = mu[0]                            # a duplicate: exact ties, first index wins
+    else:
+        X = (rng.normal(size=(d, N)) * 3).astype(np.float32)
+        mu = rng.normal(size=(K, d)) * 3 + 1e-9
+    lab, dmin, _ = oracle.assign(X, mu)              # assign_f32 defaults to True
+    m32 = [[float(np.float32(mu[k, j])) for j in range(d)] for k in range(K)]
+    ties = 0
+    for i in range(N):
+        best, arg = math.inf, 0
+        dists = []
+        for k in range(K):
+            D = 0.0
+            for j in range(d):
+                t = float(X[j, i]) - m32[k][j]
+                D = D + t * t
+            dists.append(D)
+            if D < best:
+                best, arg = D, k
+        ties += dists.count(best) > 1
+        assert lab[i] == arg and (not grid or arg != K - 1)
+        assert dmin[i] == best
+    if grid:
+        assert ties > 0
+
+
 def test_assign_f32_rounds_only_the_centres():
     X = soa([[0.0, 0.0]])
     mu = np.array([[1.0 / 3.0, 0.0]])
