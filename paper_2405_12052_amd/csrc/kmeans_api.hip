@@ -480,6 +480,19 @@ int kmeans_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int32_t d, 
                              reinterpret_cast<char*>(c->st) + km::kProgressOffset,
                              km::kUploadBytes - km::kProgressOffset, hipMemcpyDeviceToHost,
                              c->stream));
+    // the E / J history of every update that may have run (T <= that count),
+    // read with the results: one synchronisation per fit instead of two
+    {
+        const int ran = persisted ? max_iter : launched;
+        const int nc = ran < c->hist_cap ? ran : c->hist_cap;
+        if (nc > 0) {
+            KM_HIP(c, hipMemcpyAsync(c->hist_h, c->hist, sizeof(double) * (size_t)nc,
+                                     hipMemcpyDeviceToHost, c->stream));
+            KM_HIP(c, hipMemcpyAsync(c->hist_h + c->hist_cap, c->hist + c->hist_cap,
+                                     sizeof(double) * (size_t)nc, hipMemcpyDeviceToHost,
+                                     c->stream));
+        }
+    }
     KM_HIP(c, hipStreamSynchronize(c->stream));
     if (h->flags & km::FLAG_TIMEOUT)
         return fail(c, KM_EHIP, "persistent fit: a block's wait for an update timed out");
@@ -492,14 +505,6 @@ int kmeans_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int32_t d, 
             c->iter_ms += ms;
         }
         c->iter_kernels = persisted ? T : launched;
-    }
-    const int nh = T < c->hist_cap ? T : c->hist_cap;
-    if (nh > 0) {
-        KM_HIP(c, hipMemcpyAsync(c->hist_h, c->hist, sizeof(double) * (size_t)nh,
-                                 hipMemcpyDeviceToHost, c->stream));
-        KM_HIP(c, hipMemcpyAsync(c->hist_h + c->hist_cap, c->hist + c->hist_cap,
-                                 sizeof(double) * (size_t)nh, hipMemcpyDeviceToHost, c->stream));
-        KM_HIP(c, hipStreamSynchronize(c->stream));
     }
     if (h->flags & km::FLAG_NONFINITE) return fail(c, KM_EINVAL, "X holds a NaN or an infinity");
     memcpy(centroids_out, h->mu64, sizeof(double) * (size_t)K * d);

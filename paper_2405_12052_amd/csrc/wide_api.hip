@@ -255,6 +255,18 @@ int wide_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, int K,
     double* m64 = w->mu_h;
     KM_HIP(c, hipMemcpyAsync(m64, w->mu64, sizeof(double) * (size_t)K * d, hipMemcpyDeviceToHost,
                              c->stream));
+    // the E / J history of every update that ran (T <= launched), read with
+    // the results: one synchronisation instead of two
+    {
+        const int nc = launched < c->hist_cap ? launched : c->hist_cap;
+        if (nc > 0) {
+            KM_HIP(c, hipMemcpyAsync(c->hist_h, c->hist, sizeof(double) * (size_t)nc,
+                                     hipMemcpyDeviceToHost, c->stream));
+            KM_HIP(c, hipMemcpyAsync(c->hist_h + c->hist_cap, c->hist + c->hist_cap,
+                                     sizeof(double) * (size_t)nc, hipMemcpyDeviceToHost,
+                                     c->stream));
+        }
+    }
     rc = read_progress(c, kWProgressBytes);
     if (rc) return rc;
     const WState* h = w->st_h;
@@ -267,14 +279,6 @@ int wide_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, int K,
             c->iter_ms += ms;
         }
         c->iter_kernels = launched;
-    }
-    const int nh = T < c->hist_cap ? T : c->hist_cap;
-    if (nh > 0) {
-        KM_HIP(c, hipMemcpyAsync(c->hist_h, c->hist, sizeof(double) * (size_t)nh,
-                                 hipMemcpyDeviceToHost, c->stream));
-        KM_HIP(c, hipMemcpyAsync(c->hist_h + c->hist_cap, c->hist + c->hist_cap,
-                                 sizeof(double) * (size_t)nh, hipMemcpyDeviceToHost, c->stream));
-        KM_HIP(c, hipStreamSynchronize(c->stream));
     }
     if (h->flags & FLAG_NONFINITE) return fail(c, KM_EINVAL, "X holds a NaN or an infinity");
     memcpy(centroids_out, m64, sizeof(double) * (size_t)K * d);
