@@ -128,11 +128,14 @@ __device__ __forceinline__ void wide_points(const WState* __restrict__ st, const
     const int lane = threadIdx.x & 63;
     const uint64_t below = (1ull << lane) - 1ull;
     const float4* cm4 = reinterpret_cast<const float4*>(cm);
-    // twice the rounding bounds (gamma_n <= n 2^-23 here) of the two keys of
-    // a comparison; and, with a factor of 16 to spare, twice the float64
-    // rounding of the direct form of the two distances (the near-tie rule):
-    // (d + 2) 2^-53 (D1 + D2) with D1 + D2 <= 2 (|x|^2 + 2 |t1| + gap)
-    const float kc = (float)(d + 1) * 0x1p-22f;
+    // the rounding of the two keys of a comparison: each key is d FMAs on
+    // -fl32(|m|^2)/2, within gamma_{d+1} mag(x) of the exact key, gamma_n =
+    // n u / (1 - n u), u = 2^-24, so both within (d + 1) 2^-23 mag(x) (with
+    // 2^-10 to spare for the float32 evaluation of mag and of the gap); and,
+    // with a factor of 16 to spare, twice the float64 rounding of the direct
+    // form of the two distances (the near-tie rule): (d + 2) 2^-53 (D1 + D2)
+    // with D1 + D2 <= 2 (|x|^2 + 2 |t1| + gap)
+    const float kc = (float)(d + 1) * 0x1.004p-23f;
     const float dc = (float)(d + 2) * 0x1p-49f;
     const float hmax = 0.5f * amax[WD_MAX];
     int qn = 0;  // this wave's queue length (the same in every lane)
