@@ -131,10 +131,10 @@ __device__ __forceinline__ float expanded_key(float x0, float x1, float x2, floa
 // and-or), the smallest of those (m1) and the second smallest (m2): four
 // compare-type instructions per triple.  At the end the winning triple's
 // three keys are formed again (bit-identical), giving the exact smallest key
-// t1, its first index, and the triple's second smallest t2.  The second
-// smallest key over all centres is then min(m2, t2) up to the index bits in
-// m2 (at most 31 units in its last place, below 2^-18 |m2|), which the
-// certificate adds to the rounding bound.
+// t1, its first index, and the triple's second smallest t2.  Every key of
+// another triple is at least m2 less its index bits (at most 31 units in its
+// last place, below 2^-18 |m2|), so the second smallest key over all centres
+// is at least min(t2, m2 - 2^-17 |m2|), which the certificate compares with t1.
 constexpr uint32_t TRI_BITS = 31u;  // ntri <= 32
 
 // v with its 5 lowest bits replaced by the (wave-uniform) index g: one
@@ -195,13 +195,16 @@ __device__ __forceinline__ void nearest4(const float4* __restrict__ scand,
         const float t1 = fminf(fminf(s0, s1), s2);
         const float t2 = __builtin_amdgcn_fmed3f(s0, s1, s2);
         const int k = s0 == t1 ? k0 : (s1 == t1 ? k0 + 1 : k0 + 2);
-        // rounding bound of the keys of this point, plus the index bits of m2
+        // rounding bound of the keys of this point
         float b = fmaf(bnd.y, fabsf(x0), bnd.x);
         b = fmaf(bnd.z, fabsf(x1), b);
         if constexpr (D == 3) b = fmaf(bnd.w, fabsf(x2), b);
-        const bool other = m2[p] < t2;
-        const float sec = other ? m2[p] : t2;
-        if (other) b += ldexpf(fabsf(m2[p]), -17);
+        // every other triple's smallest key is at least its packed minimum
+        // less the index bits (31 units in the last place, below 2^-18 of it),
+        // and that packed minimum is at least m2: so at least
+        // m2 - 2^-17 |m2| (p - 2^-18 |p| grows with p).  With a single
+        // triple m2 = +inf, the difference is a NaN and fminf returns t2.
+        const float sec = fminf(t2, m2[p] - ldexpf(fabsf(m2[p]), -17));
         ok[p] = sec - t1 > b && k < K;
         arg[p] = ok[p] ? k : 0;
         best[p] = direct_dist<D>(x0, x1, x2, smu[arg[p]]);
@@ -320,11 +323,12 @@ __device__ __forceinline__ void assign_points(const float* __restrict__ X, int64
 
 // Centre tables for the reassignment: records {-2 m, fl32(|m|^2)} padded to
 // whole triples with {0, 0, 0, 2^127}, and the bound coefficients
-//   b(x) = 2^-20 (Cmax + 2 sum_j A_j |x_j|) + 2^-46 xmax sum_j |x_j|,
+//   b(x) = 2^-21 (1 + 2^-10) (Cmax + 2 sum_j A_j |x_j|) + 2^-46 xmax sum_j |x_j|,
 //   Cmax = max_k c_k, A_j = max_k |m_kj|, xmax = max |x| over the data
-// (xmax_bits).  The first part exceeds twice the rounding error of any key
-// (<= 4.01 u (Cmax + 2 sum_j A_j |x_j|), u = 2^-24: the rounding of c_k and of
-// three FMAs).  The second covers the float64 evaluation of the direct form
+// (xmax_bits).  The first part is twice the rounding bound of a key
+// (gamma_4 (Cmax + 2 sum_j A_j |x_j|), gamma_4 = 4u / (1 - 4u), u = 2^-24: the
+// rounding of c_k and of three FMAs), with 2^-10 to spare for the float32
+// evaluation of the bound and of the gap.  The second covers the float64 evaluation of the direct form
 // used for near-ties: two distances D err by at most 2 (d + 2) 2^-53 D, D <=
 // |x|^2 + |key|, below 2^-49 (|x|^2 + |key|); the key part lies far inside
 // the first term and |x|^2 <= xmax sum_j |x_j|.  A certified winner is
@@ -361,8 +365,9 @@ __device__ inline void prep_centres(const float4* m32, int K, float4* cand, floa
             am0 = fmaxf(am0, sa[3 * k]); am1 = fmaxf(am1, sa[3 * k + 1]); am2 = fmaxf(am2, sa[3 * k + 2]);
         }
         const float e = 0x1p-46f * __uint_as_float(xmax_bits);
-        *bnd = make_float4(ldexpf(cm, -20), ldexpf(am0, -19) + e, ldexpf(am1, -19) + e,
-                           ldexpf(am2, -19) + e);
+        const float f = 0x1.004p-21f;
+        *bnd = make_float4(cm * f, am0 * (2.0f * f) + e, am1 * (2.0f * f) + e,
+                           am2 * (2.0f * f) + e);
     }
     __syncthreads();
 }

@@ -189,9 +189,9 @@ __device__ __forceinline__ void assign_points_mfma(const float* __restrict__ X, 
     const int c = lane & 31, h = lane >> 5;
     const uint64_t below = (1ull << lane) - 1ull;
 
-    // Scales: |x 2^ex| < 2^15 and |a 2^ea| < 2^15 (max |a_kj| = 2^20 max(bnd.yzw));
-    // ex - ea <= 64 keeps every scaled key below 2^96.
-    const float amax = ldexpf(fmaxf(fmaxf(bnd.y, bnd.z), bnd.w), 20);
+    // Scales: |x 2^ex| < 2^15 and |a 2^ea| < 2^15 (max |a_kj| = 2 max_kj |m_kj| <=
+    // 2^21 max(bnd.yzw)); ex - ea <= 64 keeps every scaled key below 2^96.
+    const float amax = ldexpf(fmaxf(fmaxf(bnd.y, bnd.z), bnd.w), 21);
     int ex = G - 15;
     int ea = amax > 0.0f ? 14 - ilogbf(amax) : ex;
     if (ex > ea + 64) ex = ea + 64;
@@ -224,9 +224,10 @@ __device__ __forceinline__ void assign_points_mfma(const float* __restrict__ X, 
             C[t][r] = kr < K ? ldexpf(scand[kr].w, ea + ex) : 0x1p127f;
         }
     }
-    // bound on the scaled gap: 2^-16 mag'(x) + 64
-    const float bx = ldexpf(bnd.x, 4 + ea + ex) + 64.0f;
-    const float by = ldexpf(bnd.y, 4 + ea), bz = ldexpf(bnd.z, 4 + ea), bw = ldexpf(bnd.w, 4 + ea);
+    // bound on the scaled gap: 2^-16 mag'(x) + 64 (the coefficients hold 2^-21
+    // and 2^-20 of the magnitudes, with 2^-10 to spare)
+    const float bx = ldexpf(bnd.x, 5 + ea + ex) + 64.0f;
+    const float by = ldexpf(bnd.y, 5 + ea), bz = ldexpf(bnd.z, 5 + ea), bw = ldexpf(bnd.w, 5 + ea);
     const float sx = ldexpf(1.0f, ex);
 
     int qn = 0;

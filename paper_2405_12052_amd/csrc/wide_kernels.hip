@@ -253,11 +253,14 @@ __device__ __forceinline__ void wide_points(const WState* __restrict__ st, const
             const float t2 = __builtin_amdgcn_fmed3f(s3[0], s3[1], s3[2]);
             const int k = s3[0] == t1 ? k0 : (s3[1] == t1 ? k0 + 1 : k0 + 2);
             // certificate: the gap to the runner-up exceeds the rounding of
-            // both keys, the index bits of a packed runner-up, and the
-            // float64 rounding of the direct form (so that it, too, ranks
-            // them so)
-            const bool other = g2v[p] > t2;
-            const float sec = other ? g2v[p] : t2;
+            // both keys and the float64 rounding of the direct form (so that
+            // it, too, ranks them so).  Every other triple's largest key is
+            // at most its packed maximum plus the index bits (31 units in the
+            // last place, below 2^-18 of it), and that packed maximum is at
+            // most g2v: so at most g2v + 2^-17 |g2v| (p + 2^-18 |p| grows
+            // with p).  With a single triple g2v = -inf, the sum is a NaN and
+            // fmaxf returns t2.
+            const float sec = fmaxf(t2, g2v[p] + ldexpf(fabsf(g2v[p]), -17));
             const float gap = t1 - sec;
             float mag = hmax, xx = 0.0f;
 #pragma unroll
@@ -266,8 +269,7 @@ __device__ __forceinline__ void wide_points(const WState* __restrict__ st, const
                 mag = fmaf(a, fabsf(x[p][j]), mag);
                 xx = fmaf(x[p][j], x[p][j], xx);
             }
-            float bound = fmaf(kc, mag, dc * (xx + 2.0f * fabsf(t1) + fabsf(gap)));
-            if (other) bound = fmaf(0x1p-17f, fabsf(sec), bound);
+            const float bound = fmaf(kc, mag, dc * (xx + 2.0f * fabsf(t1) + fabsf(gap)));
             const bool valid = p < n;
             const bool ok = gap > bound && k < K;
             if (valid && ok) sink(x[p], i0 + p, k, wide_direct<D>(x[p], cm4 + k * NB));
