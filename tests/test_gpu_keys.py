@@ -84,7 +84,10 @@ def test_assign_ties_identical_across_scans(km, d):
 def test_far_points_and_large_offsets(km):
     """Points far from every centre and data offset from the origin: keys
     are dominated by |m|^2 and 2 m.x, the regime where the rounding bound
-    matters most."""
+    matters most.  This case caught a runner-up bound that allowed for the
+    index bits of another triple's packed minimum only when it undercut the
+    winning triple's second key: 45 points were mislabelled once the key
+    bound was made tight."""
     rng = np.random.default_rng(80)
     N, K = 150_001, 40
     X = (rng.normal(size=(3, N)) * 3 + 1000.0).astype(np.float32)
