@@ -35,10 +35,17 @@
  *     The objective sums, in float64, the float32 direct-form distances
  *     (left to right, the first term a product, the others fused
  *     multiply-adds) to the chosen centres.
- *     Per-cluster sums are exact integer sums of the points on a 2^-G grid,
- *     G chosen from max|x| so that every |x|*2^G < 2^30; the divide, E and the
- *     tolerance test are float64.  Results do not depend on the launch
- *     configuration and repeat bit for bit from run to run.
+ *     Per-cluster sums are exact integer sums of the points rounded to the
+ *     grid 2^-F, F = 43 - ilogb(max|x|) (so every |x| 2^F < 2^44), carried
+ *     in 128 bits across blocks; the divide, E and the tolerance test are
+ *     float64.  Each mean is therefore within 2^(ilogb(max|x|) - 44) <=
+ *     max|x| 2^-44 per coordinate of the exact mean of its points.  Fits
+ *     (kmeans_fit, kmeans_fit_batched) return KM_EUNSUPPORTED, after their
+ *     scan of X and before any update, for data with max|x| >= 2^28, where
+ *     that bound could exceed 1e-5 for a cluster near the origin (scale such
+ *     data first); kmeans_assign takes no sums and has no such limit.
+ *     Results do not depend on the launch configuration and repeat bit for
+ *     bit from run to run.
  *   - An empty cluster keeps its previous centre and is counted.
  *   - Supported shapes: 1 <= d <= 32, 1 <= K <= 1024, K <= N <= 2^31 - 1,
  *     where, outside d in {2, 3} with K <= 64, one block's tables must fit
@@ -100,7 +107,10 @@ enum km_option {
     KM_OPT_GRAPH = 1,     /* 1 (default): replay iterations from a hipGraph;
                              0: launch each iteration kernel directly          */
     KM_OPT_UNROLL = 2,    /* iterations per graph launch (0 = automatic)       */
-    KM_OPT_BLOCKS = 3,    /* grid size of the iteration kernel (0 = automatic) */
+    KM_OPT_BLOCKS = 3,    /* grid size of the iteration kernel (0 = automatic;
+                             raised to N / 2^19 blocks where smaller, so that
+                             no block adds more than 2^19 points into its
+                             int64 sums)                                       */
     KM_OPT_TIMING = 4,    /* 1: time the iteration launches with HIP events
                              (see kmeans_get_timing)                           */
     KM_OPT_KEYS = 5,      /* how the reassignment scan forms its keys
@@ -174,7 +184,7 @@ int kmeans_assign(kmeans_ctx *ctx, const float *X, int64_t N, int64_t ld,
  * with E == 0: the per-cluster sums are exact, so this is the update after
  * the indicators stopped changing -- the paper's convergence criterion);
  * max_iter >= 1.  Returns KM_EINVAL (after the run) if X holds a NaN or an
- * infinity.
+ * infinity, KM_EUNSUPPORTED (after the scan) if max|x| >= 2^28.
  */
 int kmeans_fit(kmeans_ctx *ctx, const float *X, int64_t N, int64_t ld,
                int32_t d, int32_t K, const double *init, double tol,
@@ -238,8 +248,9 @@ typedef struct km_schedule {
  * objective of each restart is evaluated at its final centres and the
  * smallest is kept (lowest restart index on ties).  Constraints per
  * instance: d in {2, 3}, 1 <= K <= 32, K <= N <= 2^27, 1 <= n_restarts <= 8,
- * ld >= N.  Returns KM_EINVAL if any instance holds a NaN or an infinity
- * (after the run; the other instances' outputs are valid).
+ * ld >= N.  Returns KM_EINVAL if any instance holds a NaN or an infinity,
+ * KM_EUNSUPPORTED if any has max|x| >= 2^28 (after the run; the other
+ * instances' outputs are valid).
  */
 int kmeans_fit_batched(kmeans_ctx *ctx, int32_t n_inst, km_instance *inst, double tol,
                        int32_t max_iter);
@@ -331,8 +342,8 @@ int kmeans_init_learned(kmeans_ctx *ctx, const float *X, int64_t N, int64_t ld, 
 
 /*
  * k-means++ initial centres (Arthur and Vassilvitskii, 2007): an alternative
- * to the paper's random choice of initial centres (Section 3, first step,
- * whose outcome the paper notes depends on that choice).  The draw is exact
+ * to the paper's random choice of initial centres (the first step of "The
+ * Lloyd's Algorithm", whose outcome the paper notes depends on that choice).  The draw is exact
  * and reproducible given the caller's K uniforms u[0..K) (host, each in
  * [0, 1)):
  *   - centre 0 is point min(N-1, floor(u[0] * N));

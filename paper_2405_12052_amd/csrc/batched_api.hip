@@ -43,6 +43,7 @@ struct BatchedWS {
     double* best_mu = nullptr;
     double* best_mu_h = nullptr;
     unsigned long long* tpart = nullptr;
+    unsigned long long* fold = nullptr;
     double* tjpart = nullptr;
     BTeam* teams = nullptr;
     int32_t* error_h = nullptr;  // pinned copy of BatchState::error
@@ -58,7 +59,7 @@ void batched_ws_free(BatchedWS* w) {
     if (!w) return;
     if (w->graph) (void)hipGraphExecDestroy(w->graph);
     void* dev[] = {w->bs, w->inst, w->order, w->init, w->absmax, w->out, w->best, w->best_mu,
-                   w->tpart, w->tjpart, w->teams};
+                   w->tpart, w->fold, w->tjpart, w->teams};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     void* host[] = {w->bs_h, w->inst_h, w->order_h, w->init_h, w->out_h, w->best_h,
@@ -150,7 +151,8 @@ int ensure_ws(kmeans_ctx* c, int n_inst, size_t n_init, int blocks) {
     if (blocks > w->cap_blocks) {
         (void)hipStreamSynchronize(c->stream);
         drop_graph(w);
-        int rc = dev_alloc(c, &w->tpart, (size_t)2 * blocks * km::BK_PART);
+        int rc = dev_alloc(c, &w->tpart, (size_t)2 * blocks * km::BK_PART * 2);
+        if (!rc) rc = dev_alloc(c, &w->fold, (size_t)blocks * km::BK_PART * 2);
         if (!rc) rc = dev_alloc(c, &w->tjpart, (size_t)2 * blocks * km::BK_RMAX);
         if (!rc) rc = dev_alloc(c, &w->teams, (size_t)blocks);
         if (rc) {
@@ -284,6 +286,7 @@ int run_batched(kmeans_ctx* c, int32_t n_inst, km_instance* inst, double tol, in
     h->best = w->best;
     h->best_mu = w->best_mu;
     h->tpart = w->tpart;
+    h->fold = w->fold;
     h->tjpart = w->tjpart;
     h->teams = w->teams;
 
@@ -340,12 +343,13 @@ int run_batched(kmeans_ctx* c, int32_t n_inst, km_instance* inst, double tol, in
     if (ms_out) *ms_out = w->last_ms;
     if (*w->error_h) return fail(c, KM_EHIP, "a team barrier of the batched kernel timed out");
 
-    int nonfinite = -1;
+    int nonfinite = -1, range = -1;
     for (int i = 0; i < n_inst; ++i) {
         km_instance& in = inst[i];
         const BOut* o = w->out_h + (size_t)i * km::BK_RMAX;
         if (o[0].iters < 0) {
-            if (nonfinite < 0) nonfinite = i;
+            if (o[0].iters == -1 && nonfinite < 0) nonfinite = i;
+            if (o[0].iters == -2 && range < 0) range = i;
             continue;
         }
         const int b = w->best_h[i];
@@ -365,6 +369,10 @@ int run_batched(kmeans_ctx* c, int32_t n_inst, km_instance* inst, double tol, in
     }
     if (nonfinite >= 0)
         return fail(c, KM_EINVAL, "instance %d holds a NaN or an infinity", nonfinite);
+    if (range >= 0) {
+        km::range_error(c);
+        return fail(c, KM_EUNSUPPORTED, "instance %d: %s", range, std::string(c->err).c_str());
+    }
     return KM_OK;
 }
 

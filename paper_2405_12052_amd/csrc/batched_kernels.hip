@@ -20,9 +20,13 @@
 // the remaining blocks, single blocks take the small instances, again largest
 // first, and run them start to finish with block barriers only.
 //
-// Per restart, the reassignment, the integer sums of x * 2^G and the float64
-// update are the same device code as the single-instance fit, so centres,
-// labels, E and T equal those of kmeans_fit from the same initial centres.
+// Per restart, the reassignment, the integer sums of rint(x 2^F) and the
+// float64 update are the same device code as the single-instance fit, so
+// centres, labels, E and T equal those of kmeans_fit from the same initial
+// centres.  A block whose share of an instance exceeds FXP_BLOCK_POINTS
+// points takes it in chunks of at most that many, adding each chunk's sums
+// into a block-private 128-bit area in device memory (fold), so that no
+// int64 slot overflows under any schedule.
 #include "lloyd_device.h"
 
 namespace km {
@@ -34,6 +38,8 @@ constexpr int BK_ACC = BK_RMAX * BK_KMAX * (DMAX + 1);
 // up to ACC_COPY_MAX copies at small ones (acc_copies).
 constexpr int BK_ACC_SLOTS = 3 * BK_ACC;
 constexpr int ACC_COPY_MAX = 16;
+static_assert(BK_ACC % BLOCK == 0 && BK_ACC_SLOTS >= 2 * BK_ACC,
+              "the accumulators hold the 128-bit totals");
 
 // Copies of an instance's accumulators: lane l adds to copy l % copies.
 // With few clusters, many of a wave's 64 lanes add to the same slot and their
@@ -106,9 +112,10 @@ __device__ bool team_barrier(BatchState* __restrict__ bs, BTeam* tm, uint32_t& n
 // in `mask`: MODE_ACC adds the points to their clusters' integer sums,
 // MODE_OBJ adds the distances to jl, MODE_LABEL writes the labels.  MODE_OBJ
 // and MODE_LABEL take a single restart in `mask`.
+// The groups of 4 points taken are [g_lo, g_hi), strided over the team.
 template <int D, int MODE>
-__device__ void points_pass(const BInst& in, int rank, int S, int mask, int G, float ninf,
-                            BSmem& sm, double& jl) {
+__device__ void points_pass(const BInst& in, int rank, int S, int mask, double fscale, float ninf,
+                            BSmem& sm, double& jl, int64_t g_lo, int64_t g_hi) {
     const int K = in.K;
     const int64_t N = in.N, ld = in.ld;
     const float* __restrict__ X = in.X;
@@ -118,25 +125,24 @@ __device__ void points_pass(const BInst& in, int rank, int S, int mask, int G, f
     float4* __restrict__ wq = sm.queue[w];
     int qn = 0;  // this wave's queue length (the same in every lane)
 
-    // add a point's fixed-point coordinates q (|q| < 2^30, see scale_exponent)
-    // and a count of one to cluster k of restart r; slots are coordinate-major
-    // per restart, [(r * (D + 1) + j) * K + k], so that the lanes' clusters
-    // spread over the LDS banks
+    // add a point's fixed-point coordinates (as fxp_bits, lloyd_device.h) and
+    // a count of one to cluster k of restart r; slots are coordinate-major per
+    // restart, [(r * (D + 1) + j) * K + k], so that the lanes' clusters spread
+    // over the LDS banks
     const int nacc = in.R * K * (D + 1);
     unsigned long long* const myacc = &sm.acc[(lane % acc_copies(nacc)) * nacc];
-    auto acc_add = [&](int r, int k, int q0, int q1, int q2) {
+    auto acc_add = [&](int r, int k, float x0, float x1, float x2) {
         unsigned long long* a = &myacc[r * (D + 1) * K + k];
-        const int qs[3] = {q0, q1, q2};
+        const float xs[3] = {x0, x1, x2};
 #pragma unroll
         for (int j = 0; j < D; ++j)
-            __hip_atomic_fetch_add(&a[j * K], (unsigned long long)(long long)qs[j],
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(&a[j * K], fxp_bits(xs[j], fscale), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
         __hip_atomic_fetch_add(&a[D * K], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     };
     auto take = [&](int r, int64_t i, float x0, float x1, float x2, int k, float dist) {
         if constexpr (MODE == MODE_ACC) {
-            acc_add(r, k, __float2int_rn(ldexpf(x0, G)), __float2int_rn(ldexpf(x1, G)),
-                    D == 3 ? __float2int_rn(ldexpf(x2, G)) : 0);
+            acc_add(r, k, x0, x1, x2);
         } else if constexpr (MODE == MODE_LABEL) {
             in.labels[i] = k;
         }
@@ -157,27 +163,18 @@ __device__ void points_pass(const BInst& in, int rank, int S, int mask, int G, f
         qn -= cnt;
     };
 
-    const int64_t ngroups = (N + 3) / 4;
     const int64_t stride = (int64_t)S * BLOCK;
-    for (int64_t gw = (int64_t)rank * BLOCK + (threadIdx.x & ~63); gw < ngroups; gw += stride) {
+    for (int64_t gw = g_lo + (int64_t)rank * BLOCK + (threadIdx.x & ~63); gw < g_hi; gw += stride) {
         const int64_t g = gw + lane;
         float x[D][4];
         int n = 0;
-        if (g < ngroups) {
+        if (g < g_hi) {
             n = load_group_rt<D>(vec, X, ld, N, g, x);
         } else {
 #pragma unroll
             for (int j = 0; j < D; ++j)
 #pragma unroll
                 for (int p = 0; p < 4; ++p) x[j][p] = 0.0f;
-        }
-        // the points' fixed-point coordinates, shared by every restart
-        int qx[D][4];
-        if constexpr (MODE == MODE_ACC) {
-#pragma unroll
-            for (int j = 0; j < D; ++j)
-#pragma unroll
-                for (int p = 0; p < 4; ++p) qx[j][p] = __float2int_rn(ldexpf(x[j][p], G));
         }
 #pragma unroll 1
         for (int r = 0; r < BK_RMAX; ++r) {
@@ -190,12 +187,7 @@ __device__ void points_pass(const BInst& in, int rank, int S, int mask, int G, f
             for (int p = 0; p < 4; ++p) {
                 const float x2 = D == 3 ? x[D - 1][p] : 0.0f;
                 const bool valid = p < n;
-                if (valid && ok[p]) {
-                    if constexpr (MODE == MODE_ACC)
-                        acc_add(r, arg[p], qx[0][p], qx[1][p], D == 3 ? qx[D - 1][p] : 0);
-                    else
-                        take(r, g * 4 + p, x[0][p], x[1][p], x2, arg[p], best[p]);
-                }
+                if (valid && ok[p]) take(r, g * 4 + p, x[0][p], x[1][p], x2, arg[p], best[p]);
                 const bool f = valid && !ok[p];
                 const uint64_t m = __ballot(f);
                 if (m) {
@@ -238,8 +230,14 @@ __device__ bool run_instance(BatchState* __restrict__ bs, int inst, int rank, in
     const int tid = threadIdx.x;
     const int nacc = R * K * (D + 1);
     const uint32_t am = bs->absmax[inst];
-    const bool bad = am >= 0x7f800000u;
-    const int G = scale_exponent(am);
+    const bool bad = am >= FXP_RANGE_BITS;  // non-finite, or beyond the sums' range
+    const int xe = data_exponent(am);
+    const double fscale = fxp_scale(xe);
+    const int64_t ngroups = (in.N + 3) / 4;
+    // groups of points per chunk: each block of the team takes at most
+    // FXP_BLOCK_POINTS / 4 of them
+    const int64_t chunk = (int64_t)S * (FXP_BLOCK_POINTS / 4);
+    unsigned long long* const fold = bs->fold + (size_t)blockIdx.x * BK_ACC * 2;
     const float ninf = bs->minus_inf;
     const double tol = bs->tol;
     const int max_iter = bs->max_iter;
@@ -271,34 +269,74 @@ __device__ bool run_instance(BatchState* __restrict__ bs, int inst, int rank, in
         const int active = __builtin_amdgcn_readfirstlane(sm.active);
         if (!active) break;
         const int copies = acc_copies(nacc);
-        for (int i = tid; i < copies * nacc; i += BLOCK) sm.acc[i] = 0ull;
-        __syncthreads();
-        points_pass<D, MODE_ACC>(in, rank, S, active, G, ninf, sm, jl);
-        __syncthreads();
-        if (copies > 1) {  // the copies summed into the first
-            for (int i = tid; i < nacc; i += BLOCK) {
-                unsigned long long s = sm.acc[i];
-                for (int c = 1; c < copies; ++c) s += sm.acc[c * nacc + i];
-                sm.acc[i] = s;
+        for (int64_t g0 = 0; g0 < ngroups; g0 += chunk) {
+            const int64_t g1 = g0 + chunk < ngroups ? g0 + chunk : ngroups;
+            for (int i = tid; i < copies * nacc; i += BLOCK) sm.acc[i] = 0ull;
+            __syncthreads();
+            points_pass<D, MODE_ACC>(in, rank, S, active, fscale, ninf, sm, jl, g0, g1);
+            __syncthreads();
+            // the chunk's sums: copies added, FXP_MAGIC_BITS removed once per
+            // point (the count slot of the same restart and cluster), added to
+            // the earlier chunks' in 128 bits (in this block's fold area, each
+            // slot always by the same thread)
+            i128 t[BK_ACC / BLOCK];
+#pragma unroll
+            for (int u = 0; u < BK_ACC / BLOCK; ++u) {
+                const int i = tid + u * BLOCK;
+                if (i >= nacc) break;
+                const int rj = i / K, k = i - rj * K;
+                const int r = rj / (D + 1), j = rj - r * (D + 1);
+                const int ic = (r * (D + 1) + D) * K + k;
+                unsigned long long n = 0ull;
+                for (int c = 0; c < copies; ++c) n += sm.acc[c * nacc + ic];
+                unsigned long long v = n;
+                if (j < D) {
+                    v = 0ull - n * FXP_MAGIC_BITS;
+                    for (int c = 0; c < copies; ++c) v += sm.acc[c * nacc + i];
+                }
+                t[u] = i128_of((long long)v);
+                if (g0 > 0) i128_add(t[u], i128{fold[2 * i], (long long)fold[2 * i + 1]});
+                if (g1 < ngroups) {
+                    fold[2 * i] = t[u].lo;
+                    fold[2 * i + 1] = (unsigned long long)t[u].hi;
+                }
             }
             __syncthreads();
+            if (g1 == ngroups) {
+                // the block's totals, as i128, into the accumulators' LDS
+                i128* tot = reinterpret_cast<i128*>(sm.acc);
+#pragma unroll
+                for (int u = 0; u < BK_ACC / BLOCK; ++u) {
+                    const int i = tid + u * BLOCK;
+                    if (i < nacc) tot[i] = t[u];
+                }
+                __syncthreads();
+            }
         }
         if (S > 1) {
+            // the team's sums: every block's 128-bit totals, added in rank order
             const uint32_t par = nbar & 1u;
-            unsigned long long* dst = tpart + ((size_t)par * S + rank) * BK_PART;
-            for (int i = tid; i < nacc; i += BLOCK) st_agent(&dst[i], sm.acc[i]);
+            i128* tot = reinterpret_cast<i128*>(sm.acc);
+            unsigned long long* dst = tpart + ((size_t)par * S + rank) * BK_PART * 2;
+            for (int i = tid; i < nacc; i += BLOCK) {
+                st_agent(&dst[2 * i], tot[i].lo);
+                st_agent(&dst[2 * i + 1], (unsigned long long)tot[i].hi);
+            }
             if (!team_barrier(bs, tm, nbar, S, &sm.flag)) return false;
-            const unsigned long long* src = tpart + (size_t)par * S * BK_PART;
+            const unsigned long long* src = tpart + (size_t)par * S * BK_PART * 2;
             for (int i = tid; i < nacc; i += BLOCK) {
                 // all S device-coherent loads in flight before the first add
-                unsigned long long v[BK_TEAM_MAX];
+                unsigned long long v[2 * BK_TEAM_MAX];
 #pragma unroll
-                for (int q = 0; q < BK_TEAM_MAX; ++q)
-                    v[q] = q < S ? ld_agent(&src[(size_t)q * BK_PART + i]) : 0ull;
-                unsigned long long s = 0ull;
+                for (int q = 0; q < BK_TEAM_MAX; ++q) {
+                    const unsigned long long* e = &src[((size_t)q * BK_PART + i) * 2];
+                    v[2 * q] = q < S ? ld_agent(&e[0]) : 0ull;
+                    v[2 * q + 1] = q < S ? ld_agent(&e[1]) : 0ull;
+                }
+                i128 sum = {0ull, 0ll};
 #pragma unroll
-                for (int q = 0; q < BK_TEAM_MAX; ++q) s += v[q];
-                sm.acc[i] = s;
+                for (int q = 0; q < BK_TEAM_MAX; ++q) i128_add(sum, i128{v[2 * q], (long long)v[2 * q + 1]});
+                tot[i] = sum;
             }
             __syncthreads();
         }
@@ -306,14 +344,14 @@ __device__ bool run_instance(BatchState* __restrict__ bs, int inst, int rank, in
         for (int i = tid; i < R * K; i += BLOCK) {
             const int r = i / K, k = i - r * K;
             if (!((active >> r) & 1)) continue;
-            const unsigned long long* a = &sm.acc[r * (D + 1) * K + k];
-            const unsigned long long cnt = a[D * K];
+            const i128* a = reinterpret_cast<const i128*>(sm.acc) + r * (D + 1) * K + k;
+            const unsigned long long cnt = a[D * K].lo;
             double e = 0.0;
             float m32[3] = {0.f, 0.f, 0.f};
 #pragma unroll
             for (int j = 0; j < D; ++j) {
                 const double old = sm.mu64[r][k * D + j];
-                const double v = cnt ? ldexp((double)(long long)a[j * K], -G) / (double)cnt : old;
+                const double v = cnt ? fxp_mean(a[j * K], xe, cnt) : old;
                 const double sh = v - old;
                 e = fma(sh, sh, e);
                 sm.mu64[r][k * D + j] = v;
@@ -348,7 +386,7 @@ __device__ bool run_instance(BatchState* __restrict__ bs, int inst, int rank, in
         for (int r = 0; r < R; ++r) prep_centres(sm.smu[r], K, sm.scand[r], &sm.sbnd[r], sm.sc, sm.sa, am);
         for (int r = 0; r < R; ++r) {
             jl = 0.0;
-            points_pass<D, MODE_OBJ>(in, rank, S, 1 << r, G, ninf, sm, jl);
+            points_pass<D, MODE_OBJ>(in, rank, S, 1 << r, fscale, ninf, sm, jl, 0, ngroups);
             block_objective(sm, r, jl);
         }
         if (S > 1) {
@@ -374,7 +412,8 @@ __device__ bool run_instance(BatchState* __restrict__ bs, int inst, int rank, in
             if (sm.J[r] < sm.J[best]) best = r;
         best = __builtin_amdgcn_readfirstlane(best);
         // ---- labels of the kept restart
-        if (in.labels) points_pass<D, MODE_LABEL>(in, rank, S, 1 << best, G, ninf, sm, jl);
+        if (in.labels)
+            points_pass<D, MODE_LABEL>(in, rank, S, 1 << best, fscale, ninf, sm, jl, 0, ngroups);
         if (rank == 0) {
             if (tid < R) {
                 BOut o;
@@ -390,7 +429,8 @@ __device__ bool run_instance(BatchState* __restrict__ bs, int inst, int rank, in
             if (tid == 0) bs->best[inst] = best;
         }
     } else if (rank == 0 && tid < R) {
-        BOut o = {-1, 0, 0, 0.0, 0.0};  // NaN or infinity in this instance's points
+        // -1: NaN or infinity in this instance's points; -2: max|x| >= 2^28
+        BOut o = {am >= 0x7f800000u ? -1 : -2, 0, 0, 0.0, 0.0};
         bs->out[(size_t)inst * BK_RMAX + tid] = o;
         if (tid == 0) bs->best[inst] = 0;
     }
@@ -471,7 +511,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
     if (S > 1 && b < bs->n_teams * S) {
         const int ti = b / S, rank = b - ti * S;
         BTeam* tm = &bs->teams[ti];
-        unsigned long long* tpart = bs->tpart + (size_t)ti * 2 * S * BK_PART;
+        unsigned long long* tpart = bs->tpart + (size_t)ti * 2 * S * BK_PART * 2;
         double* tjpart = bs->tjpart + (size_t)ti * 2 * S * BK_RMAX;
         for (;;) {
             if (rank == 0 && threadIdx.x == 0) {

@@ -82,6 +82,9 @@ int check_device_ptr(kmeans_ctx* c, const void* p, const char* what);
 int ensure_hist(kmeans_ctx* c, int cap);
 // At least n timing events in c->ev (kmeans_api.hip).
 int ensure_events(kmeans_ctx* c, size_t n);
+// Records the error of a fit whose data exceed the range of the fixed-point
+// cluster sums (FLAG_RANGE) and returns KM_EUNSUPPORTED (kmeans_api.hip).
+int range_error(kmeans_ctx* c);
 // True when (d, K) takes the general-shape fit: d not in {2, 3}, K > KMAX,
 // or KM_OPT_WIDE set (kmeans_api.hip).
 bool wide_shape(const kmeans_ctx* c, int d, int K);

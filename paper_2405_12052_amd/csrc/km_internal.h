@@ -18,7 +18,17 @@ constexpr int KPAD = 66;          // KMAX rounded up to whole triples of centres
 constexpr int PART = KMAX * (DMAX + 1);  // int64 slots of one block partial
 
 // Status flags written by the device.
-enum : int32_t { FLAG_NONFINITE = 1, FLAG_TIMEOUT = 2 };
+// Fixed-point cluster sums (see lloyd_device.h): |q| < 2^FXP_BITS per
+// coordinate, at most FXP_BLOCK_POINTS points per int64 slot of a block, data
+// with max|x| >= 2^28 (FXP_RANGE_BITS, float32 bits) refused by fits.
+constexpr int FXP_BITS = 44;
+constexpr int64_t FXP_BLOCK_POINTS = (int64_t)1 << 19;
+constexpr uint32_t FXP_RANGE_BITS = 0x4d800000u;
+
+// FLAG_RANGE: max|x| >= 2^28, beyond the range in which the fixed-point
+// cluster sums guarantee the centre tolerance (lloyd_device.h); fits stop
+// before their first update.
+enum : int32_t { FLAG_NONFINITE = 1, FLAG_TIMEOUT = 2, FLAG_RANGE = 4 };
 
 // One fit (or one reassignment pass) lives in this struct in device memory.
 // The host writes the problem fields and the initial centres before the
@@ -35,8 +45,9 @@ struct alignas(16) State {
     int32_t max_iter;
     int32_t hist_cap;      // entries of E_hist / J_hist
     double* jpart;         // [MAX_BLOCKS] per-block objective partials
-    unsigned long long* part;   // [MAX_BLOCKS][PART] per-block sums | counts
-    unsigned long long* gpart;  // [MAX_GROUPS][PART] per-group sums | counts
+    unsigned long long* part;   // [MAX_BLOCKS][PART] per-block sums | counts (int64)
+    unsigned long long* gpart;  // [MAX_GROUPS][PART][2] per-group sums | counts (128-bit:
+                                // lo, hi)
     double* gjpart;        // [MAX_GROUPS] per-group objective partials
     uint32_t* gticket;     // [MAX_GROUPS] blocks finished per group
     double* E_hist;        // [hist_cap]
@@ -45,7 +56,8 @@ struct alignas(16) State {
     int32_t t;             // updates performed
     int32_t done;          // 1: no further update runs
     int32_t flags;         // FLAG_*
-    int32_t G;             // fixed-point exponent of the per-cluster sums
+    int32_t xe;            // ilogb(max|x|) (-1 for all-zero data): the fixed-point
+                           // exponent of the per-cluster sums is 43 - xe
     double E;              // E of the last update
     double J;              // objective of the last reassignment-only pass
     int64_t empty_events;  // clusters left empty, summed over updates
@@ -121,7 +133,8 @@ struct BatchState {
     BOut* out;                 // [n_inst][BK_RMAX]
     int32_t* best;             // [n_inst] restart with the smallest objective
     double* best_mu;           // [n_inst][BK_KMAX * DMAX] its final centres
-    unsigned long long* tpart; // [n_teams][2][team_size][BK_PART]
+    unsigned long long* tpart; // [n_teams][2][team_size][BK_PART][2] (128-bit: lo, hi)
+    unsigned long long* fold;  // [grid][BK_PART][2] block-private 128-bit chunk sums
     double* tjpart;            // [n_teams][2][team_size][BK_RMAX]
     BTeam* teams;              // [n_teams]
 };

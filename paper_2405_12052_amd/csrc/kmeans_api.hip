@@ -80,6 +80,12 @@ int km::ensure_events(kmeans_ctx* c, size_t n) {
     return KM_OK;
 }
 
+int km::range_error(kmeans_ctx* c) {
+    return fail(c, KM_EUNSUPPORTED,
+                "max|x| >= 2^28: the fixed-point cluster sums (|x| 2^F < 2^44) would not "
+                "guarantee the centres to 1e-5 of a cluster near the origin; scale the data");
+}
+
 bool km::wide_shape(const kmeans_ctx* c, int d, int K) {
     return c->wide != 0 || (d != 2 && d != 3) || K > km::KMAX;
 }
@@ -123,7 +129,15 @@ bool vec_ok(const float* X, int64_t ld) {
 // reduction), so blocks with few points lose: measured per update at K = 16,
 // N = 4e6: 512 blocks 37.2 us, 3907 blocks 46.9 us; N = 1e7: 1024 blocks
 // 52.9 us, 4096 blocks 64.7 us; at N = 2e8, K = 64 the 16 per unit cap
-// (4096 blocks) is best.
+// (4096 blocks) is best.  Whatever the cap (KM_OPT_BLOCKS included), the grid
+// is at least min_blocks(N), so that no block adds more than
+// FXP_BLOCK_POINTS points into its int64 sums.
+int64_t min_blocks(int64_t N) {
+    const int64_t groups = (N + 3) / 4;
+    const int64_t per_block = km::FXP_BLOCK_POINTS / 4;  // groups of 4 points
+    return (groups + per_block - 1) / per_block;
+}
+
 int grid_for(kmeans_ctx* c, int64_t N) {
     const int64_t groups = (N + 3) / 4;
     const int64_t need = (groups + km::BLOCK - 1) / km::BLOCK;
@@ -136,7 +150,9 @@ int grid_for(kmeans_ctx* c, int64_t N) {
         cap = want < lo ? lo : (want > hi ? hi : want);
     }
     if (cap > km::MAX_BLOCKS) cap = km::MAX_BLOCKS;
-    const int64_t g = need < cap ? need : cap;
+    int64_t g = need < cap ? need : cap;
+    const int64_t lo = min_blocks(N);  // <= MAX_BLOCKS for N < 2^31
+    if (g < lo) g = lo;
     return (int)(g < 1 ? 1 : g);
 }
 
@@ -293,7 +309,7 @@ int kmeans_create(kmeans_ctx** out, int device, void* hip_stream, uint32_t flags
     } else if (hipMalloc(&c->st, sizeof(State)) != hipSuccess ||
                hipMalloc(&c->jpart, sizeof(double) * km::MAX_BLOCKS) != hipSuccess ||
                hipMalloc(&c->part, sizeof(unsigned long long) * km::PART * km::MAX_BLOCKS) != hipSuccess ||
-               hipMalloc(&c->gpart, sizeof(unsigned long long) * km::PART * km::MAX_GROUPS) != hipSuccess ||
+               hipMalloc(&c->gpart, sizeof(unsigned long long) * 2 * km::PART * km::MAX_GROUPS) != hipSuccess ||
                hipMalloc(&c->gjpart, sizeof(double) * km::MAX_GROUPS) != hipSuccess ||
                hipMalloc(&c->gticket, sizeof(uint32_t) * km::MAX_GROUPS) != hipSuccess) {
         rc = fail(nullptr, KM_ENOMEM, "hipMalloc of the workspace failed");
@@ -436,7 +452,7 @@ int kmeans_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int32_t d, 
         if (per_cu == 0) per_cu = km::persist_max_blocks_per_cu(d, vec);
         const int cap = c->n_cu * per_cu;
         const int pgrid = grid < cap ? grid : cap;
-        if (pgrid >= 1) {
+        if (pgrid >= 1 && pgrid >= min_blocks(N)) {
             if (c->timing) {
                 rc = ensure_events(c, 2);
                 if (rc) return rc;
@@ -507,6 +523,7 @@ int kmeans_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int32_t d, 
         c->iter_kernels = persisted ? T : launched;
     }
     if (h->flags & km::FLAG_NONFINITE) return fail(c, KM_EINVAL, "X holds a NaN or an infinity");
+    if (h->flags & km::FLAG_RANGE) return km::range_error(c);
     memcpy(centroids_out, h->mu64, sizeof(double) * (size_t)K * d);
     if (res) {
         res->iters = T;

@@ -58,12 +58,74 @@ __device__ __forceinline__ void st_agent(T* p, T v) {
 // Wait until this thread's memory operations have completed.
 __device__ __forceinline__ void wait_mem() { __builtin_amdgcn_s_waitcnt(0); }
 
-// Fixed-point exponent: every |x| * 2^G < 2^30 for |x| <= max|x|.
-__device__ __forceinline__ int scale_exponent(uint32_t absmax_bits) {
-    float a = __uint_as_float(absmax_bits);
-    if (!(a > 0.0f)) return 30;
-    int G = 29 - ilogbf(a);  // a < 2^(ilogb(a)+1)
-    return G > 120 ? 120 : G;
+// Exponent of the data's magnitude: ilogb(max|x|), so max|x| < 2^(xe+1);
+// -1 for all-zero data.
+__device__ __forceinline__ int data_exponent(uint32_t absmax_bits) {
+    const float a = __uint_as_float(absmax_bits);
+    return a > 0.0f ? ilogbf(a) : -1;
+}
+
+// ---------------------------------------------------------------------------
+// Per-cluster sums in fixed point (the numerators of the paper's mean step).
+//
+// Every coordinate enters as the integer q = rint(x 2^F), F = FXP_BITS - 1 -
+// xe, so |q| < 2^44 (x 2^F is a float32 scaled by a power of two: exact, and
+// an integer once it reaches 2^23).  Integer sums are exact in any order, so
+// the means do not depend on the schedule.  One int64 slot of a block never
+// receives more than FXP_BLOCK_POINTS = 2^19 points between two readings
+// (|sum| < 2^63); sums over blocks are carried in 128 bits.  The rounding
+// moves each mean coordinate by at most 2^(xe-44) <= max|x| 2^-44 from the
+// exact mean, below the 1e-5 centre tolerance of any cluster (a cluster at
+// the origin included) while xe <= 27: fits refuse data with max|x| >= 2^28
+// (FXP_RANGE_BITS) rather than return means that could miss it.
+//
+// The conversion is one float64 FMA: x 2^F + 1.5 2^52 rounds to an integer
+// (the spacing of doubles in [2^52, 2^53) is 1) whose bit pattern is
+// FXP_MAGIC_BITS + q for |q| < 2^51.  The accumulators add those bit patterns
+// as 64-bit integers; a slot that received n points is corrected by
+// subtracting n FXP_MAGIC_BITS (mod 2^64) when it is read.
+// (FXP_BITS, FXP_BLOCK_POINTS and FXP_RANGE_BITS are in km_internal.h.)
+constexpr double FXP_MAGIC = 0x1.8p52;
+constexpr unsigned long long FXP_MAGIC_BITS = 0x4338000000000000ull;
+
+// 2^F for data of exponent xe.
+__device__ __forceinline__ double fxp_scale(int xe) { return ldexp(1.0, FXP_BITS - 1 - xe); }
+
+// FXP_MAGIC_BITS + rint(x 2^F) (mod 2^64), scale = 2^F.
+__device__ __forceinline__ unsigned long long fxp_bits(float x, double scale) {
+    return (unsigned long long)__double_as_longlong(fma((double)x, scale, FXP_MAGIC));
+}
+
+// A signed 128-bit integer: value = hi 2^64 + lo.
+struct i128 {
+    unsigned long long lo;
+    long long hi;
+};
+
+__device__ __forceinline__ i128 i128_of(long long v) {
+    return i128{(unsigned long long)v, v >> 63};
+}
+
+__device__ __forceinline__ void i128_add(i128& a, const i128& b) {
+    const unsigned long long lo = a.lo + b.lo;
+    a.hi += b.hi + (lo < a.lo ? 1 : 0);
+    a.lo = lo;
+}
+
+// The double nearest to v (|v| < 2^116): hi 2^64 and the upper 32 bits of
+// lo add exactly (at most 53 significant bits), the lower 32 bits are added
+// with the one rounding.
+__device__ __forceinline__ double i128_to_double(const i128& v) {
+    const double a = ldexp((double)v.hi, 64);
+    const double b = ldexp((double)(v.lo >> 32), 32);
+    const double c = (double)(v.lo & 0xffffffffull);
+    return (a + b) + c;
+}
+
+// Mean of a cluster from the 128-bit sum of its q and its count n > 0:
+// (S 2^-F) / n in float64.
+__device__ __forceinline__ double fxp_mean(const i128& S, int xe, unsigned long long n) {
+    return ldexp(i128_to_double(S), -(FXP_BITS - 1 - xe)) / (double)n;
 }
 
 // Load the 4 consecutive points of group g (coordinates x[j][p]); returns how

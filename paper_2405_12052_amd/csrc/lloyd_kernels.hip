@@ -5,8 +5,9 @@
 // successive centres, tolerance test).
 //
 // Kernels
-//   km_scan      one pass over X: max |x| (sets the fixed-point exponent G and
-//                flags NaN/Inf); prepares the centre tables.
+//   km_scan      one pass over X: max |x| (sets the exponent of the fixed-point
+//                sums, flags NaN/Inf and data beyond their range); prepares
+//                the centre tables.
 //   lloyd_iter   one whole update: reassignment of every point, per-cluster
 //                integer sums and counts in LDS, one partial per block, a
 //                two-level reduction of the partials by the last block of each
@@ -18,10 +19,10 @@
 //
 // Reassignment: see lloyd_device.h.
 //
-// Determinism: the per-cluster sums are exact integer sums of x * 2^G
-// (|x| * 2^G < 2^30, rounded to nearest), so their value does not depend on
-// the order in which points, waves or blocks add them: results are identical
-// for any grid size and from run to run, without float atomics.  The
+// Determinism: the per-cluster sums are exact integer sums of rint(x 2^F)
+// (|x| 2^F < 2^44, lloyd_device.h), so their value does not depend on the
+// order in which points, waves or blocks add them: results are identical for
+// any grid size and from run to run, without float atomics.  The
 // objective (reported, not fed back) is summed per lane, reduced across the
 // wave with a fixed butterfly and across waves, blocks and groups in index
 // order.
@@ -61,35 +62,34 @@ __device__ double sum_partials(const double* __restrict__ jpart, int nb, double*
     return tot;
 }
 
-// For every entry i < nr: the integer sum over q < n of the partial P(q, i),
-// into out[i] (LDS).  The loads are spread over the whole block -- each
-// thread takes a slice of q for one entry, 8 device-coherent loads in
+// For every entry i < nr: the sum over q < n of the partial P(q, i) (an
+// i128), into out[i] (LDS).  The loads are spread over the whole block --
+// each thread takes a slice of q for one entry, 8 device-coherent loads in
 // flight at a time -- and the slices are added in LDS (integer sums: the
 // order does not matter).  scr: LDS scratch of BLOCK values.
 template <typename F>
-__device__ __forceinline__ void sum_entries(int n, int nr, F P, unsigned long long* out,
-                            unsigned long long* scr) {
+__device__ __forceinline__ void sum_entries(int n, int nr, F P, i128* out, i128* scr) {
     const int tid = threadIdx.x;
     const int S = BLOCK / nr;                 // slices per entry (nr <= BLOCK)
     const int slice = tid / nr, i = tid - slice * nr;
-    unsigned long long s = 0ull;
+    i128 s = {0ull, 0ll};
     if (slice < S) {
         const int per = (n + S - 1) / S;
         const int q0 = slice * per;
         const int q1 = q0 + per < n ? q0 + per : n;
         for (int qb = q0; qb < q1; qb += 8) {
-            unsigned long long t[8];
+            i128 t[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) t[u] = qb + u < q1 ? P(qb + u, i) : 0ull;
+            for (int u = 0; u < 8; ++u) t[u] = qb + u < q1 ? P(qb + u, i) : i128{0ull, 0ll};
 #pragma unroll
-            for (int u = 0; u < 8; ++u) s += t[u];
+            for (int u = 0; u < 8; ++u) i128_add(s, t[u]);
         }
     }
     scr[tid] = s;
     __syncthreads();
     for (int j = tid; j < nr; j += BLOCK) {
-        unsigned long long t = 0ull;
-        for (int sl = 0; sl < S; ++sl) t += scr[sl * nr + j];
+        i128 t = {0ull, 0ll};
+        for (int sl = 0; sl < S; ++sl) i128_add(t, scr[sl * nr + j]);
         out[j] = t;
     }
     __syncthreads();
@@ -111,19 +111,21 @@ __device__ __forceinline__ double sum_in_order(int n, const double* p, double* s
 constexpr int ONE_LEVEL_LOADS = 16 * BLOCK;
 
 // Two-level reduction of the block partials (integer sums | counts, and the
-// objective).  Every block publishes its partial; the last block of each
-// group of GROUP blocks adds the group's partials; the last group adds the
+// objective).  Every block publishes its partial (int64: a block adds at
+// most FXP_BLOCK_POINTS points); the last block of each group of GROUP
+// blocks adds the group's partials in 128 bits; the last group adds the
 // group sums.  With at most MAX_GROUPS blocks and ONE_LEVEL_LOADS partial
-// entries in all, the last block of the grid adds the partials directly.  Returns true in that one final block, with the grid totals in
-// tot[0..nr) (LDS) and the objective in *jtot.  No two blocks add to the same
-// address, so there is no contention; the integer sums are exact in any order
-// and the objective is added in block, then group, order.  Partials move as
-// device-coherent stores and loads (see lloyd_device.h).
-__device__ __forceinline__ bool reduce_grid(State* __restrict__ st, const unsigned long long* blk, int nr,
-                            double jb, unsigned long long* tot, double* jtot, int* sflag) {
-    __shared__ unsigned long long scr[BLOCK];
-    __shared__ unsigned long long gsum[PART];
-    __shared__ double sj[MAX_GROUPS];
+// entries in all, the last block of the grid adds the partials directly.
+// Returns true in that one final block, with the grid totals in tot[0..nr)
+// (LDS) and the objective in *jtot.  No two blocks add to the same address,
+// so there is no contention; the integer sums are exact in any order and the
+// objective is added in block, then group, order.  Partials move as
+// device-coherent stores and loads (see lloyd_device.h).  acc: LDS of nr
+// i128 for the group sums and the totals; scr, sj: LDS scratch of BLOCK
+// i128 and MAX_GROUPS doubles.
+__device__ __forceinline__ bool reduce_grid(State* __restrict__ st, const unsigned long long* blk,
+                                            int nr, double jb, i128* acc, i128* scr, double* sj,
+                                            double* jtot, int* sflag) {
     const int tid = threadIdx.x;
     const int b = blockIdx.x, nb = gridDim.x;
     unsigned long long* mine = st->part + (size_t)b * PART;
@@ -131,6 +133,10 @@ __device__ __forceinline__ bool reduce_grid(State* __restrict__ st, const unsign
     if (tid == 0) st_agent(&st->jpart[b], jb);
     wait_mem();
     __syncthreads();
+    const unsigned long long* part = st->part;
+    auto block_partial = [&](int q, int i) {
+        return i128_of((long long)ld_agent(&part[(size_t)q * PART + i]));
+    };
     if (nb <= MAX_GROUPS && nb * nr <= ONE_LEVEL_LOADS) {
         // few partials: the last block of the grid adds them all (one round
         // trip of device-coherent exchanges fewer)
@@ -141,9 +147,7 @@ __device__ __forceinline__ bool reduce_grid(State* __restrict__ st, const unsign
         }
         __syncthreads();
         if (!*sflag) return false;
-        const unsigned long long* part = st->part;
-        sum_entries(nb, nr, [&](int q, int i) { return ld_agent(&part[(size_t)q * PART + i]); },
-                    tot, scr);
+        sum_entries(nb, nr, block_partial, acc, scr);
         const double jt = sum_in_order(nb, st->jpart, sj);
         if (tid == 0) {
             *jtot = jt;
@@ -161,11 +165,13 @@ __device__ __forceinline__ bool reduce_grid(State* __restrict__ st, const unsign
     }
     __syncthreads();
     if (!*sflag) return false;
-    // last block of its group
-    const unsigned long long* part = st->part;
-    sum_entries(gn, nr, [&](int q, int i) { return ld_agent(&part[(size_t)(g0 + q) * PART + i]); },
-                gsum, scr);
-    for (int i = tid; i < nr; i += BLOCK) st_agent(&st->gpart[(size_t)grp * PART + i], gsum[i]);
+    // last block of its group: the group's sums (128-bit, as lo / hi words)
+    sum_entries(gn, nr, [&](int q, int i) { return block_partial(g0 + q, i); }, acc, scr);
+    unsigned long long* gmine = st->gpart + (size_t)grp * PART * 2;
+    for (int i = tid; i < nr; i += BLOCK) {
+        st_agent(&gmine[2 * i], acc[i].lo);
+        st_agent(&gmine[2 * i + 1], (unsigned long long)acc[i].hi);
+    }
     const double jg = sum_in_order(gn, st->jpart + g0, sj);
     if (tid == 0) {
         st_agent(&st->gjpart[grp], jg);
@@ -183,8 +189,10 @@ __device__ __forceinline__ bool reduce_grid(State* __restrict__ st, const unsign
     if (!*sflag) return false;
     // the final block
     const unsigned long long* gpart = st->gpart;
-    sum_entries(ng, nr, [&](int q, int i) { return ld_agent(&gpart[(size_t)q * PART + i]); },
-                tot, scr);
+    sum_entries(ng, nr, [&](int q, int i) {
+        const unsigned long long* e = &gpart[((size_t)q * PART + i) * 2];
+        return i128{ld_agent(&e[0]), (long long)ld_agent(&e[1])};
+    }, acc, scr);
     const double jt = sum_in_order(ng, st->gjpart, sj);
     if (tid == 0) {
         *jtot = jt;
@@ -236,9 +244,12 @@ __global__ __launch_bounds__(BLOCK) void km_scan(State* __restrict__ st) {
     prep_centres(st->mu32, st->K, st->cand, &st->bnd, sc, sa, a);
     for (int i = tid; i < MAX_GROUPS; i += BLOCK) st->gticket[i] = 0u;
     if (tid == 0) {
-        st->G = scale_exponent(a);
+        st->xe = data_exponent(a);
         if (a >= 0x7f800000u) {  // NaN or infinity in X
             st->flags |= FLAG_NONFINITE;
+            st->done = 1;
+        } else if (a >= FXP_RANGE_BITS) {  // beyond the fixed-point sums' range
+            st->flags |= FLAG_RANGE;
             st->done = 1;
         }
         st->scan_ticket = 0;
@@ -253,12 +264,12 @@ template <int D, bool VEC, int KT, typename Sink>
 __device__ __forceinline__ void scan_points(const float* __restrict__ X, int64_t ld, int64_t N,
                                             const float4* __restrict__ scand,
                                             const float4* __restrict__ smu, int K,
-                                            float4 bnd, float ninf, int G,
+                                            float4 bnd, float ninf, int xe,
                                             float4* __restrict__ wq, Sink&& sink) {
     if constexpr (KT == 0)
         assign_points<D, VEC>(X, ld, N, scand, smu, K, bnd, ninf, wq, sink);
     else
-        assign_points_mfma<D, VEC, KT>(X, ld, N, scand, smu, K, bnd, ninf, G, wq, sink);
+        assign_points_mfma<D, VEC, KT>(X, ld, N, scand, smu, K, bnd, ninf, xe, wq, sink);
 }
 
 // ---------------------------------------------------------------- lloyd_iter
@@ -275,21 +286,36 @@ constexpr int ACC_COPY_MAX = 16;
 struct IterSmem {
     float4 scand[KPAD];
     float4 smu[KMAX];
-    // copy c at [c * K * (d+1)], coordinate-major inside: slot j * K + k
+    // copy c at [c * K * (d+1)], coordinate-major inside: slot j * K + k.
+    // After the pass: the group sums and grid totals of the reduction
+    // (KMAX * (DMAX + 1) i128, the same bytes).
     unsigned long long sacc[ACC_SLOTS];
     unsigned int scnt[ACC_SLOTS / 2];  // counts, 32-bit: copy c at [c * K], slot k
-    unsigned long long stot[KMAX * (DMAX + 1)];
-    float4 squeue[NW][QCAP];
+    // storage used in turn by the scan (re-scan queues), the block totals
+    // until they are published, the reduction's scratch, and the final
+    // block's update
+    union {
+        float4 squeue[NW][QCAP];
+        unsigned long long stot[KMAX * (DMAX + 1)];
+        struct {
+            i128 scr[BLOCK];
+            double sj[MAX_GROUPS];
+        } red;
+        struct {
+            double sE[KMAX];
+            int sEmpty[KMAX];
+            float sc[KPAD];
+            float sa[3 * KPAD];
+        } fin;
+    } u;
     double sred[NW];
-    double sE[KMAX];
-    int sEmpty[KMAX];
-    float sc[KPAD];
-    float sa[3 * KPAD];
     float4 sbnd;
     double sJ;
     int sflag;
     int sdone;
 };
+static_assert(sizeof(unsigned long long) * ACC_SLOTS >= sizeof(i128) * KMAX * (DMAX + 1),
+              "the accumulators hold the grid totals");
 
 // float4 through four device-coherent 32-bit accesses (lloyd_device.h).
 __device__ __forceinline__ void st4_agent(float4* p, float4 v) {
@@ -326,7 +352,7 @@ __device__ __forceinline__ void wr4(float4* p, float4 v) {
 // the one final block, with the grid's integer sums | counts in sm.sacc
 // and the objective of this pass in sm.sJ.
 template <int D, bool VEC, int KT>
-__device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm, int K, int G,
+__device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm, int K, int xe,
                             float4 bnd, float ninf) {
     constexpr int R = D + 1;  // per cluster: D sums, 1 count
     const int tid = threadIdx.x, w = tid >> 6;
@@ -339,9 +365,10 @@ __device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm
     __syncthreads();
 
     double jl = 0.0;
+    const double fscale = fxp_scale(xe);
     unsigned long long* myacc = &sm.sacc[(tid % copies) * KR];
     unsigned int* mycnt = &sm.scnt[(tid % copies) * K];
-    scan_points<D, VEC, KT>(X, ld, N, sm.scand, sm.smu, K, bnd, ninf, G, sm.squeue[w],
+    scan_points<D, VEC, KT>(X, ld, N, sm.scand, sm.smu, K, bnd, ninf, xe, sm.u.squeue[w],
                             [&](int64_t, float x0, float x1, float x2, int k, float dist) {
         // coordinate-major slots [j * K + k]: the 64 lanes' clusters spread
         // over the LDS banks (a cluster-major stride of 4 int64 would put
@@ -349,31 +376,34 @@ __device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm
         unsigned long long* a = &myacc[k];
         const float xs[3] = {x0, x1, x2};
 #pragma unroll
-        for (int j = 0; j < D; ++j) {
-            const long long q = (long long)__float2int_rn(ldexpf(xs[j], G));
-            __hip_atomic_fetch_add(&a[j * K], (unsigned long long)q, __ATOMIC_RELAXED,
+        for (int j = 0; j < D; ++j)
+            __hip_atomic_fetch_add(&a[j * K], fxp_bits(xs[j], fscale), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
         __hip_atomic_fetch_add(&mycnt[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         jl += (double)dist;
     });
     jl = wave_sum(jl);
     if ((tid & 63) == 0) sm.sred[w] = jl;
     __syncthreads();
-    for (int i = tid; i < K * R; i += BLOCK) {  // block totals, cluster-major [k * R + j]
+    // block totals, cluster-major [k * R + j]: the sums of q (each slot less
+    // FXP_MAGIC_BITS per point it received) and the counts
+    for (int i = tid; i < K * R; i += BLOCK) {
         const int k = i / R, j = i - k * R;
-        unsigned long long s = 0ull;
-        if (j < D)
+        unsigned long long n = 0ull;
+        for (int c = 0; c < copies; ++c) n += sm.scnt[c * K + k];
+        unsigned long long s = n;
+        if (j < D) {
+            s = 0ull - n * FXP_MAGIC_BITS;
             for (int c = 0; c < copies; ++c) s += sm.sacc[c * KR + j * K + k];
-        else
-            for (int c = 0; c < copies; ++c) s += sm.scnt[c * K + k];
-        sm.stot[i] = s;
+        }
+        sm.u.stot[i] = s;
     }
     double jb = 0.0;
 #pragma unroll
     for (int v = 0; v < NW; ++v) jb += sm.sred[v];
     __syncthreads();
-    return reduce_grid(st, sm.stot, K * R, jb, sm.sacc, &sm.sJ, &sm.sflag);
+    return reduce_grid(st, sm.u.stot, K * R, jb, reinterpret_cast<i128*>(sm.sacc), sm.u.red.scr,
+                       sm.u.red.sj, &sm.sJ, &sm.sflag);
 }
 
 // The final block's update (the paper's mean-calculation step, its error E
@@ -383,20 +413,19 @@ __device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm
 // state is also read by other blocks of a persistent kernel, so every access
 // to it is device-coherent.
 template <int D, bool COH>
-__device__ __forceinline__ void finalize_update(State* __restrict__ st, IterSmem& sm, int K, int G) {
+__device__ __forceinline__ void finalize_update(State* __restrict__ st, IterSmem& sm, int K, int xe) {
     constexpr int R = D + 1;
     const int tid = threadIdx.x;
-    const unsigned long long* tot = sm.sacc;
+    const i128* tot = reinterpret_cast<const i128*>(sm.sacc);
     if (tid < K) {
         const int k = tid;
-        const unsigned long long cnt = tot[k * R + D];
+        const unsigned long long cnt = tot[k * R + D].lo;
         double e = 0.0;
         float m32[DMAX] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-            const long long s = (long long)tot[k * R + j];
             const double old = rd<COH>(&st->mu64[k * D + j]);
-            const double v = cnt ? ldexp((double)s, -G) / (double)cnt : old;
+            const double v = cnt ? fxp_mean(tot[k * R + j], xe, cnt) : old;
             const double sh = v - old;
             e = fma(sh, sh, e);
             wr<COH>(&st->mu64[k * D + j], v);
@@ -405,18 +434,18 @@ __device__ __forceinline__ void finalize_update(State* __restrict__ st, IterSmem
         const float4 m = make_float4(m32[0], m32[1], m32[2], 0.0f);
         wr4<COH>(&st->mu32[k], m);
         sm.smu[k] = m;
-        sm.sE[k] = e;
-        sm.sEmpty[k] = cnt == 0ull;
+        sm.u.fin.sE[k] = e;
+        sm.u.fin.sEmpty[k] = cnt == 0ull;
     }
     __syncthreads();
-    prep_centres(sm.smu, K, sm.scand, &sm.sbnd, sm.sc, sm.sa, st->absmax_bits);
+    prep_centres(sm.smu, K, sm.scand, &sm.sbnd, sm.u.fin.sc, sm.u.fin.sa, st->absmax_bits);
     const int ntri = (K + 2) / 3;
     for (int i = tid; i < 3 * ntri; i += BLOCK) wr4<COH>(&st->cand[i], sm.scand[i]);
     if (tid == 0) {
         wr4<COH>(&st->bnd, sm.sbnd);
         double E = 0.0;
         int emp = 0;
-        for (int k = 0; k < K; ++k) { E += sm.sE[k]; emp += sm.sEmpty[k]; }
+        for (int k = 0; k < K; ++k) { E += sm.u.fin.sE[k]; emp += sm.u.fin.sEmpty[k]; }
         const int t = rd<COH>(&st->t);
         if (t < st->hist_cap) { st->E_hist[t] = E; st->J_hist[t] = sm.sJ; }
         const int done = (E < st->tol || t + 1 >= st->max_iter) ? 1 : 0;
@@ -438,8 +467,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) v
     const int K = st->K;
     stage_centres(st, K, sm.scand, sm.smu);
     __syncthreads();
-    if (!update_pass<D, VEC, KT>(st, sm, K, st->G, st->bnd, st->minus_inf)) return;
-    finalize_update<D, false>(st, sm, K, st->G);
+    if (!update_pass<D, VEC, KT>(st, sm, K, st->xe, st->bnd, st->minus_inf)) return;
+    finalize_update<D, false>(st, sm, K, st->xe);
 }
 
 // The whole fit in one cooperative launch (every block resident), for small
@@ -458,14 +487,14 @@ __global__ __launch_bounds__(BLOCK) void lloyd_persist(State* __restrict__ st) {
     __shared__ IterSmem sm;
     const int tid = threadIdx.x;
     const int K = st->K;
-    const int G = st->G;
+    const int xe = st->xe;
     const float ninf = st->minus_inf;
     const int ntri = stage_centres(st, K, sm.scand, sm.smu);
     float4 bnd = st->bnd;
     __syncthreads();
     for (uint32_t round = 1;; ++round) {
-        if (update_pass<D, VEC, KT>(st, sm, K, G, bnd, ninf)) {
-            finalize_update<D, true>(st, sm, K, G);
+        if (update_pass<D, VEC, KT>(st, sm, K, xe, bnd, ninf)) {
+            finalize_update<D, true>(st, sm, K, xe);
             wait_mem();
             __syncthreads();
             if (tid == 0) st_agent(&st->gen, round);
@@ -523,7 +552,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) v
     stage_centres(st, K, scand, smu);
     __syncthreads();
     double jl = 0.0;
-    scan_points<D, VEC, KT>(X, ld, N, scand, smu, K, bnd, ninf, st->G, squeue[w],
+    scan_points<D, VEC, KT>(X, ld, N, scand, smu, K, bnd, ninf, st->xe, squeue[w],
                             [&](int64_t i, float, float, float, int k, float dist) {
         if (labels) labels[i] = k;
         jl += (double)dist;

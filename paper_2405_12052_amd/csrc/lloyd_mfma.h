@@ -177,13 +177,13 @@ __device__ __forceinline__ f16x8 point_column(float x0, float x1, float x2) {
 // Reassignment of the points of this wave's share of the grid (chunks of 128
 // points) with the matrix-core keys; same contract as assign_points (sink
 // receives every certified point, the others are re-scanned from the
-// per-wave queue).  G: the fixed-point exponent of the data (every
-// |x| < 2^(30-G)).
+// per-wave queue).  xe: the exponent of the data's magnitude (every
+// |x| < 2^(xe+1)).
 template <int D, bool VEC, int KT, typename Sink>
 __device__ __forceinline__ void assign_points_mfma(const float* __restrict__ X, int64_t ld,
                                                    int64_t N, const float4* __restrict__ scand,
                                                    const float4* __restrict__ smu, int K,
-                                                   float4 bnd, float ninf, int G,
+                                                   float4 bnd, float ninf, int xe,
                                                    float4* __restrict__ wq, Sink&& sink) {
     const int lane = threadIdx.x & 63;
     const int c = lane & 31, h = lane >> 5;
@@ -192,7 +192,7 @@ __device__ __forceinline__ void assign_points_mfma(const float* __restrict__ X, 
     // Scales: |x 2^ex| < 2^15 and |a 2^ea| < 2^15 (max |a_kj| = 2 max_kj |m_kj| <=
     // 2^21 max(bnd.yzw)); ex - ea <= 64 keeps every scaled key below 2^96.
     const float amax = ldexpf(fmaxf(fmaxf(bnd.y, bnd.z), bnd.w), 21);
-    int ex = G - 15;
+    int ex = 14 - xe < 105 ? 14 - xe : 105;
     int ea = amax > 0.0f ? 14 - ilogbf(amax) : ex;
     if (ex > ea + 64) ex = ea + 64;
 

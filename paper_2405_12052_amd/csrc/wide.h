@@ -7,9 +7,9 @@
 // Algorithm" and "Serial Lloyd's Algorithm"): reassignment by the first-index
 // argmin of the squared distance to the float32 centres in the direct form
 // evaluated in float64 (found through a certified expanded key, see
-// wide_kernels.hip), per-cluster exact integer sums of
-// x * 2^G, the float64 mean step with the empty-cluster rule, E and the
-// tolerance test.  Per update two kernels run: wide_update (reassignment and
+// wide_kernels.hip), per-cluster exact integer sums of rint(x 2^F)
+// (lloyd_device.h), the float64 mean step with the empty-cluster rule, E and
+// the tolerance test.  Per update two kernels run: wide_update (reassignment and
 // per-block sums) and wide_reduce (the partials summed into the totals by the
 // whole grid, then the mean step and the next pass's key tables in the last
 // block).
@@ -23,7 +23,7 @@ namespace km {
 constexpr int WD_MAX = 32;        // largest d
 constexpr int WK_MAX = 1024;      // largest K
 constexpr int WBLOCK = 256;       // threads per block of the wide kernels
-constexpr int WMAX_GRID = 1024;   // cap of the update grid (rows of partials)
+constexpr int WMAX_GRID = 4096;   // cap of the update grid (rows of partials)
 constexpr int WCHUNK = 32;        // partials summed per thread in wide_reduce
 constexpr int WLDS_MAX = 65536;   // dynamic LDS of one wide_update block
 constexpr int WQCAP = 128;        // re-scan queue entries per wave
@@ -71,8 +71,9 @@ struct alignas(16) WState {
     float* mu32;           // [K * stride] the same rounded to float32, zero padded
     float* hh;             // [Kpad] -|m_k|^2 / 2 of the float32 centres (pads: -2^127)
     float* amax;           // [WD_MAX + 1] max_k |m_kj| for j < d; [WD_MAX]: max_k |m_k|^2
-    unsigned long long* part;  // [grid][K * (d + 1)] per-block sums | counts
-    unsigned long long* tot;   // [K * (d + 1)] totals (zero between updates)
+    unsigned long long* part;  // [grid][K * (d + 1)] per-block sums | counts (int64)
+    unsigned long long* tot;   // [2][K * (d + 1)] totals as two limbs, value =
+                               // tot[1][i] 2^32 + tot[0][i] (zero between updates)
     double* jpart;         // [grid] per-block objective partials
     double* E_hist;        // [hist_cap]
     double* J_hist;        // [hist_cap]
@@ -87,7 +88,8 @@ struct alignas(16) WState {
     float plus_inf;        // +infinity, read at run time by the kernels
     int32_t pad1;
     // ---- device scratch ----
-    uint32_t absmax_bits;  // max |x| over the data, as float bits
+    uint32_t absmax_bits;  // max |x| over the data, as float bits (the exponent of
+                           // the fixed-point sums, lloyd_device.h)
     uint32_t ticket;       // blocks finished in the current kernel
 };
 

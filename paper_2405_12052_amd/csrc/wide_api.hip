@@ -62,7 +62,7 @@ int ensure_ws(kmeans_ctx* c) {
         hipHostMalloc(&w->mu_h, sizeof(double) * kMu64Max + sizeof(float) * kMu32Max, 0) != hipSuccess ||
         hipMalloc(&w->mu64, sizeof(double) * kMu64Max) != hipSuccess ||
         hipMalloc(&w->mu32, sizeof(float) * kMu32Max) != hipSuccess ||
-        hipMalloc(&w->tot, sizeof(unsigned long long) * kTotMax) != hipSuccess ||
+        hipMalloc(&w->tot, sizeof(unsigned long long) * 2 * kTotMax) != hipSuccess ||
         hipMalloc(&w->jpart, sizeof(double) * WMAX_GRID) != hipSuccess ||
         hipMalloc(&w->hh, sizeof(float) * (WK_MAX + 4)) != hipSuccess ||
         hipMalloc(&w->amax, sizeof(float) * (WD_MAX + 1)) != hipSuccess) {
@@ -92,15 +92,23 @@ int ensure_part(kmeans_ctx* c, size_t n) {
 
 int points_per_lane(int d) { return wide_width(d) <= 16 ? 4 : 2; }
 
+// Grid of wide_update: the resident blocks of the device (or KM_OPT_BLOCKS),
+// but never fewer than one block per FXP_BLOCK_POINTS points: a block takes
+// ceil(groups / (grid WBLOCK)) groups of P points per thread, at most
+// FXP_BLOCK_POINTS / (WBLOCK P) of them (N < 2^31 needs at most 4096 blocks).
 int update_grid(kmeans_ctx* c, int d, int K, int64_t N) {
     const size_t lds = wide_lds_bytes(d, K);
     int& b = c->wws->bpc[{wide_width(d), lds}];
     if (b == 0) b = wide_blocks_per_cu(d, lds);
     const int P = points_per_lane(d);
-    const int64_t need = ((N + P - 1) / P + WBLOCK - 1) / WBLOCK;
+    const int64_t groups = (N + P - 1) / P;
+    const int64_t need = (groups + WBLOCK - 1) / WBLOCK;
     int64_t cap = c->blocks > 0 ? c->blocks : (int64_t)c->n_cu * (b > 0 ? b : 1);
     if (cap > WMAX_GRID) cap = WMAX_GRID;
-    const int64_t g = need < cap ? need : cap;
+    int64_t g = need < cap ? need : cap;
+    const int64_t per_block = FXP_BLOCK_POINTS / P;  // groups of one block
+    const int64_t lo = (groups + per_block - 1) / per_block;
+    if (g < lo) g = lo;
     return g < 1 ? 1 : (int)g;
 }
 
@@ -281,6 +289,7 @@ int wide_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, int K,
         c->iter_kernels = launched;
     }
     if (h->flags & FLAG_NONFINITE) return fail(c, KM_EINVAL, "X holds a NaN or an infinity");
+    if (h->flags & FLAG_RANGE) return range_error(c);
     memcpy(centroids_out, m64, sizeof(double) * (size_t)K * d);
     if (res) {
         res->iters = T;

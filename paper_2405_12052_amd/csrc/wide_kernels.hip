@@ -14,13 +14,15 @@
 // LDS and are read as wave-uniform (broadcast) float4s, each serving the P
 // points of every lane.
 //
-// Mean step: the points' coordinates as integers rint(x * 2^G) (|x| * 2^G <
-// 2^30) and a count of one are added to their cluster's int64 slots in LDS
-// (coordinate-major, slot j * K + k); each block writes its K * (d + 1) slots
-// as one row of partials.
-// wide_reduce sums the rows over the grid, WCHUNK rows per thread, and adds
-// the chunk sums to the totals with device-scope integer atomics; integer
-// addition is exact, so the totals do not depend on the order.  The last
+// Mean step: the points' coordinates as integers rint(x 2^F) (|x| 2^F < 2^44,
+// lloyd_device.h) and a count of one are added to their cluster's int64
+// slots in LDS (coordinate-major, slot j * K + k; no block takes more than
+// FXP_BLOCK_POINTS points); each block writes its K * (d + 1) slots as one
+// row of partials.
+// wide_reduce sums the rows over the grid, WCHUNK rows per thread in 128
+// bits, and adds each chunk sum to the totals as two limbs (its low 32 bits
+// and the rest) with device-scope integer atomics; integer addition is exact,
+// so the totals do not depend on the order.  The last
 // block to finish divides in float64 (the paper's mean with its indicator
 // function), keeps the centre of an empty cluster, computes E (sum over the
 // centres of the squared shift) and applies the tolerance test.
@@ -389,7 +391,7 @@ __global__ __launch_bounds__(WBLOCK) void wide_scan(WState* __restrict__ st) {
     const int nacc = st->K * (d + 1);
     const int64_t stride = (int64_t)gridDim.x * WBLOCK;
     const int64_t t0 = (int64_t)blockIdx.x * WBLOCK + tid;
-    for (int64_t i = t0; i < nacc; i += stride) st->tot[i] = 0ull;
+    for (int64_t i = t0; i < 2 * nacc; i += stride) st->tot[i] = 0ull;
     uint32_t m = 0;
     for (int j = 0; j < d; ++j) {
         const float* __restrict__ row = st->X + (int64_t)j * ld;
@@ -401,9 +403,11 @@ __global__ __launch_bounds__(WBLOCK) void wide_scan(WState* __restrict__ st) {
     m = wave_max(m);
     if ((tid & 63) == 0 && m) {
         __hip_atomic_fetch_max(&st->absmax_bits, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (m >= 0x7f800000u) {
-            __hip_atomic_fetch_or(&st->flags, (int32_t)FLAG_NONFINITE, __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
+        if (m >= FXP_RANGE_BITS) {
+            // NaN or infinity, or beyond the range of the fixed-point sums
+            __hip_atomic_fetch_or(&st->flags,
+                                  (int32_t)(m >= 0x7f800000u ? FLAG_NONFINITE : FLAG_RANGE),
+                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             st_agent(&st->done, 1);
         }
     }
@@ -424,7 +428,7 @@ __global__ __launch_bounds__(WBLOCK) void wide_update(WState* __restrict__ st) {
     float* amax = hh + ((kp + 3) & ~3);
     int* wq = reinterpret_cast<int*>(amax + 36) + (tid >> 6) * WQCAP;
     double* sw = reinterpret_cast<double*>(reinterpret_cast<int*>(amax + 36) + NW * WQCAP);
-    const int G = scale_exponent(st->absmax_bits);
+    const double fscale = fxp_scale(data_exponent(st->absmax_bits));
     stage_tables<D>(st, K, cm, hh, amax);
     for (int i = tid; i < nacc; i += WBLOCK) acc[i] = 0ull;
     __syncthreads();
@@ -437,17 +441,20 @@ __global__ __launch_bounds__(WBLOCK) void wide_update(WState* __restrict__ st) {
         unsigned long long* a = acc + k;
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-            if (j < d) {
-                const long long q = (long long)__float2int_rn(ldexpf(xr[j], G));
-                __hip_atomic_fetch_add(&a[j * K], (unsigned long long)q, __ATOMIC_RELAXED,
+            if (j < d)
+                __hip_atomic_fetch_add(&a[j * K], fxp_bits(xr[j], fscale), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
         }
         __hip_atomic_fetch_add(&a[d * K], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     });
     const double jb = block_sum(jl, sw);  // also orders the LDS atomics before the copy-out
+    // the row: the sums of q (each slot less FXP_MAGIC_BITS per point it
+    // received, the count of its cluster) and the counts
     unsigned long long* row = st->part + (size_t)blockIdx.x * nacc;
-    for (int i = tid; i < nacc; i += WBLOCK) row[i] = acc[i];
+    for (int i = tid; i < nacc; i += WBLOCK) {
+        const int k = i % K;
+        row[i] = i < d * K ? acc[i] - acc[d * K + k] * FXP_MAGIC_BITS : acc[i];
+    }
     if (tid == 0) st->jpart[blockIdx.x] = jb;
 }
 
@@ -472,10 +479,16 @@ __global__ __launch_bounds__(WBLOCK) void wide_reduce(WState* __restrict__ st) {
             unsigned long long v[WCHUNK];
 #pragma unroll
             for (int u = 0; u < WCHUNK; ++u) v[u] = b0 + u < b1 ? col[(size_t)(b0 + u) * nacc] : 0ull;
-            unsigned long long s = 0ull;
+            i128 s = {0ull, 0ll};
 #pragma unroll
-            for (int u = 0; u < WCHUNK; ++u) s += v[u];
-            if (s) (void)__hip_atomic_fetch_add(&tot[i], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int u = 0; u < WCHUNK; ++u) i128_add(s, i128_of((long long)v[u]));
+            // limbs: s = l1 2^32 + l0, 0 <= l0 < 2^32, |l1| < 2^36 (|s| < 2^68)
+            const unsigned long long l0 = s.lo & 0xffffffffull;
+            const long long l1 = (long long)(((unsigned long long)s.hi << 32) | (s.lo >> 32));
+            if (l0) (void)__hip_atomic_fetch_add(&tot[i], l0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (l1)
+                (void)__hip_atomic_fetch_add(&tot[nacc + i], (unsigned long long)l1, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
         }
     }
     wait_mem();
@@ -490,37 +503,28 @@ __global__ __launch_bounds__(WBLOCK) void wide_reduce(WState* __restrict__ st) {
     __syncthreads();
     if (!sflag) return;
 
-    // ---- last block: totals into LDS (8 device-coherent loads in flight per
-    // thread), then cleared for the next update
-    unsigned long long* stot = reinterpret_cast<unsigned long long*>(wsm);
-    double* se = reinterpret_cast<double*>(wsm + (size_t)nacc * 8);
-    for (int i0 = tid; i0 < nacc; i0 += 8 * WBLOCK) {
-        unsigned long long v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int i = i0 + u * WBLOCK;
-            v[u] = i < nacc ? ld_agent(&tot[i]) : 0ull;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int i = i0 + u * WBLOCK;
-            if (i < nacc) {
-                stot[i] = v[u];
-                st_agent(&tot[i], 0ull);
-            }
-        }
-    }
-    __syncthreads();
-    const int G = scale_exponent(st->absmax_bits);
+    // ---- last block: the mean step from the totals (device-coherent loads),
+    // each slot cleared for the next update by the thread that read it
+    auto total = [&](int i) {
+        const unsigned long long l0 = ld_agent(&tot[i]);
+        const long long l1 = (long long)ld_agent(&tot[nacc + i]);
+        st_agent(&tot[i], 0ull);
+        st_agent(&tot[nacc + i], 0ull);
+        i128 v = {(unsigned long long)l1 << 32, l1 >> 32};
+        i128_add(v, i128{l0, 0ll});
+        return v;
+    };
+    double* se = reinterpret_cast<double*>(wsm);
+    const int xe = data_exponent(st->absmax_bits);
     const int DS = wide_stride(wide_width(d));
     int emp = 0;
     for (int k = tid; k < K; k += WBLOCK) {
-        const unsigned long long* a = stot + k;   // slots [j * K + k]
-        const unsigned long long cnt = a[d * K];
+        const unsigned long long cnt = total(d * K + k).lo;   // slots [j * K + k]
         double e = 0.0;
         for (int j = 0; j < d; ++j) {
+            const i128 sj = total(j * K + k);
             const double old = st->mu64[k * d + j];
-            const double v = cnt ? ldexp((double)(long long)a[j * K], -G) / (double)cnt : old;
+            const double v = cnt ? fxp_mean(sj, xe, cnt) : old;
             const double sh = v - old;
             e = fma(sh, sh, e);
             st->mu64[k * d + j] = v;
@@ -555,7 +559,6 @@ template <int D>
 __global__ __launch_bounds__(WBLOCK) void wide_label(WState* __restrict__ st,
                                                      int32_t* __restrict__ labels) {
     extern __shared__ __align__(16) unsigned char wsm[];
-    __shared__ double sj[WMAX_GRID];
     __shared__ double sw[64];
     __shared__ int sflag;
     using S = WShape<D>;
@@ -585,9 +588,8 @@ __global__ __launch_bounds__(WBLOCK) void wide_label(WState* __restrict__ st,
     __syncthreads();
     if (!sflag) return;
     const int nb = gridDim.x;
-    for (int b = tid; b < nb; b += WBLOCK) sj[b] = ld_agent(&st->jpart[b]);
-    __syncthreads();
-    const double J = ordered_sum(nb, [&](int b) { return sj[b]; }, sw);
+    const double* jp = st->jpart;
+    const double J = ordered_sum(nb, [&](int b) { return ld_agent(&jp[b]); }, sw);
     if (tid == 0) {
         st->J = J;
         st_agent(&st->ticket, 0u);
@@ -628,9 +630,8 @@ hipError_t launch_wide_update(WState* st, int d, int K, int grid, hipStream_t s)
 
 hipError_t launch_wide_reduce(WState* st, int d, int K, int grid_update, hipStream_t s) {
     const int nacc = K * (d + 1);
-    // LDS of the last block: the totals and one float64 per centre (no more
-    // than wide_update's tables, whose centres take at least 16 bytes each)
-    const size_t lds = (size_t)nacc * 8 + (size_t)K * 8;
+    // LDS of the last block: one float64 per centre
+    const size_t lds = (size_t)K * 8;
     if (d < 1 || d > WD_MAX || K < 1 || K > WK_MAX || grid_update < 1 ||
         grid_update > WMAX_GRID || lds > (size_t)WLDS_MAX)
         return hipErrorInvalidValue;

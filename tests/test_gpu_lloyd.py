@@ -112,35 +112,69 @@ def test_fit_end_to_end(km, name, kw):
     try:
         assert r.iters == ref["T"] and r.converged == ref["converged"]
         centre_check(r.centroids, ref["mu"])
-        e_check(r.E, ref["E"])
+        e_check(r.E, ref["E"], ref["mu"])
         assert abs(r.objective - ref["J"]) <= 1e-6 * ref["J"]
         assert r.empty_events == ref["empty_events"]
+        Eh, Jh = km.history()
+        assert len(Eh) == r.iters
+        assert np.all(np.abs(Eh - ref["E_hist"]) <= 1e-6)
+        assert np.all(np.abs(Jh - ref["J_hist"]) <= 1e-6 * ref["J_hist"])
     except AssertionError:
-        # The trajectories may part when the rounding of the sums (a 2^-G grid
-        # on the GPU, compensated float64 in the oracle) moves a centre across
-        # a near-tie of a later update.  Then every update, started from the
-        # GPU's own previous centres, must still match the oracle's update
-        # from those centres: identical labels, centres within tolerance.
+        # Excused only as reading A14 allows: the trajectories part at some
+        # update because a centre, within tolerance of the oracle's, rounds to
+        # a different float32 centre and a near-tie point (relative gap below
+        # 1e-6) changes side.  Find that update and show it; if there is none,
+        # or a differing label is not such a near-tie, the failure stands.
+        t, n = first_divergence(km, X, Xd, mu0, max(r.iters, ref["T"]))
+        if t is None:
+            raise
+        log(f"{name}: trajectories part at update {t} ({n} near-tie labels differ); "
+            f"every update matches the oracle's from the same centres")
         stepwise_check(km, X, Xd, mu0, max(r.iters, ref["T"]))
-        log(f"{name}: trajectories part; every update matches the oracle's from the same centres")
         return
     label_check(r.labels.cpu().numpy(), X, r.centroids)
-    Eh, Jh = km.history()
-    assert len(Eh) == r.iters
-    assert np.all(np.abs(Eh - ref["E_hist"]) <= 1e-6)
-    assert np.all(np.abs(Jh - ref["J_hist"]) <= 1e-6 * ref["J_hist"])
+
+
+def first_divergence(km, X, Xd, mu0, T):
+    """The first update t at which the GPU's labels (at its centres mu^t) and
+    the oracle's (at its own mu^t) differ, and how many differ; (None, 0) if
+    the two runs agree on every update.  Raises AssertionError unless every
+    differing point is a near-tie at the oracle's centres (relative gap below
+    REL_GAP) and the two float32 centre sets differ."""
+    from parity import REL_GAP
+    mu_g = np.asarray(mu0, np.float64)
+    mu_o = mu_g.copy()
+    for t in range(T):
+        lab, _ = km.assign(Xd, mu_g)
+        lg = lab.cpu().numpy()
+        label_check(lg, X, mu_g)                        # exact at its own centres
+        lo, d1, d2 = oracle.assign(X, mu_o)
+        diff = lg != lo
+        if diff.any():
+            assert not np.array_equal(mu_g.astype(np.float32), mu_o.astype(np.float32))
+            near = (d2 - d1) <= REL_GAP * d2
+            assert near[diff].all(), (f"update {t}: {int((diff & ~near).sum())} differing labels "
+                                      f"are not near-ties")
+            return t, int(diff.sum())
+        mu_g = km.fit(Xd, mu0, tol=0.0, max_iter=t + 1, labels=False).centroids
+        mu_o = oracle.update(X, lo, mu_o)["mu"]
+    return None, 0
 
 
 def stepwise_check(km, X, Xd, mu0, T):
     """Updates 1..T of the GPU fit, each against the oracle's update from the
-    GPU's previous centres: identical labels, centres within tolerance."""
+    GPU's previous centres: identical labels, centres, E and J within
+    tolerance."""
+    prev = np.asarray(mu0, np.float64)
     for t in range(1, T + 1):
-        g = km.fit(Xd, mu0, tol=0.0, max_iter=t, labels=False).centroids
-        prev = km.fit(Xd, mu0, tol=0.0, max_iter=t - 1, labels=False).centroids if t > 1 else mu0
+        g = km.fit(Xd, mu0, tol=0.0, max_iter=t, labels=False)
         o = oracle.step(X, prev)
-        lab, _ = km.assign(Xd, prev)
+        lab, J = km.assign(Xd, prev)
         label_check(lab.cpu().numpy(), X, prev)
-        centre_check(g, o["mu"])
+        centre_check(g.centroids, o["mu"])
+        e_check(g.E, o["E"], o["mu"])
+        assert abs(J - o["J"]) <= 1e-6 * o["J"]
+        prev = g.centroids
 
 
 # -------------------------------------------------------------- determinism
