@@ -67,19 +67,24 @@ def traffic_from_profile(name: str):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(X, mu0, n_sample: int, target_s: float = 12.0):
+def cpu_baseline(X, mu0, n_sample: int, target_s: float = 12.0, threads: int = 0):
     """The FP64 oracle on the host cores over the first n_sample points of the
-    same data and initial centres; as many updates as fit in ~target_s."""
+    same data and initial centres; as many updates as fit in ~target_s.
+    threads: OpenMP threads (0 = all host cores)."""
     import oracle
-    cores = oracle.threads()
-    Xs = X[:, :n_sample].copy()
-    t = time.perf_counter()
-    oracle.fit(Xs, mu0, tol=0.0, max_iter=1, labels=False)
-    one = time.perf_counter() - t               # one update + one final pass
-    iters = max(1, min(20, int(target_s / max(one / 1.5, 1e-3))))
-    t = time.perf_counter()
-    r = oracle.fit(Xs, mu0, tol=0.0, max_iter=iters, labels=False)
-    el = time.perf_counter() - t
+    all_threads = oracle.threads()
+    cores = oracle.threads(threads) if threads else all_threads
+    try:
+        Xs = X[:, :n_sample].copy()
+        t = time.perf_counter()
+        oracle.fit(Xs, mu0, tol=0.0, max_iter=1, labels=False)
+        one = time.perf_counter() - t               # one update + one final pass
+        iters = max(1, min(20, int(target_s / max(one / 1.5, 1e-3))))
+        t = time.perf_counter()
+        r = oracle.fit(Xs, mu0, tol=0.0, max_iter=iters, labels=False)
+        el = time.perf_counter() - t
+    finally:
+        oracle.threads(all_threads)
     assert r["T"] == iters
     return {"value": n_sample * iters / el, "unit": "point-iters/s", "cores": cores,
             "kind": "oracle",
@@ -227,6 +232,32 @@ def _c5_instance(seed):
     return int(seed), X
 
 
+def c5_instances(seeds, workers: int = 8):
+    """The held-out C5 instances, in seed order, drawn by host threads (numpy
+    releases the interpreter lock while it draws): no child processes, so a
+    profiled run holds one process on the GPU."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        yield from ex.map(_c5_instance, seeds)
+
+
+def converge_run(km, Xd, mu0, N, tol=1e-6, max_iter=1000, repeats=3):
+    """kmeans_fit from mu0 to E < tol (cap max_iter) on resident points: the
+    wall-clock span of the call, median of `repeats` (identical results)."""
+    import numpy as np
+    import torch
+    times = []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = km.fit(Xd, mu0, tol=tol, max_iter=max_iter, labels=False)
+        times.append(time.perf_counter() - t)
+    s = float(np.median(times))
+    return {"tol": tol, "max_iter": max_iter, "T": r.iters, "converged": bool(r.converged),
+            "E": r.E, "objective": r.objective, "ms": s * 1e3,
+            "point_iters_per_s": N * r.iters / s}
+
+
 def time_to_converge(km, X, Xd, N, K, seed, method, weights=None, repeats=3):
     """One initialisation method followed by kmeans_fit (E < 1e-6 or 300
     updates) on resident points; the wall-clock span covers the
@@ -263,41 +294,34 @@ def time_to_converge(km, X, Xd, N, K, seed, method, weights=None, repeats=3):
     return float(np.median(times)), r.iters, r.objective, fell_back
 
 
-def bench_learned(args):
-    """Learned initialiser against a seeded sample of data points and against
-    k-means++ on held-out instances of the N=1e6, d=3, K=16 mixture (16
-    axis-aligned Gaussian components in [-50, 50]^3, Dirichlet weights, 1%
-    uniform noise), seeds 9_000_000 + i, disjoint from the training seeds.
-    Reports, per method, the median time-to-converge, mean updates and the
-    geometric-mean ratios to the seeded sample, and the share of instances on
-    which the learned start reaches an objective within 0.1% of the seeded
-    sample's (or lower) in less wall-clock time."""
-    import multiprocessing as mp
-
+def learned_vs_plain(km, seeds, weights, repeats=3, progress=False):
+    """Time-to-converge from a seeded sample of data points, from k-means++ and
+    from the learned initialiser on the held-out C5 instances `seeds` (N=1e6,
+    d=3, K=16: 16 axis-aligned Gaussian components in [-50, 50]^3, Dirichlet
+    weights, 1% uniform noise).  Per method: the median time-to-converge, the
+    mean updates, the geometric-mean ratios of time and objective to the seeded
+    sample, and the share of instances whose objective is within 0.1% of the
+    seeded sample's (or lower), alone and together with a shorter wall-clock
+    time."""
     import numpy as np
     import torch
 
-    from paper_2405_12052_amd import KMeans, initnet
-    weights = torch.from_numpy(initnet.load_weights(args.weights or initnet.DEFAULT_WEIGHTS)).cuda()
-    km = KMeans(0)
-    seeds = [9_000_000 + i for i in range(args.instances)]
     methods = ["sample", "kmeans++", "learned"]
     rec = {m: [] for m in methods}
     K, N = 16, 1_000_000
     t0 = time.time()
     warm = False
-    with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
-        for n_done, (seed, X) in enumerate(pool.imap(_c5_instance, seeds)):
-            Xd = torch.from_numpy(X).cuda()
-            if not warm:        # first-call set-up (graphs, workspaces) out of the records
-                for m in methods:
-                    time_to_converge(km, X, Xd, N, K, seed, m, weights, repeats=1)
-                warm = True
+    for n_done, (seed, X) in enumerate(c5_instances(seeds)):
+        Xd = torch.from_numpy(X).cuda()
+        if not warm:        # first-call set-up (graphs, workspaces) out of the records
             for m in methods:
-                rec[m].append(time_to_converge(km, X, Xd, N, K, seed, m, weights, args.repeats))
-            if (n_done + 1) % 10 == 0:
-                log(f"{n_done + 1}/{len(seeds)} instances, {time.time() - t0:.0f}s")
-    km.close()
+                time_to_converge(km, X, Xd, N, K, seed, m, weights, repeats=1)
+            warm = True
+        for m in methods:
+            rec[m].append(time_to_converge(km, X, Xd, N, K, seed, m, weights, repeats))
+        if progress and (n_done + 1) % 10 == 0:
+            log(f"{n_done + 1}/{len(seeds)} instances, {time.time() - t0:.0f}s")
+        del Xd
     a = {m: np.array([r[:3] for r in rec[m]], np.float64) for m in methods}
     base = a["sample"]
     summary = {}
@@ -312,6 +336,23 @@ def bench_learned(args):
                 np.mean((a[m][:, 2] <= 1.001 * base[:, 2]) & (a[m][:, 0] < base[:, 0]))),
         }
     summary["learned"]["fallbacks"] = int(sum(r[3] for r in rec["learned"]))
+    return summary
+
+
+def bench_learned(args):
+    """Learned initialiser against a seeded sample of data points and against
+    k-means++ on held-out instances of the N=1e6, d=3, K=16 mixture, seeds
+    9_000_000 + i, disjoint from the training seeds (learned_vs_plain)."""
+    import torch
+
+    from paper_2405_12052_amd import KMeans, initnet
+    # instances are drawn by threads of this process (c5_instances); the GPU is
+    # initialised here, before any of them
+    weights = torch.from_numpy(initnet.load_weights(args.weights or initnet.DEFAULT_WEIGHTS)).cuda()
+    km = KMeans(0)
+    seeds = [9_000_000 + i for i in range(args.instances)]
+    summary = learned_vs_plain(km, seeds, weights, args.repeats, progress=True)
+    km.close()
     L = summary["learned"]
     res = {
         "metric": "time-to-converge, learned init vs seeded sample (geomean ratio)",
@@ -422,6 +463,12 @@ def main():
                     help="default workload only: K centres seeded from the same K=64 mixture "
                          "(testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-converge", action="store_true",
+                    help="default workload: skip the run to E < 1e-6 and the learned-vs-plain "
+                         "comparison")
+    ap.add_argument("--learned-instances", type=int, default=16,
+                    help="default workload: held-out N=1e6 instances of the learned-vs-plain "
+                         "comparison (0: none)")
     ap.add_argument("--cpu-sample", type=int, default=20_000_000)
     ap.add_argument("--workload", choices=["hbm", "batched", "learned", "configs", "wide"],
                     default="hbm",
@@ -530,11 +577,31 @@ def main():
                 "v_med3_tops": peaks["med3_lane_ops_per_s"] / 1e12,
                 "hbm_read_gbs": peaks["hbm_read_bytes_per_s"] / 1e9}
     log(f"measured peaks: {measured}")
+    # the metric's second half, outside the timed region: time to converge
+    # (E < 1e-6) on this workload, and learned vs plain initialisation
+    ttc = None
+    if not args.no_converge and args.N is None and args.K is None:
+        ttc = {"C3_run_to_tol": converge_run(km, Xd, mu0, s.N)}
+        log(f"converge run: {ttc['C3_run_to_tol']}")
+        if args.learned_instances > 0:
+            from paper_2405_12052_amd import initnet
+            weights = torch.from_numpy(initnet.load_weights(initnet.DEFAULT_WEIGHTS)).cuda()
+            seeds = [9_000_000 + i for i in range(args.learned_instances)]
+            summ = learned_vs_plain(km, seeds, weights, repeats=3)
+            ttc["learned_vs_plain"] = {
+                "workload": f"{len(seeds)} held-out instances (seeds 9000000+i), N=1e6, d=3, "
+                            "K=16 axis-aligned mixture with 1% noise; E<1e-6 or 300 updates; "
+                            "time spans init + fit + sync, points resident; median of 3",
+                "methods": summ}
+            log(f"learned vs plain: {summ}")
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         cpu = cpu_baseline(X, mu0, min(args.cpu_sample, s.N))
         log(f"cpu baseline {cpu['value']:.3e} pt-it/s on {cpu['cores']} threads")
+        one = cpu_baseline(X, mu0, min(args.cpu_sample // 10, s.N), target_s=8.0, threads=1)
+        cpu["single_thread"] = {k: one[k] for k in ("value", "unit", "cores", "sample")}
+        log(f"cpu baseline {one['value']:.3e} pt-it/s on 1 thread")
     out = {
         "metric": "Lloyd point-iters/s", "value": value, "unit": "point-iters/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -548,6 +615,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "measured_peaks": measured,
+        "time_to_converge": ttc,
     }
     print(json.dumps(out), flush=True)
     km.close()

@@ -85,3 +85,39 @@ def test_zero_loss_at_a_perfect_prediction():
     L, g, pi = net.loss_and_grad(theta, pts, tgt, K, bf16_mode=False)
     assert L < 1e-24 and np.abs(g).max() < 1e-12
     assert pi[0].tolist() == list(range(K))[::-1]
+
+
+def _golden_tiny():
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                    "initnet_forward_tiny.json")))
+    K = g["K"]
+    blocks = {name: np.zeros(s) for name, s in net.shapes(K)}
+    for name, idx, v in g["weights"]:
+        blocks[name][tuple(idx)] = v
+    return g, K, net.pack(blocks, K), np.asarray(g["points"], np.float64)[None]
+
+
+@pytest.mark.parametrize("bf16_mode", [False, True])
+def test_forward_against_hand_computed_golden(bf16_mode):
+    """The forward pass on sparse, hand-chosen weights against values computed
+    by hand (tests/golden/initnet_forward_tiny.json): the ReLU zeros, the
+    biases, mean (not sum) pooling in features 0..63 and max pooling in
+    64..127, the first point on a tied maximum, and the head."""
+    g, K, theta, pts = _golden_tiny()
+    y, c = net.forward(theta, pts, K, bf16_mode=bf16_mode)
+    assert np.array_equal(y.reshape(-1), np.asarray(g["y"], np.float64))
+    h1 = np.maximum(c["a1"][0], 0.0)
+    h2 = np.maximum(c["a2"][0], 0.0)
+    for j in range(net.H):
+        assert np.array_equal(h1[:, j], np.asarray(g["h1"].get(str(j), [0] * 4), np.float64)), j
+        assert np.array_equal(h2[:, j], np.asarray(g["h2"].get(str(j), [0] * 4), np.float64)), j
+        assert c["amax"][0, j] == g["argmax_point"].get(str(j), 0), j
+    pool = c["poolr"][0]
+    for j in range(net.H):
+        assert pool[j] == g["pool_mean"].get(str(j), 0.0), j
+        assert pool[net.H + j] == g["pool_max"].get(str(j), 0.0), j
+    z = np.maximum(c["a3"][0], 0.0)
+    for j in range(net.Z):
+        assert z[j] == g["z"].get(str(j), 0.0), j
