@@ -191,6 +191,30 @@ int kmeans_fit(kmeans_ctx *ctx, const float *X, int64_t N, int64_t ld,
                int32_t max_iter, double *centroids_out, int32_t *labels_out,
                km_result *res);
 
+/*
+ * kmeans_fit for callers that cannot allocate memory (code that must not
+ * call hipMalloc or create graphs, streams or events: tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, results and error
+ * codes as kmeans_fit, without a context: `device` is the HIP device (made
+ * current for the call, the caller's current device restored on return) and
+ * `hip_stream` the stream of that device to run on (NULL: its null stream).
+ * Shapes: d in {2, 3} and K <= 64, else KM_EUNSUPPORTED; N, ld, tol and
+ * max_iter as kmeans_fit.  Errors are read with kmeans_last_error(NULL) (per
+ * host thread).
+ * Scratch: the fit's device state, partial sums, tickets and E/J history
+ * live in one statically sized device array of about 8.6 MB, which the
+ * library holds on every device it runs on until the process ends (no
+ * history is kept for reading back; updates beyond 1024 run unrecorded).
+ * The call allocates no device or host memory; the initial state is copied
+ * from, and the results read back into, memory on the caller's stack.
+ * Calls that overlap on one device (from two threads, or on two streams)
+ * share that array and race: serialise them.
+ */
+int kmeans_fit_noalloc(int device, void *hip_stream, const float *X, int64_t N,
+                       int64_t ld, int32_t d, int32_t K, const double *init,
+                       double tol, int32_t max_iter, double *centroids_out,
+                       int32_t *labels_out, km_result *res);
+
 /* Set a km_option on the context.  Returns KM_EINVAL for an unknown option
  * or a value out of range. */
 int kmeans_set_option(kmeans_ctx *ctx, int32_t option, int64_t value);

@@ -5,7 +5,7 @@ include/kmeans.h (libkmeans_mi355x.so, built in-tree by build.py); this
 package is its Python binding.
 """
 from ._binding import (KMeans, KMeansError, FitResult, load_library, validate,  # noqa: F401
-                       initnet_param_count,
+                       initnet_param_count, fit_noalloc,
                        LIB_PATH, KM_OK, KM_EINVAL, KM_ENODEV, KM_EHIP, KM_ENOMEM,
                        KM_EUNSUPPORTED, KM_OPT_GRAPH, KM_OPT_UNROLL, KM_OPT_BLOCKS,
                        KM_OPT_TIMING, KM_OPT_KEYS, KM_OPT_PERSIST, KM_OPT_WIDE)

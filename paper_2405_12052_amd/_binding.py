@@ -96,6 +96,9 @@ def load_library():
         "kmeans_pp_init": (C.c_int, [vp, f32p, C.c_int64, C.c_int64, C.c_int32, C.c_int32, f64p,
                                      f64p, C.POINTER(C.c_int64)]),
         "kmeans_measure_peaks": (C.c_int, [vp, f64p]),
+        "kmeans_fit_noalloc": (C.c_int, [C.c_int, vp, f32p, C.c_int64, C.c_int64, C.c_int32,
+                                         C.c_int32, f64p, C.c_double, C.c_int32, f64p, i32p,
+                                         C.POINTER(km_result)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -133,6 +136,37 @@ class FitResult:
     shift_l2: float
     objective: float
     empty_events: int
+
+
+def fit_noalloc(X, init, tol=1e-6, max_iter=100, N=None, labels=None, stream=None) -> FitResult:
+    """kmeans_fit_noalloc: the fit of KMeans.fit without a context and without
+    any allocation inside the library (its scratch is a static device array).
+    X: float32 CUDA tensor (d, >= N), unit stride along the points; labels:
+    an int32 CUDA tensor of at least N entries to receive the labels, or None;
+    stream: a torch stream of X's device (default: its current stream)."""
+    import torch
+    lib = load_library()
+    if not isinstance(X, torch.Tensor) or X.dtype != torch.float32 or not X.is_cuda or X.dim() != 2:
+        raise TypeError("X must be a float32 CUDA tensor of shape (d, N)")
+    if X.stride(1) != 1:
+        raise ValueError("X must have unit stride along the points")
+    n = X.shape[1] if N is None else int(N)
+    dev = X.device.index if X.device.index is not None else torch.cuda.current_device()
+    s = torch.cuda.current_stream(dev) if stream is None else stream
+    if labels is not None and (labels.dtype != torch.int32 or not labels.is_cuda
+                               or labels.numel() < n or not labels.is_contiguous()):
+        raise ValueError("labels must be a contiguous int32 CUDA tensor of at least N entries")
+    mu0 = _f64(init)
+    K, d = mu0.shape[0], X.shape[0]
+    out = np.empty((K, d), np.float64)
+    res = km_result()
+    rc = lib.kmeans_fit_noalloc(dev, C.c_void_p(s.cuda_stream), X.data_ptr(), n, X.stride(0), d, K,
+                                _dptr(mu0), float(tol), int(max_iter), _dptr(out),
+                                labels.data_ptr() if labels is not None else None, C.byref(res))
+    if rc != KM_OK:
+        raise KMeansError(rc, lib.kmeans_last_error(None).decode())
+    return FitResult(out, labels, res.iters, bool(res.converged), res.E, res.shift_l2,
+                     res.objective, res.empty_events)
 
 
 class KMeans:

@@ -13,7 +13,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["lloyd_kernels.hip", "batched_kernels.hip", "initnet_kernels.hip", "kmeans_api.hip",
            "batched_api.hip", "initnet_api.hip", "seeding.hip", "peaks.hip", "wide_kernels.hip",
-           "wide_api.hip"]
+           "wide_api.hip", "noalloc_api.hip"]
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 instructions.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -88,6 +88,33 @@ int range_error(kmeans_ctx* c);
 // True when (d, K) takes the general-shape fit: d not in {2, 3}, K > KMAX,
 // or KM_OPT_WIDE set (kmeans_api.hip).
 bool wide_shape(const kmeans_ctx* c, int d, int K);
+// Argument checks of a fit or reassignment (kmeans_api.hip); with c == NULL
+// the message goes where kmeans_last_error(NULL) reads it.
+int validate(kmeans_ctx* c, int64_t N, int64_t ld, int32_t d, int32_t K, double tol,
+             int32_t max_iter);
+int check_centres(kmeans_ctx* c, const double* m, int K, int d, const char* what);
+// Rows 16-byte aligned with ld % 4 == 0: the 128-bit load path.
+bool vec_ok(const float* X, int64_t ld);
+// Fewest blocks that keep every block at or below FXP_BLOCK_POINTS points.
+int64_t min_blocks(int64_t N);
+// Grid of the per-update kernels for N points on n_cu compute units
+// (blocks_opt: KM_OPT_BLOCKS, 0 = automatic).
+int grid_blocks(int n_cu, int blocks_opt, int64_t N);
+// Updates per graph replay when KM_OPT_UNROLL is automatic.
+int auto_unroll(int64_t N, int max_iter);
+// Device buffers a fit's state points to.
+struct FitBufs {
+    double* jpart;
+    unsigned long long* part;
+    unsigned long long* gpart;
+    double* gjpart;
+    uint32_t* gticket;
+    double* hist;   // [2 * hist_cap]: E then J
+    int hist_cap;
+};
+// Host copy of the state of a fit (or reassignment) of the given problem.
+void stage_state(State* h, const FitBufs& b, const float* X, int64_t N, int64_t ld, int d,
+                 int K, const double* mu, double tol, int max_iter);
 // The general-shape fit and reassignment (wide_api.hip); same contract as
 // kmeans_fit / kmeans_assign after argument validation.
 int wide_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, int K,

@@ -90,9 +90,7 @@ bool km::wide_shape(const kmeans_ctx* c, int d, int K) {
     return c->wide != 0 || (d != 2 && d != 3) || K > km::KMAX;
 }
 
-namespace {
-
-int validate(kmeans_ctx* c, int64_t N, int64_t ld, int32_t d, int32_t K, double tol,
+int km::validate(kmeans_ctx* c, int64_t N, int64_t ld, int32_t d, int32_t K, double tol,
              int32_t max_iter) {
     if (N < 1 || N > 2147483647LL) return fail(c, KM_EINVAL, "N=%lld out of [1, 2^31-1]", (long long)N);
     if (ld < N) return fail(c, KM_EINVAL, "ld=%lld < N=%lld", (long long)ld, (long long)N);
@@ -111,14 +109,14 @@ int validate(kmeans_ctx* c, int64_t N, int64_t ld, int32_t d, int32_t K, double 
     return KM_OK;
 }
 
-int check_centres(kmeans_ctx* c, const double* m, int K, int d, const char* what) {
+int km::check_centres(kmeans_ctx* c, const double* m, int K, int d, const char* what) {
     if (!m) return fail(c, KM_EINVAL, "%s is NULL", what);
     for (int i = 0; i < K * d; ++i)
         if (!isfinite(m[i])) return fail(c, KM_EINVAL, "%s[%d] is not finite", what, i);
     return KM_OK;
 }
 
-bool vec_ok(const float* X, int64_t ld) {
+bool km::vec_ok(const float* X, int64_t ld) {
     return (reinterpret_cast<uintptr_t>(X) & 15u) == 0 && (ld & 3) == 0;
 }
 
@@ -132,20 +130,20 @@ bool vec_ok(const float* X, int64_t ld) {
 // (4096 blocks) is best.  Whatever the cap (KM_OPT_BLOCKS included), the grid
 // is at least min_blocks(N), so that no block adds more than
 // FXP_BLOCK_POINTS points into its int64 sums.
-int64_t min_blocks(int64_t N) {
+int64_t km::min_blocks(int64_t N) {
     const int64_t groups = (N + 3) / 4;
     const int64_t per_block = km::FXP_BLOCK_POINTS / 4;  // groups of 4 points
     return (groups + per_block - 1) / per_block;
 }
 
-int grid_for(kmeans_ctx* c, int64_t N) {
+int km::grid_blocks(int n_cu, int blocks_opt, int64_t N) {
     const int64_t groups = (N + 3) / 4;
     const int64_t need = (groups + km::BLOCK - 1) / km::BLOCK;
     int64_t cap;
-    if (c->blocks > 0) {
-        cap = c->blocks;
+    if (blocks_opt > 0) {
+        cap = blocks_opt;
     } else {
-        const int64_t lo = (int64_t)c->n_cu * 2, hi = (int64_t)c->n_cu * 16;
+        const int64_t lo = (int64_t)n_cu * 2, hi = (int64_t)n_cu * 16;
         const int64_t want = (N + 8191) / 8192;
         cap = want < lo ? lo : (want > hi ? hi : want);
     }
@@ -156,10 +154,9 @@ int grid_for(kmeans_ctx* c, int64_t N) {
     return (int)(g < 1 ? 1 : g);
 }
 
-// Fill the host staging copy of the state for a problem and its centres.
-void stage(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, int K,
-           const double* mu, double tol, int max_iter) {
-    State* h = c->st_h;
+// Fill a host copy of the state for a problem and its centres.
+void km::stage_state(State* h, const FitBufs& b, const float* X, int64_t N, int64_t ld, int d,
+                     int K, const double* mu, double tol, int max_iter) {
     memset(h, 0, km::kUploadBytes);
     h->X = X;
     h->N = N;
@@ -168,14 +165,14 @@ void stage(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, int K,
     h->K = K;
     h->tol = tol;
     h->max_iter = max_iter;
-    h->hist_cap = c->hist_cap;
-    h->jpart = c->jpart;
-    h->part = c->part;
-    h->gpart = c->gpart;
-    h->gjpart = c->gjpart;
-    h->gticket = c->gticket;
-    h->E_hist = c->hist;
-    h->J_hist = c->hist + c->hist_cap;
+    h->hist_cap = b.hist_cap;
+    h->jpart = b.jpart;
+    h->part = b.part;
+    h->gpart = b.gpart;
+    h->gjpart = b.gjpart;
+    h->gticket = b.gticket;
+    h->E_hist = b.hist;
+    h->J_hist = b.hist + b.hist_cap;
     h->E = INFINITY;
     h->minus_inf = -INFINITY;
     for (int k = 0; k < K; ++k) {
@@ -186,6 +183,21 @@ void stage(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, int K,
         }
         h->mu32[k] = make_float4(m[0], m[1], m[2], 0.f);
     }
+}
+
+namespace {
+
+using km::validate;
+using km::check_centres;
+using km::vec_ok;
+using km::min_blocks;
+
+int grid_for(kmeans_ctx* c, int64_t N) { return km::grid_blocks(c->n_cu, c->blocks, N); }
+
+void stage(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, int K,
+           const double* mu, double tol, int max_iter) {
+    const km::FitBufs b{c->jpart, c->part, c->gpart, c->gjpart, c->gticket, c->hist, c->hist_cap};
+    km::stage_state(c->st_h, b, X, N, ld, d, K, mu, tol, max_iter);
 }
 
 int get_graph(kmeans_ctx* c, int d, bool vec, int keys, int grid, int unroll,
@@ -253,12 +265,12 @@ int scan_keys(kmeans_ctx* c, int K) {
     return 0;
 }
 
-int auto_unroll(int64_t N, int max_iter) {
+}  // namespace
+
+int km::auto_unroll(int64_t N, int max_iter) {
     int u = N >= (1 << 24) ? 10 : (N >= (1 << 20) ? 16 : 32);
     return u < max_iter ? u : max_iter;
 }
-
-}  // namespace
 
 extern "C" {
 
@@ -432,7 +444,7 @@ int kmeans_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int32_t d, 
     if (rc) return rc;
     const bool vec = vec_ok(X, ld);
     const int grid = grid_for(c, N);
-    const int U = c->unroll > 0 ? (c->unroll < max_iter ? c->unroll : max_iter) : auto_unroll(N, max_iter);
+    const int U = c->unroll > 0 ? (c->unroll < max_iter ? c->unroll : max_iter) : km::auto_unroll(N, max_iter);
 
     stage(c, X, N, ld, d, K, init, tol, max_iter);
     KM_HIP(c, hipMemcpyAsync(c->st, c->st_h, km::kUploadBytes, hipMemcpyHostToDevice, c->stream));
