@@ -261,7 +261,7 @@ __device__ bool run_instance(BatchState* __restrict__ bs, int inst, int rank, in
     }
     if (tid == 0) sm.active = bad ? 0 : (1 << R) - 1;
     __syncthreads();
-    for (int r = 0; r < R; ++r) prep_centres(sm.smu[r], K, sm.scand[r], &sm.sbnd[r], sm.sc, sm.sa, am);
+    for (int r = 0; r < R; ++r) prep_centres(sm.smu[r], K, 3 * ((K + 2) / 3), sm.scand[r], &sm.sbnd[r], sm.sc, sm.sa, am);
 
     double jl = 0.0;
     // ---- Lloyd updates of all active restarts
@@ -378,12 +378,12 @@ __device__ bool run_instance(BatchState* __restrict__ bs, int inst, int rank, in
         const int still = __builtin_amdgcn_readfirstlane(sm.active);
         for (int r = 0; r < R; ++r)
             if ((still >> r) & 1)
-                prep_centres(sm.smu[r], K, sm.scand[r], &sm.sbnd[r], sm.sc, sm.sa, am);
+                prep_centres(sm.smu[r], K, 3 * ((K + 2) / 3), sm.scand[r], &sm.sbnd[r], sm.sc, sm.sa, am);
         __syncthreads();
     }
     if (!bad) {
         // ---- objective of every restart at its final centres
-        for (int r = 0; r < R; ++r) prep_centres(sm.smu[r], K, sm.scand[r], &sm.sbnd[r], sm.sc, sm.sa, am);
+        for (int r = 0; r < R; ++r) prep_centres(sm.smu[r], K, 3 * ((K + 2) / 3), sm.scand[r], &sm.sbnd[r], sm.sc, sm.sa, am);
         for (int r = 0; r < R; ++r) {
             jl = 0.0;
             points_pass<D, MODE_OBJ>(in, rank, S, 1 << r, fscale, ninf, sm, jl, 0, ngroups);

@@ -395,13 +395,13 @@ __device__ __forceinline__ void assign_points(const float* __restrict__ X, int64
 // |x|^2 + |key|, below 2^-49 (|x|^2 + |key|); the key part lies far inside
 // the first term and |x|^2 <= xmax sum_j |x_j|.  A certified winner is
 // therefore also the first-index minimum of the float64 direct form.
-// Written to cand[0 .. 3*ceil(K/3)) and *bnd (global or LDS).  Called by one
-// whole block; sc and sa are LDS scratch of KPAD and 3*KPAD floats.
-__device__ inline void prep_centres(const float4* m32, int K, float4* cand, float4* bnd,
+// Written to cand[0 .. npad) (npad >= 3*ceil(K/3): records past K are pads)
+// and *bnd (global or LDS).  Called by one whole block; sc and sa are LDS
+// scratch of npad and 3*npad floats.
+__device__ inline void prep_centres(const float4* m32, int K, int npad, float4* cand, float4* bnd,
                                     float* sc, float* sa, uint32_t xmax_bits) {
     const int tid = threadIdx.x;
-    const int ntri = (K + 2) / 3;
-    if (tid < 3 * ntri) {
+    if (tid < npad) {
         // pads: a finite key far above any real one (their keys carry index
         // bits in the scan, which would turn an infinity into a NaN)
         float4 r = make_float4(0.f, 0.f, 0.f, 0x1p127f);
@@ -434,13 +434,13 @@ __device__ inline void prep_centres(const float4* m32, int K, float4* cand, floa
     __syncthreads();
 }
 
-// Stage the centre tables of the current iteration in LDS.
-__device__ __forceinline__ int stage_centres(const State* __restrict__ st, int K, float4* scand,
-                                             float4* smu) {
-    const int ntri = (K + 2) / 3;
-    for (int i = threadIdx.x; i < 3 * ntri; i += BLOCK) scand[i] = st->cand[i];
+// Stage the centre tables of the current iteration in LDS: all KPAD records
+// (pads included, for the matrix-core scan's re-keying of a quad) and the K
+// float32 centres.
+__device__ __forceinline__ void stage_centres(const State* __restrict__ st, int K, float4* scand,
+                                              float4* smu) {
+    for (int i = threadIdx.x; i < KPAD; i += BLOCK) scand[i] = st->cand[i];
     for (int i = threadIdx.x; i < K; i += BLOCK) smu[i] = st->mu32[i];
-    return ntri;
 }
 
 }  // namespace km

@@ -241,7 +241,7 @@ __global__ __launch_bounds__(BLOCK) void km_scan(State* __restrict__ st) {
     __syncthreads();
     if (!slast) return;
     const uint32_t a = ld_agent(&st->absmax_bits);
-    prep_centres(st->mu32, st->K, st->cand, &st->bnd, sc, sa, a);
+    prep_centres(st->mu32, st->K, KPAD, st->cand, &st->bnd, sc, sa, a);
     for (int i = tid; i < MAX_GROUPS; i += BLOCK) st->gticket[i] = 0u;
     if (tid == 0) {
         st->xe = data_exponent(a);
@@ -266,10 +266,16 @@ __device__ __forceinline__ void scan_points(const float* __restrict__ X, int64_t
                                             const float4* __restrict__ smu, int K,
                                             float4 bnd, float ninf, int xe,
                                             float4* __restrict__ wq, Sink&& sink) {
-    if constexpr (KT == 0)
-        assign_points<D, VEC>(X, ld, N, scand, smu, K, bnd, ninf, wq, sink);
-    else
-        assign_points_mfma<D, VEC, KT>(X, ld, N, scand, smu, K, bnd, ninf, xe, wq, sink);
+    int e = 0;
+    if constexpr (KT != 0) {
+        if (mfma_scale(xe, bnd, e)) {
+            assign_points_mfma<D, VEC, KT>(X, ld, N, scand, smu, K, bnd, e, ninf, wq, sink);
+            return;
+        }
+    }
+    // the VALU keys (also for data or centres beyond the matrix-core scale's
+    // range)
+    assign_points<D, VEC>(X, ld, N, scand, smu, K, bnd, ninf, wq, sink);
 }
 
 // ---------------------------------------------------------------- lloyd_iter
@@ -438,9 +444,8 @@ __device__ __forceinline__ void finalize_update(State* __restrict__ st, IterSmem
         sm.u.fin.sEmpty[k] = cnt == 0ull;
     }
     __syncthreads();
-    prep_centres(sm.smu, K, sm.scand, &sm.sbnd, sm.u.fin.sc, sm.u.fin.sa, st->absmax_bits);
-    const int ntri = (K + 2) / 3;
-    for (int i = tid; i < 3 * ntri; i += BLOCK) wr4<COH>(&st->cand[i], sm.scand[i]);
+    prep_centres(sm.smu, K, KPAD, sm.scand, &sm.sbnd, sm.u.fin.sc, sm.u.fin.sa, st->absmax_bits);
+    for (int i = tid; i < KPAD; i += BLOCK) wr4<COH>(&st->cand[i], sm.scand[i]);
     if (tid == 0) {
         wr4<COH>(&st->bnd, sm.sbnd);
         double E = 0.0;
@@ -489,7 +494,7 @@ __global__ __launch_bounds__(BLOCK) void lloyd_persist(State* __restrict__ st) {
     const int K = st->K;
     const int xe = st->xe;
     const float ninf = st->minus_inf;
-    const int ntri = stage_centres(st, K, sm.scand, sm.smu);
+    stage_centres(st, K, sm.scand, sm.smu);
     float4 bnd = st->bnd;
     __syncthreads();
     for (uint32_t round = 1;; ++round) {
@@ -520,7 +525,7 @@ __global__ __launch_bounds__(BLOCK) void lloyd_persist(State* __restrict__ st) {
             }
             __syncthreads();
             if (!sm.sflag) return;
-            for (int i = tid; i < 3 * ntri; i += BLOCK) sm.scand[i] = ld4_agent(&st->cand[i]);
+            for (int i = tid; i < KPAD; i += BLOCK) sm.scand[i] = ld4_agent(&st->cand[i]);
             for (int k = tid; k < K; k += BLOCK) sm.smu[k] = ld4_agent(&st->mu32[k]);
             if (tid == 0) {
                 sm.sbnd = ld4_agent(&st->bnd);
