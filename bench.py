@@ -37,6 +37,18 @@ def alg_bytes_per_point(d: int) -> int:
     return 4 * d
 
 
+def scan_tiles(K: int, keys: int) -> int:
+    """Template argument of the iteration kernel the library runs for K
+    centres under KM_OPT_KEYS = keys (0 = the VALU scan, 1 / 2 = matrix-core
+    tiles of 32 centres): the library's automatic choice for keys = 0."""
+    tiles = 2 if K > 32 else 1
+    if keys == 1:
+        return 0
+    if keys == 2:
+        return tiles
+    return tiles if (24 < K <= 32 or K > 44) else 0
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -486,7 +498,8 @@ def main():
                          "copy kernel of known size, to calibrate traffic counters)")
     ap.add_argument("--print-source-hash", action="store_true")
     ap.add_argument("--keys", type=int, default=0, choices=[0, 1, 2],
-                    help="reassignment scan (KM_OPT_KEYS): 0 automatic, 1 VALU, 2 matrix cores")
+                    help="reassignment scan (KM_OPT_KEYS): 0 automatic (matrix cores at K = 64), "
+                         "1 VALU, 2 matrix cores")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -563,8 +576,8 @@ def main():
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
             "traffic": (traffic_from_profile("lloyd_iter_C3_traffic.json")
-                        if args.keys != 2 and args.N is None and args.K is None else None),
-            "kernel": f"lloyd_iter<{s.d},true,{0 if args.keys != 2 else (2 if K > 32 else 1)}>",
+                        if args.keys == 0 and args.N is None and args.K is None else None),
+            "kernel": f"lloyd_iter<{s.d},true,{scan_tiles(K, args.keys)}>",
             "avg_launch_us": avg_kernel_s * 1e6,
             "alg_flops_per_launch": flops,
             "alg_bytes_per_launch": alg_bytes_per_point(s.d) * s.N,

@@ -114,12 +114,14 @@ enum km_option {
     KM_OPT_TIMING = 4,    /* 1: time the iteration launches with HIP events
                              (see kmeans_get_timing)                           */
     KM_OPT_KEYS = 5,      /* how the reassignment scan forms its keys
-                             |m|^2 - 2 m.x: 0 (default) automatic (currently
-                             the vector ALUs), 1 vector ALUs, 2 matrix cores
+                             |m|^2 - 2 m.x: 0 (default) automatic (matrix
+                             cores for 24 < K <= 32 and K > 44, the vector
+                             ALUs otherwise), 1 vector ALUs, 2 matrix cores
                              (one fp16 MFMA per 32 x 32 keys on hi/lo pieces
-                             of the operands; slower on gfx950, kept
-                             selectable).  Labels, centres, E and T do not
-                             depend on it.                                      */
+                             of the operands; data or centres beyond about
+                             2^36 or below 2^-48 in magnitude take the vector
+                             ALUs).  Labels, centres, E and T do not depend
+                             on it.                                             */
     KM_OPT_PERSIST = 6,   /* how kmeans_fit runs its updates: 0 (default)
                              and 1: graph replays of one launch per update
                              (measured as fast or faster at every size); 2:

@@ -100,6 +100,9 @@ int64_t min_blocks(int64_t N);
 // Grid of the per-update kernels for N points on n_cu compute units
 // (blocks_opt: KM_OPT_BLOCKS, 0 = automatic).
 int grid_blocks(int n_cu, int blocks_opt, int64_t N);
+// Scan variant of KM_OPT_KEYS = 0 (automatic) for K centres: 0 the VALU
+// keys, 1 or 2 matrix-core tiles of 32 centres.
+int auto_keys(int K);
 // Updates per graph replay when KM_OPT_UNROLL is automatic.
 int auto_unroll(int64_t N, int max_iter);
 // Device buffers a fit's state points to.

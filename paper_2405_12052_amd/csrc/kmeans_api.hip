@@ -242,11 +242,11 @@ int run_iterations(kmeans_ctx* c, int d, bool vec, int keys, int grid, int n_ite
     return KM_OK;
 }
 
-// Scan variant for K centres.  Automatic = the VALU scan: the matrix-core
-// scan takes only the FMAs off the VALU, while the compare-type tracking that
-// sets the scan's pace stays; with its MFMA time and lower occupancy it is
-// slower at K = 64 (1781 vs 1556 us per update at N = 2e8 on one box).  It
-// stays selectable.
+// Scan variant for K centres (scan_keys): the matrix-core keys take the 3 d
+// FMAs per centre off the VALU, leaving it the argmin tracking (five
+// instructions per quad of centres) and a fixed per-point cost (operands,
+// merge, re-keying the winning quad); at N = 2e8, K = 64 1203 vs 1547 us per
+// update on one box.  The VALU scan stays faster for small K.
 // Persistent fit: only when selected (KM_OPT_PERSIST = 2).  With the grid
 // of grid_for, the launch per update is as fast or faster at every size
 // measured (K = 16, per update: N = 1e6 22.3 vs 26.0 us, 4e6 37.3 vs 41.0 us,
@@ -259,13 +259,21 @@ bool use_persist(kmeans_ctx* c, int64_t N, int keys) {
 }
 
 int scan_keys(kmeans_ctx* c, int K) {
-    const int tiles = K > 32 ? 2 : 1;
     if (c->keys == 1) return 0;
-    if (c->keys == 2) return tiles;
-    return 0;
+    if (c->keys == 2) return K > 32 ? 2 : 1;
+    return km::auto_keys(K);
 }
 
 }  // namespace
+
+// The matrix-core scan where it was measured faster (N = 5e7, d = 3, per
+// update: K = 24 264 vs 273 us VALU vs matrix cores, 32 285 vs 275, 40 334
+// vs 345, 48 366 vs 347, 64 444 vs 363): its cost per point hardly depends
+// on K within a tile of 32 centres, the VALU scan's grows with K.
+int km::auto_keys(int K) {
+    if ((K > 24 && K <= 32) || K > 44) return K > 32 ? 2 : 1;
+    return 0;
+}
 
 int km::auto_unroll(int64_t N, int max_iter) {
     int u = N >= (1 << 24) ? 10 : (N >= (1 << 20) ? 16 : 32);

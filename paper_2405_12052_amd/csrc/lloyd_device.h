@@ -285,12 +285,15 @@ __device__ __forceinline__ int load_group_rt(bool vec, const float* __restrict__
 // operations).
 template <int D>
 __device__ __forceinline__ double direct_dist64(float x0, float x1, float x2, float4 c) {
+    // plain operators under contract(off): the _rn helpers' own bodies may be
+    // contracted once inlined
+#pragma clang fp contract(off)
     const double d0 = (double)x0 - (double)c.x;
     const double d1 = (double)x1 - (double)c.y;
-    double s = __dadd_rn(__dmul_rn(d0, d0), __dmul_rn(d1, d1));
+    double s = d0 * d0 + d1 * d1;
     if constexpr (D == 3) {
         const double d2 = (double)x2 - (double)c.z;
-        s = __dadd_rn(s, __dmul_rn(d2, d2));
+        s = s + d2 * d2;
     }
     return s;
 }
@@ -407,10 +410,10 @@ __device__ inline void prep_centres(const float4* m32, int K, int npad, float4* 
         float4 r = make_float4(0.f, 0.f, 0.f, 0x1p127f);
         float c = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f;
         if (tid < K) {
+#pragma clang fp contract(off)
             const float4 m = m32[tid];
-            const double q = __dadd_rn(__dadd_rn(__dmul_rn((double)m.x, (double)m.x),
-                                                 __dmul_rn((double)m.y, (double)m.y)),
-                                       __dmul_rn((double)m.z, (double)m.z));
+            const double q = ((double)m.x * (double)m.x + (double)m.y * (double)m.y) +
+                             (double)m.z * (double)m.z;
             c = (float)q;
             r = make_float4(-2.0f * m.x, -2.0f * m.y, -2.0f * m.z, c);
             a0 = fabsf(m.x); a1 = fabsf(m.y); a2 = fabsf(m.z);

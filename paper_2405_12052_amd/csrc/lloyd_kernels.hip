@@ -466,7 +466,7 @@ __device__ __forceinline__ void finalize_update(State* __restrict__ st, IterSmem
 // One update per launch (replayed from a graph): the update's pass, then the
 // final block's update of the centres.
 template <int D, bool VEC, int KT>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) void lloyd_iter(State* __restrict__ st) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) void lloyd_iter(State* __restrict__ st) {
     if (st->done) return;
     __shared__ IterSmem sm;
     const int K = st->K;
@@ -540,7 +540,7 @@ __global__ __launch_bounds__(BLOCK) void lloyd_persist(State* __restrict__ st) {
 
 // ---------------------------------------------------------------- lloyd_label
 template <int D, bool VEC, int KT>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) void lloyd_label(State* __restrict__ st,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) void lloyd_label(State* __restrict__ st,
                                                      int32_t* __restrict__ labels) {
     if (st->flags & FLAG_NONFINITE) return;
     __shared__ float4 scand[KPAD];

@@ -29,10 +29,11 @@
 //
 // A wave takes 128 points at a time: lane (c, h) loads the coordinates of
 // points 4c .. 4c+3, so "chunk" j in 0..3 is the 32 points {4c + j}.  Per
-// chunk each lane folds its 16 KT keys, in quads of result registers (four
-// consecutive centres, group number g = 4 t + r / 4 in the 3 low mantissa
-// bits of the quad's minimum), into W, the smallest packed quad minimum, and
-// L, the second smallest: five instructions per quad.  The halves are merged
+// chunk each lane reduces its 16 KT keys to one minimum per quad of result
+// registers (four consecutive centres; group number g = 4 t + r / 4 in the 3
+// low mantissa bits: three instructions per quad), and a small tournament
+// over those packed minima gives W, the smallest, and L, the second smallest
+// (12 instructions for the 8 of K > 32).  The halves are merged
 // with one lane swap per value (v_permlane32_swap), two chunks at a time, so
 // that lane half h then finishes chunk 2 pair + h.  The winning quad's four
 // centres (8 g + 4 hw + 0..3, hw the half that held it) are re-keyed on the
@@ -58,9 +59,9 @@
 // above the float64 rounding of the direct form (b carries that term): the
 // label of the VALU scan.  Other points go to the same per-wave re-scan queue.
 //
-// Range.  The scale needs 2^(2e) and the scaled bound coefficients to stay
-// finite and normal: e in [-24, 96], i.e. data and centres between about
-// 2^-84 and 2^36 in magnitude.  Outside it the pass takes the VALU scan.
+// Range.  The scale needs 2^(2e + 4) to stay finite and normal: e in
+// [-24, 60], i.e. data and centres between about 2^-48 and 2^36 in
+// magnitude.  Outside it the pass takes the VALU scan.
 #pragma once
 
 #include "lloyd_device.h"
@@ -94,52 +95,81 @@ __device__ __forceinline__ float vmax2(float a, float b) {
     return r;
 }
 
-// Fold one quad of keys (a, b, c, d) into the running (m1, m2): the quad's
-// minimum with the group number GID in its 3 low mantissa bits, m1 = the
-// smallest such value so far, m2 = the second smallest.  FIRST: the quad is
-// the first one read from a matrix-core result; its first minimum is then
-// the compiler's own instruction, which carries the wait for the matrix core
-// (the assembly that follows depends on it).
+// The minimum of one quad of keys (a, b, c, d) with the group number GID in
+// its 3 low mantissa bits.  FIRST: the quad is the first one read from a
+// matrix-core result; its first minimum is then the compiler's own
+// instruction, which carries the wait for the matrix core (the assembly that
+// follows depends on it).
 template <uint32_t GID, bool FIRST>
-__device__ __forceinline__ void fold_quad(float a, float b, float c, float d, uint32_t mask,
-                                          float ninf, float& m1, float& m2) {
+__device__ __forceinline__ float quad_min(float a, float b, float c, float d, uint32_t mask,
+                                          float ninf) {
     float t;
     if constexpr (FIRST) {
         const float ab = min2(a, b, ninf);
-        asm("v_min3_f32 %0, %3, %4, %5\n\t"
-            "v_and_or_b32 %0, %0, %6, %7\n\t"
-            "v_med3_f32 %1, %2, %1, %0\n\t"
-            "v_min_f32 %2, %2, %0"
-            : "=&v"(t), "+v"(m2), "+v"(m1)
+        asm("v_min3_f32 %0, %1, %2, %3\n\t"
+            "v_and_or_b32 %0, %0, %4, %5"
+            : "=&v"(t)
             : "v"(ab), "v"(c), "v"(d), "s"(mask), "i"(GID));
     } else {
-        asm("v_min3_f32 %0, %3, %4, %5\n\t"
-            "v_min_f32 %0, %0, %6\n\t"
-            "v_and_or_b32 %0, %0, %7, %8\n\t"
-            "v_med3_f32 %1, %2, %1, %0\n\t"
-            "v_min_f32 %2, %2, %0"
-            : "=&v"(t), "+v"(m2), "+v"(m1)
+        asm("v_min3_f32 %0, %1, %2, %3\n\t"
+            "v_min_f32 %0, %0, %4\n\t"
+            "v_and_or_b32 %0, %0, %5, %6"
+            : "=&v"(t)
             : "v"(a), "v"(b), "v"(c), "v"(d), "s"(mask), "i"(GID));
     }
+    return t;
 }
 
-// Fold the KT tiles of one chunk's keys (per lane: 16 KT) into (W, L).
-template <int KT>
-__device__ __forceinline__ void fold_chunk(const f32x16 (&s)[KT], float ninf, float& W, float& L) {
+// The four packed quad minima of one tile of keys (per lane: 16).
+template <int T>
+__device__ __forceinline__ void tile_minima(const f32x16& s, float ninf, float (&p)[4]) {
     const uint32_t mask = ~7u;
-    float m1 = INFINITY, m2 = INFINITY;
-    fold_quad<0, true>(s[0][0], s[0][1], s[0][2], s[0][3], mask, ninf, m1, m2);
-    fold_quad<1, false>(s[0][4], s[0][5], s[0][6], s[0][7], mask, ninf, m1, m2);
-    fold_quad<2, false>(s[0][8], s[0][9], s[0][10], s[0][11], mask, ninf, m1, m2);
-    fold_quad<3, false>(s[0][12], s[0][13], s[0][14], s[0][15], mask, ninf, m1, m2);
+    p[0] = quad_min<4 * T, true>(s[0], s[1], s[2], s[3], mask, ninf);
+    p[1] = quad_min<4 * T + 1, false>(s[4], s[5], s[6], s[7], mask, ninf);
+    p[2] = quad_min<4 * T + 2, false>(s[8], s[9], s[10], s[11], mask, ninf);
+    p[3] = quad_min<4 * T + 3, false>(s[12], s[13], s[14], s[15], mask, ninf);
+}
+
+// Smallest and second smallest of (a, b, c) and of (a, b, c, d): the three
+// values' minimum and median, then d merged in.
+__device__ __forceinline__ void top2_3(float a, float b, float c, float& m1, float& m2) {
+    m1 = vmin3(a, b, c);
+    m2 = __builtin_amdgcn_fmed3f(a, b, c);
+}
+
+// (m1, m2) <- the two smallest of {m1, m2, u1, u2}, given m1 <= m2, u1 <= u2.
+__device__ __forceinline__ void top2_merge(float& m1, float& m2, float u1, float u2) {
+    m2 = vmin3(vmax2(m1, u1), m2, u2);
+    m1 = vmin2(m1, u1);
+}
+
+// The keys of one chunk (B: its points' operand) against the KT tiles of
+// centres A: W, the smallest packed quad minimum, and L, the second smallest
+// (a small tournament over the 4 KT packed minima).
+template <int KT>
+__device__ __forceinline__ void chunk_keys(const f16x8 (&A)[KT], f16x8 B, float ninf, float& W,
+                                           float& L) {
+    const f32x16 zero16 = {};
+    float p[4 * KT];
+    const f32x16 k0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[0], B, zero16, 0, 0, 0);
+    tile_minima<0>(k0, ninf, reinterpret_cast<float(&)[4]>(p[0]));
     if constexpr (KT == 2) {
-        fold_quad<4, true>(s[1][0], s[1][1], s[1][2], s[1][3], mask, ninf, m1, m2);
-        fold_quad<5, false>(s[1][4], s[1][5], s[1][6], s[1][7], mask, ninf, m1, m2);
-        fold_quad<6, false>(s[1][8], s[1][9], s[1][10], s[1][11], mask, ninf, m1, m2);
-        fold_quad<7, false>(s[1][12], s[1][13], s[1][14], s[1][15], mask, ninf, m1, m2);
+        const f32x16 k1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[1], B, zero16, 0, 0, 0);
+        tile_minima<1>(k1, ninf, reinterpret_cast<float(&)[4]>(p[4]));
+        float a1, a2, b1, b2;
+        top2_3(p[0], p[1], p[2], a1, a2);
+        top2_3(p[3], p[4], p[5], b1, b2);
+        top2_merge(a1, a2, b1, b2);
+        top2_merge(a1, a2, vmin2(p[6], p[7]), vmax2(p[6], p[7]));
+        W = a1;
+        L = a2;
+    } else {
+        float a1, a2;
+        top2_3(p[0], p[1], p[2], a1, a2);
+        // d merged in: second smallest = min(a2, max(a1, d))
+        L = vmin2(a2, vmax2(a1, p[3]));
+        W = vmin2(a1, p[3]);
     }
-    W = m1;
-    L = m2;
 }
 
 // a in lane half 0, b in half 1 (hm: all ones in half 1), as one bitfield
@@ -186,7 +216,7 @@ __device__ __forceinline__ bool mfma_scale(int xe, float4 bnd, int& e) {
         const int ea = 12 - ilogbf(amax);            // |a| 2^e = 2 |m| 2^e < 2^14
         e = ea < e ? ea : e;
     }
-    return e >= -24 && e <= 96;
+    return e >= -24 && e <= 60;
 }
 
 // Reassignment of the points of this wave's share of the grid (chunks of 128
@@ -244,11 +274,9 @@ __device__ __forceinline__ void assign_points_mfma(const float* __restrict__ X, 
     const uint32_t q3 = h == 0 ? pack2((_Float16)T, (_Float16)T) : pack2((_Float16)P, (_Float16)P);
     const float s = ldexpf(1.0f, e);
     // matrix-key bound in scaled units: 16 b(x) 2^(2e) + 16 (the absolute
-    // part covers f16 subnormal pieces even if the matrix core flushed them)
-    const float bmx = ldexpf(16.0f * bnd.x, 2 * e) + 16.0f;
-    const float bmy = ldexpf(16.0f * bnd.y, 2 * e), bmz = ldexpf(16.0f * bnd.z, 2 * e),
-                bmw = ldexpf(16.0f * bnd.w, 2 * e);
-    const f32x16 zero16 = {};
+    // part covers f16 subnormal pieces even if the matrix core flushed them);
+    // the scale 2^(2e+4) <= 2^124 stays finite
+    const float bms = ldexpf(16.0f, 2 * e);
 
     int qn = 0;
     auto drain = [&](int cnt) {
@@ -268,6 +296,8 @@ __device__ __forceinline__ void assign_points_mfma(const float* __restrict__ X, 
     for (int64_t ch = (int64_t)blockIdx.x * NW + (threadIdx.x >> 6); ch < nchunks;
          ch += (int64_t)gridDim.x * NW) {
         const int64_t i0 = ch * 128 + 4 * c;  // first of this lane's 4 points
+        // points of this chunk of 128 that exist (wave-uniform)
+        const int rem = N - ch * 128 < 128 ? (int)(N - ch * 128) : 128;
         float x[3][4];
         if (VEC && i0 + 4 <= N) {
 #pragma unroll
@@ -296,12 +326,7 @@ __device__ __forceinline__ void assign_points_mfma(const float* __restrict__ X, 
                 const int j = 2 * pair + q;
                 const float u = sel_half(hm, x[0][j], x[2][j]) * s;
                 const float v = sel_half(hm, x[1][j] * s, T);
-                const f16x8 B = point_operand(u, v, q3);
-                f32x16 keys[KT];
-#pragma unroll
-                for (int t = 0; t < KT; ++t)
-                    keys[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[t], B, zero16, 0, 0, 0);
-                fold_chunk<KT>(keys, ninf, W[q], L[q]);
+                chunk_keys<KT>(A, point_operand(u, v, q3), ninf, W[q], L[q]);
             }
             // lane half h finishes chunk 2 pair + h.  After the swaps, in
             // either half, w0 / l0 come from the h = 0 lane of the point and
@@ -341,11 +366,9 @@ __device__ __forceinline__ void assign_points_mfma(const float* __restrict__ X, 
             float b = fmaf(bnd.y, fabsf(x0), bnd.x);
             b = fmaf(bnd.z, fabsf(x1), b);
             if constexpr (D == 3) b = fmaf(bnd.w, fabsf(x2), b);
-            float bm = fmaf(bmy, fabsf(x0), bmx);
-            bm = fmaf(bmz, fabsf(x1), bm);
-            if constexpr (D == 3) bm = fmaf(bmw, fabsf(x2), bm);
+            const float bm = fmaf(b, bms, 16.0f);
             const int64_t i = i0 + j;
-            const bool valid = i < N;
+            const bool valid = 4 * c + j < rem;
             const bool ok = Lc - Wc > bm && t2 - t1 > b && k < K;
             if (valid && ok) sink(i, x0, x1, x2, k, direct_dist<D>(x0, x1, x2, smu[k]));
             const bool f = valid && !ok;

@@ -148,6 +148,7 @@ extern "C" int kmeans_fit_noalloc(int device, void* hip_stream, const float* X, 
     const bool vec = vec_ok(X, ld);
     const int grid = grid_blocks(s->n_cu, 0, N);
     const int U = auto_unroll(N, max_iter);
+    const int keys = auto_keys(K);  // the scan kmeans_fit takes by default
 
     // the initial state, from this call's stack (read back into it at the end)
     State h;
@@ -162,7 +163,7 @@ extern "C" int kmeans_fit_noalloc(int device, void* hip_stream, const float* X, 
     int launched = 0;
     while (launched < max_iter) {
         const int n = (max_iter - launched) < U ? (max_iter - launched) : U;
-        for (int i = 0; i < n; ++i) NA_HIP(launch_iter(st, d, vec, 0, grid, stream));
+        for (int i = 0; i < n; ++i) NA_HIP(launch_iter(st, d, vec, keys, grid, stream));
         launched += n;
         if (tol > 0.0 && launched < max_iter) {
             NA_HIP(hipMemcpyAsync(reinterpret_cast<char*>(&h) + kProgressOffset,
@@ -172,7 +173,7 @@ extern "C" int kmeans_fit_noalloc(int device, void* hip_stream, const float* X, 
             if (h.done) break;
         }
     }
-    NA_HIP(launch_label(st, labels_out, d, vec, 0, grid, stream));
+    NA_HIP(launch_label(st, labels_out, d, vec, keys, grid, stream));
     NA_HIP(hipMemcpyAsync(reinterpret_cast<char*>(&h) + kProgressOffset,
                           reinterpret_cast<char*>(st) + kProgressOffset,
                           kUploadBytes - kProgressOffset, hipMemcpyDeviceToHost, stream));

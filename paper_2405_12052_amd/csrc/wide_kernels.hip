@@ -93,6 +93,7 @@ __device__ __forceinline__ float wide_direct(const float (&x)[D], const float4* 
 // running sum each rounded to float64, left to right): the near-tie rule.
 template <int D>
 __device__ __forceinline__ double wide_direct64(const float (&x)[D], const float4* __restrict__ c) {
+#pragma clang fp contract(off)
     double s = 0.0;
 #pragma unroll
     for (int b = 0; b < (D + 3) / 4; ++b) {
@@ -103,7 +104,7 @@ __device__ __forceinline__ double wide_direct64(const float (&x)[D], const float
             const int j = 4 * b + u;
             if (j < D) {
                 const double t = (double)x[j] - (double)mv[u];
-                s = j == 0 ? __dmul_rn(t, t) : __dadd_rn(s, __dmul_rn(t, t));
+                s = j == 0 ? t * t : s + t * t;
             }
         }
     }
