@@ -292,11 +292,12 @@ constexpr int ACC_COPY_MAX = 16;
 struct IterSmem {
     float4 scand[KPAD];
     float4 smu[KMAX];
-    // copy c at [c * K * (d+1)], coordinate-major inside: slot j * K + k.
+    // copy c at [c * KS * (d+1)], coordinate-major inside: slot j * KS + k
+    // (KS = K, or 32 KT with the matrix-core scan).
     // After the pass: the group sums and grid totals of the reduction
     // (KMAX * (DMAX + 1) i128, the same bytes).
     unsigned long long sacc[ACC_SLOTS];
-    unsigned int scnt[ACC_SLOTS / 2];  // counts, 32-bit: copy c at [c * K], slot k
+    unsigned int scnt[ACC_SLOTS / 2];  // counts, 32-bit: copy c at [c * KS], slot k
     // storage used in turn by the scan (re-scan queues), the block totals
     // until they are published, the reduction's scratch, and the final
     // block's update
@@ -364,26 +365,29 @@ __device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm
     const int tid = threadIdx.x, w = tid >> 6;
     const int64_t N = st->N, ld = st->ld;
     const float* __restrict__ X = st->X;
-    const int KR = K * R;
+    // slots per coordinate row: K, or with the matrix-core scan the compile-
+    // time 32 KT (>= K), so that the rows sit at immediate offsets
+    const int KS = KT ? 32 * KT : K;
+    const int KR = KS * R;
     const int copies = ACC_SLOTS / KR < ACC_COPY_MAX ? ACC_SLOTS / KR : ACC_COPY_MAX;
     for (int i = tid; i < copies * KR; i += BLOCK) sm.sacc[i] = 0ull;
-    for (int i = tid; i < copies * K; i += BLOCK) sm.scnt[i] = 0u;
+    for (int i = tid; i < copies * KS; i += BLOCK) sm.scnt[i] = 0u;
     __syncthreads();
 
     double jl = 0.0;
     const double fscale = fxp_scale(xe);
     unsigned long long* myacc = &sm.sacc[(tid % copies) * KR];
-    unsigned int* mycnt = &sm.scnt[(tid % copies) * K];
+    unsigned int* mycnt = &sm.scnt[(tid % copies) * KS];
     scan_points<D, VEC, KT>(X, ld, N, sm.scand, sm.smu, K, bnd, ninf, xe, sm.u.squeue[w],
                             [&](int64_t, float x0, float x1, float x2, int k, float dist) {
-        // coordinate-major slots [j * K + k]: the 64 lanes' clusters spread
+        // coordinate-major slots [j * KS + k]: the 64 lanes' clusters spread
         // over the LDS banks (a cluster-major stride of 4 int64 would put
         // every cluster on one of a few bank groups)
         unsigned long long* a = &myacc[k];
         const float xs[3] = {x0, x1, x2};
 #pragma unroll
         for (int j = 0; j < D; ++j)
-            __hip_atomic_fetch_add(&a[j * K], fxp_bits(xs[j], fscale), __ATOMIC_RELAXED,
+            __hip_atomic_fetch_add(&a[j * KS], fxp_bits(xs[j], fscale), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
         __hip_atomic_fetch_add(&mycnt[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         jl += (double)dist;
@@ -396,11 +400,11 @@ __device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm
     for (int i = tid; i < K * R; i += BLOCK) {
         const int k = i / R, j = i - k * R;
         unsigned long long n = 0ull;
-        for (int c = 0; c < copies; ++c) n += sm.scnt[c * K + k];
+        for (int c = 0; c < copies; ++c) n += sm.scnt[c * KS + k];
         unsigned long long s = n;
         if (j < D) {
             s = 0ull - n * FXP_MAGIC_BITS;
-            for (int c = 0; c < copies; ++c) s += sm.sacc[c * KR + j * K + k];
+            for (int c = 0; c < copies; ++c) s += sm.sacc[c * KR + j * KS + k];
         }
         sm.u.stot[i] = s;
     }

@@ -11,31 +11,31 @@
 // c' 2^-14 (< 3 2^12) is split into three f16 pieces, each multiplied by the
 // exact f16 constant 2^14.  The 12 terms of a real centre are 12 of the 16
 // inner-dimension entries of one 32x32x16 product (the accumulator input is
-// zero); centres past K (pads) carry instead three terms 2^15 x 2^14,
-// 2^15 x 2^15, 2^15 x 2^15 = 5 2^29, above every real key.
+// zero); centres past K (pads) carry instead the one term 2^15 x 2^15 =
+// 2^30, above every real key.
 //
 // Operand layout of the instruction (lane l, c = l % 32, h = l / 32):
 // A[m][8h + i] and B[8h + i][n] are element i of lane (m or n) + 32h's
 // 8-element operand; result register r holds row 8 (r / 4) + 4h + r % 4,
 // column c.  Rows are centres, columns points.  Inner dimension:
-//   k :  0    1    2    3    4    5    6    7  |  8    9   10   11   12  13  14  15
-//   A :  ah0  ah0  al0  ah1  ah1  al1  c1   c2 |  ah2  ah2  al2  c3   0   p   p   p
-//   B :  xh0  xl0  xh0  xh1  xl1  xh1  T    T  |  xh2  xl2  xh2  T    0   T   P   P
+//   k :  0    1    2    3    4    5    6    7  |  8    9   10   11   12   13   14  15
+//   A :  ah0  ah0  ah1  ah1  al0  al1  c1   c2 |  ah2  ah2  0    0    al2  0    c3  p
+//   B :  xh0  xl0  xh1  xl1  xh0  xh1  T    T  |  xh2  xl2  xh1  xl1  xh2  xh1  T   P
 // with T = 2^14, P = 2^15, c1 + c2 + c3 = c' 2^-14, and p = P for pads (all
 // other A entries of a pad zero), p = 0 for real centres.  Lane half h builds
-// its B operand from u = (x0 if h = 0 else x2) and v = (x1 if h = 0 else
-// T 2^-e, whose split is exactly (T, 0)) as (uh, ul), (uh, vh), (vl, vh) and
-// the constant (T, T) or (P, P): the same instructions in both halves.
+// its B operand from u = (x0 if h = 0 else x2) and v = x1 as (uh, ul),
+// (vh, vl), (uh, vh) and the constant (T, T) or (T, P): the same
+// instructions in both halves.
 //
-// A wave takes 128 points at a time: lane (c, h) loads the coordinates of
-// points 4c .. 4c+3, so "chunk" j in 0..3 is the 32 points {4c + j}.  Per
+// A wave takes 64 points at a time: lane (c, h) loads the coordinates of
+// points 2c and 2c+1, so "chunk" j in 0..1 is the 32 points {2c + j}.  Per
 // chunk each lane reduces its 16 KT keys to one minimum per quad of result
 // registers (four consecutive centres; group number g = 4 t + r / 4 in the 3
 // low mantissa bits: three instructions per quad), and a small tournament
 // over those packed minima gives W, the smallest, and L, the second smallest
 // (12 instructions for the 8 of K > 32).  The halves are merged
 // with one lane swap per value (v_permlane32_swap), two chunks at a time, so
-// that lane half h then finishes chunk 2 pair + h.  The winning quad's four
+// that lane half h then finishes chunk h.  The winning quad's four
 // centres (8 g + 4 hw + 0..3, hw the half that held it) are re-keyed on the
 // VALU exactly as the VALU scan keys them, giving the quad's smallest key t1
 // (first index) and second smallest t2.
@@ -190,13 +190,14 @@ __device__ __forceinline__ uint32_t pack2(_Float16 lo, _Float16 hi) {
     return __builtin_bit_cast(uint32_t, v);
 }
 
-// The B operand of one point for this lane half from the scaled u, v (see
-// the file header) and the half's constant register q3.
+// The B operand of one point for this lane half from the scaled u and v = x1
+// (see the file header): (uh, ul), (vh, vl), (uh, vh) and the half's
+// constant register q3.
 __device__ __forceinline__ f16x8 point_operand(float u, float v, uint32_t q3) {
     _Float16 uh, ul, vh, vl;
     split_f16(u, uh, ul);
     split_f16(v, vh, vl);
-    const u32x4 r = {pack2(uh, ul), pack2(uh, vh), pack2(vl, vh), q3};
+    const u32x4 r = {pack2(uh, ul), pack2(vh, vl), pack2(uh, vh), q3};
     return __builtin_bit_cast(f16x8, r);
 }
 
@@ -254,10 +255,10 @@ __device__ __forceinline__ void assign_points_mfma(const float* __restrict__ X, 
             const _Float16 c2 = (_Float16)r1;
             const _Float16 c3 = (_Float16)(r1 - (float)c2);
             if (h == 0) {
-                const f16x8 a = {h0, h0, l0, h1, h1, l1, c1, c2};
+                const f16x8 a = {h0, h0, h1, h1, l0, l1, c1, c2};
                 A[t] = a;
             } else {
-                const f16x8 a = {h2, h2, l2, c3, z, z, z, z};
+                const f16x8 a = {h2, h2, z, z, l2, z, c3, z};
                 A[t] = a;
             }
         } else {
@@ -265,13 +266,13 @@ __device__ __forceinline__ void assign_points_mfma(const float* __restrict__ X, 
             if (h == 0) {
                 A[t] = zero_operand();
             } else {
-                const f16x8 a = {z, z, z, z, z, p, p, p};
+                const f16x8 a = {z, z, z, z, z, z, z, p};
                 A[t] = a;
             }
         }
     }
     const uint32_t hm = h ? ~0u : 0u;  // lane half as a bit mask
-    const uint32_t q3 = h == 0 ? pack2((_Float16)T, (_Float16)T) : pack2((_Float16)P, (_Float16)P);
+    const uint32_t q3 = h == 0 ? pack2((_Float16)T, (_Float16)T) : pack2((_Float16)T, (_Float16)P);
     const float s = ldexpf(1.0f, e);
     // matrix-key bound in scaled units: 16 b(x) 2^(2e) + 16 (the absolute
     // part covers f16 subnormal pieces even if the matrix core flushed them);
@@ -292,92 +293,89 @@ __device__ __forceinline__ void assign_points_mfma(const float* __restrict__ X, 
         qn -= cnt;
     };
 
-    const int64_t nchunks = (N + 127) / 128;
-    for (int64_t ch = (int64_t)blockIdx.x * NW + (threadIdx.x >> 6); ch < nchunks;
+    const int64_t nchunks = (N + 63) / 64;
+    // the wave's index, known to the compiler as uniform (scalar registers)
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int64_t ch = (int64_t)blockIdx.x * NW + wid; ch < nchunks;
          ch += (int64_t)gridDim.x * NW) {
-        const int64_t i0 = ch * 128 + 4 * c;  // first of this lane's 4 points
-        // points of this chunk of 128 that exist (wave-uniform)
-        const int rem = N - ch * 128 < 128 ? (int)(N - ch * 128) : 128;
-        float x[3][4];
-        if (VEC && i0 + 4 <= N) {
+        const int64_t i0 = ch * 64 + 2 * c;  // first of this lane's 2 points
+        // points of this chunk pair that exist (wave-uniform)
+        const int rem = N - ch * 64 < 64 ? (int)(N - ch * 64) : 64;
+        float x[3][2];
+        if (VEC && i0 + 2 <= N) {
 #pragma unroll
             for (int j = 0; j < D; ++j) {
-                const float4 v = *reinterpret_cast<const float4*>(X + j * ld + i0);
-                x[j][0] = v.x; x[j][1] = v.y; x[j][2] = v.z; x[j][3] = v.w;
+                const float2 v = *reinterpret_cast<const float2*>(X + j * ld + i0);
+                x[j][0] = v.x; x[j][1] = v.y;
             }
         } else {
 #pragma unroll
-            for (int p = 0; p < 4; ++p) {
+            for (int p = 0; p < 2; ++p) {
                 const bool in = i0 + p < N;
 #pragma unroll
                 for (int j = 0; j < D; ++j) x[j][p] = in ? X[j * ld + i0 + p] : 0.0f;
             }
         }
         if constexpr (D == 2) {
-#pragma unroll
-            for (int p = 0; p < 4; ++p) x[2][p] = 0.0f;
+            x[2][0] = 0.0f;
+            x[2][1] = 0.0f;
         }
 
+        float W[2], L[2];
 #pragma unroll
-        for (int pair = 0; pair < 2; ++pair) {
-            float W[2], L[2];
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int j = 2 * pair + q;
-                const float u = sel_half(hm, x[0][j], x[2][j]) * s;
-                const float v = sel_half(hm, x[1][j] * s, T);
-                chunk_keys<KT>(A, point_operand(u, v, q3), ninf, W[q], L[q]);
-            }
-            // lane half h finishes chunk 2 pair + h.  After the swaps, in
-            // either half, w0 / l0 come from the h = 0 lane of the point and
-            // w1 / l1 from the h = 1 lane.
-            const auto ws = __builtin_amdgcn_permlane32_swap(__float_as_uint(W[0]),
-                                                              __float_as_uint(W[1]), false, false);
-            const auto ls = __builtin_amdgcn_permlane32_swap(__float_as_uint(L[0]),
-                                                              __float_as_uint(L[1]), false, false);
-            const float w0 = __uint_as_float(ws[0]), w1 = __uint_as_float(ws[1]);
-            const float l0 = __uint_as_float(ls[0]), l1 = __uint_as_float(ls[1]);
-            const float Wc = vmin2(w0, w1);
-            const float Lc = vmin3(vmax2(w0, w1), l0, l1);
-            const int hw = w1 < w0 ? 1 : 0;
-            // this lane's point: chunk 2 pair + h (selected, not indexed:
-            // a lane-dependent index would put x in scratch memory)
-            const float x0 = sel_half(hm, x[0][2 * pair], x[0][2 * pair + 1]);
-            const float x1 = sel_half(hm, x[1][2 * pair], x[1][2 * pair + 1]);
-            const float x2 = sel_half(hm, x[2][2 * pair], x[2][2 * pair + 1]);
-            const int j = 2 * pair + h;
-            // the winning quad: centres 8 g + 4 hw + 0..3 (records padded to KPAD)
-            const int base = ((int)(__float_as_uint(Wc) & 7u) << 3) | (hw << 2);
-            const float s0 = expanded_key<D>(x0, x1, x2, scand[base]);
-            const float s1 = expanded_key<D>(x0, x1, x2, scand[base + 1]);
-            const float s2 = expanded_key<D>(x0, x1, x2, scand[base + 2]);
-            const float s3 = expanded_key<D>(x0, x1, x2, scand[base + 3]);
-            const float a3 = fminf(fminf(s0, s1), s2);
-            const float t1 = fminf(a3, s3);
-            // second smallest of the four: of the first three, or max(their
-            // minimum, s3)
-            const float t2 = fminf(__builtin_amdgcn_fmed3f(s0, s1, s2), fmaxf(a3, s3));
-            // first index attaining t1 (selects, not branches)
-            int kq = 3;
-            kq = s2 == t1 ? 2 : kq;
-            kq = s1 == t1 ? 1 : kq;
-            kq = s0 == t1 ? 0 : kq;
-            const int k = base + kq;
-            float b = fmaf(bnd.y, fabsf(x0), bnd.x);
-            b = fmaf(bnd.z, fabsf(x1), b);
-            if constexpr (D == 3) b = fmaf(bnd.w, fabsf(x2), b);
-            const float bm = fmaf(b, bms, 16.0f);
-            const int64_t i = i0 + j;
-            const bool valid = 4 * c + j < rem;
-            const bool ok = Lc - Wc > bm && t2 - t1 > b && k < K;
-            if (valid && ok) sink(i, x0, x1, x2, k, direct_dist<D>(x0, x1, x2, smu[k]));
-            const bool f = valid && !ok;
-            const uint64_t m = __ballot(f);
-            if (m) {
-                if (f) wq[qn + __popcll(m & below)] = make_float4(x0, x1, x2, __int_as_float((int)i));
-                qn += __popcll(m);
-                if (qn >= 64) drain(64);
-            }
+        for (int q = 0; q < 2; ++q) {
+            const float u = sel_half(hm, x[0][q], x[2][q]) * s;
+            const float v = x[1][q] * s;
+            chunk_keys<KT>(A, point_operand(u, v, q3), ninf, W[q], L[q]);
+        }
+        // lane half h finishes chunk h.  After the swaps, in either half,
+        // w0 / l0 come from the h = 0 lane of the point and w1 / l1 from the
+        // h = 1 lane.
+        const auto ws = __builtin_amdgcn_permlane32_swap(__float_as_uint(W[0]),
+                                                          __float_as_uint(W[1]), false, false);
+        const auto ls = __builtin_amdgcn_permlane32_swap(__float_as_uint(L[0]),
+                                                          __float_as_uint(L[1]), false, false);
+        const float w0 = __uint_as_float(ws[0]), w1 = __uint_as_float(ws[1]);
+        const float l0 = __uint_as_float(ls[0]), l1 = __uint_as_float(ls[1]);
+        const float Wc = vmin2(w0, w1);
+        const float Lc = vmin3(vmax2(w0, w1), l0, l1);
+        const int hw = w1 < w0 ? 1 : 0;
+        // this lane's point: chunk h (selected, not indexed: a lane-dependent
+        // index would put x in scratch memory)
+        const float x0 = sel_half(hm, x[0][0], x[0][1]);
+        const float x1 = sel_half(hm, x[1][0], x[1][1]);
+        const float x2 = sel_half(hm, x[2][0], x[2][1]);
+        // the winning quad: centres 8 g + 4 hw + 0..3 (records padded to KPAD)
+        const int base = ((int)(__float_as_uint(Wc) & 7u) << 3) | (hw << 2);
+        const float s0 = expanded_key<D>(x0, x1, x2, scand[base]);
+        const float s1 = expanded_key<D>(x0, x1, x2, scand[base + 1]);
+        const float s2 = expanded_key<D>(x0, x1, x2, scand[base + 2]);
+        const float s3 = expanded_key<D>(x0, x1, x2, scand[base + 3]);
+        const float a3 = fminf(fminf(s0, s1), s2);
+        const float t1 = fminf(a3, s3);
+        // second smallest of the four: of the first three, or max(their
+        // minimum, s3)
+        const float t2 = fminf(__builtin_amdgcn_fmed3f(s0, s1, s2), fmaxf(a3, s3));
+        // first index attaining t1 (selects, not branches)
+        int kq = 3;
+        kq = s2 == t1 ? 2 : kq;
+        kq = s1 == t1 ? 1 : kq;
+        kq = s0 == t1 ? 0 : kq;
+        const int k = base + kq;
+        float b = fmaf(bnd.y, fabsf(x0), bnd.x);
+        b = fmaf(bnd.z, fabsf(x1), b);
+        if constexpr (D == 3) b = fmaf(bnd.w, fabsf(x2), b);
+        const float bm = fmaf(b, bms, 16.0f);
+        const int64_t i = i0 + h;
+        const bool valid = 2 * c + h < rem;
+        const bool ok = Lc - Wc > bm && t2 - t1 > b && k < K;
+        if (valid && ok) sink(i, x0, x1, x2, k, direct_dist<D>(x0, x1, x2, smu[k]));
+        const bool f = valid && !ok;
+        const uint64_t m = __ballot(f);
+        if (m) {
+            if (f) wq[qn + __popcll(m & below)] = make_float4(x0, x1, x2, __int_as_float((int)i));
+            qn += __popcll(m);
+            if (qn >= 64) drain(64);
         }
     }
     if (qn > 0) drain(qn);
