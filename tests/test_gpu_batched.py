@@ -130,3 +130,41 @@ def test_tuner_and_cache(km, tmp_path):
     assert again == best and len(open(cache).read().strip().splitlines()) == 1
     assert km.batched_schedule() == best
     km.set_batched_schedule(0, 0, 0.0)
+
+
+def test_bench_size_slice_on_teams(km):
+    """The largest instances of the 4096-instance batch the benchmark times
+    (N close to 1e6, 8 restarts each), run as teams of 8 blocks as the tuned
+    schedule runs them: every restart's T and objective equal a single fit
+    from the same start, and the kept restart equals the float64 oracle (T,
+    centres, E, objective, labels at its final centres)."""
+    specs = datagen.batched_specs(4096)
+    big = sorted(range(len(specs)), key=lambda i: -specs[i].N)[:6]
+    sub = [specs[i] for i in big]
+    log("bench-size slice: " + ", ".join(f"{s.name} N={s.N} d={s.d} K={s.K}" for s in sub))
+    flat, offs, inits = datagen.batched_generate(sub)
+    dev = torch.from_numpy(flat).cuda()
+    inst, host = [], []
+    for s, off, ini in zip(sub, offs, inits):
+        ld = datagen.round_up(s.N, 4)
+        inst.append((dev[off:off + s.d * ld].view(s.d, ld), s.N, ini))
+        host.append(flat[off:off + s.d * ld].reshape(s.d, ld))
+    km.set_batched_schedule(8, 2, 0.0)
+    try:
+        out = km.fit_batched(inst, tol=1e-6, max_iter=300)
+    finally:
+        km.set_batched_schedule(0, 0, 0.0)
+    for s, (X, N, ini), r, h in zip(sub, inst, out, host):
+        singles = [km.fit(X, ini[q], tol=1e-6, max_iter=300, N=N, labels=False)
+                   for q in range(len(ini))]
+        assert r["restart_iters"].tolist() == [f.iters for f in singles], s.name
+        assert np.allclose(r["restart_objective"], [f.objective for f in singles],
+                           rtol=1e-12, atol=0), s.name
+        b = r["best_restart"]
+        ref = oracle.fit(h, ini[b], tol=1e-6, max_iter=300, N=N)
+        assert r["iters"] == ref["T"], s.name
+        centre_check(r["centroids"], ref["mu"])
+        e_check(r["E"], ref["E"])
+        assert abs(r["objective"] - ref["J"]) <= 1e-6 * ref["J"], s.name
+        label_check(r["labels"].cpu().numpy(), h, r["centroids"], N=N)
+        log(f"  {s.name}: kept restart {b}, T={ref['T']}, oracle parity")
