@@ -348,6 +348,10 @@ def learned_vs_plain(km, seeds, weights, repeats=3, progress=False):
                 np.mean((a[m][:, 2] <= 1.001 * base[:, 2]) & (a[m][:, 0] < base[:, 0]))),
         }
     summary["learned"]["fallbacks"] = int(sum(r[3] for r in rec["learned"]))
+    summary["per_instance"] = [
+        {"seed": int(sd), **{m: {"ms": float(a[m][i, 0] * 1e3), "T": int(a[m][i, 1]),
+                                "J": float(a[m][i, 2])} for m in methods}}
+        for i, sd in enumerate(seeds)]
     return summary
 
 
@@ -384,11 +388,13 @@ def bench_learned(args):
 def bench_configs(args):
     """Time-to-converge on the small and medium workloads (N=1e5 2-D K=4;
     N=1e7 3-D K=16; N=1e6 3-D K=16) and on the shapes of the paper's timing
-    tables (2-D N=5e5 and 3-D N=1e6 with K = 4, 8, 11; 2-D K=8 with N = 1e5,
-    2e5, 5e5; 3-D K=4 with N = 1e5 .. 1e6), on synthetic stand-ins of its
-    unpublished Gaussian-mixture datasets: GPU (kmeans_fit, points resident)
-    beside the float64 CPU oracle with 1 .. all host threads.  E < 1e-6, as the
-    paper's tolerance, or the workload's cap."""
+    tables (2-D N=5e5 and 3-D N=1e6 with K = 4, 8, 11), and two fixed-K series
+    over N (2-D K=8, 3-D K=4: its Tables 2-3 and time-vs-N figures), on
+    synthetic stand-ins of its unpublished Gaussian-mixture datasets: GPU
+    (kmeans_fit, points resident) beside the float64 CPU oracle with 1 .. all
+    host threads up to 2e6 points, with the speedup T_1/T_p and efficiency
+    speedup/p of the oracle's threads.  E < 1e-6, as the paper's tolerance, or
+    the workload's cap."""
     import numpy as np
     import torch
 
@@ -417,40 +423,58 @@ def bench_configs(args):
         return time.perf_counter() - t, f["T"], f["J"]
 
     rows = []
-    cases = [("N=1e5, d=2, K=4 (isotropic, equal weights)", datagen.spec("C1"), 100),
-             ("N=1e6, d=3, K=16 (axis-aligned, Dirichlet, 1% noise)", datagen.spec("C5"), 300),
-             ("N=1e7, d=3, K=16 (axis-aligned, Dirichlet, 1% noise)", datagen.spec("C2"), 300)]
+    cases = [("N=1e5, d=2, K=4 (isotropic, equal weights)", datagen.spec("C1"), 100, True),
+             ("N=1e6, d=3, K=16 (axis-aligned, Dirichlet, 1% noise)", datagen.spec("C5"), 300, True),
+             ("N=1e7, d=3, K=16 (axis-aligned, Dirichlet, 1% noise)", datagen.spec("C2"), 300, True)]
     for K in (4, 8, 11):
         cases.append((f"paper Table 1 shape: N=5e5, d=2, K={K}",
-                      datagen.spec("C1", N=500_000, K=K, seed=31000 + K), 1000))
+                      datagen.spec("C1", N=500_000, K=K, seed=31000 + K), 1000, True))
         cases.append((f"paper Table 1 shape: N=1e6, d=3, K={K}",
-                      datagen.spec("C2", N=1_000_000, K=K, seed=32000 + K), 1000))
-    for N in (100_000, 200_000):
-        cases.append((f"paper Table 2 shape: N={N}, d=2, K=8",
-                      datagen.spec("C1", N=N, K=8, seed=33000 + N // 1000), 1000))
-    for N in (100_000, 200_000, 400_000, 800_000):
-        cases.append((f"paper Table 3 shape: N={N}, d=3, K=4",
-                      datagen.spec("C2", N=N, K=4, seed=34000 + N // 1000), 1000))
-    for name, s, max_iter in cases:
+                      datagen.spec("C2", N=1_000_000, K=K, seed=32000 + K), 1000, True))
+    # the paper's Tables 2 (2-D, K = 8) and 3 (3-D, K = 4) and its time-vs-N
+    # figures: fixed-K series over N, beside the oracle up to 2e6 points and
+    # on the GPU alone beyond
+    for N in (100_000, 200_000, 500_000, 1_000_000, 2_000_000, 10_000_000, 100_000_000):
+        cases.append((f"series 2-D K=8 (paper Table 2 shape): N={N}",
+                      datagen.spec("C1", N=N, K=8, seed=33000 + N // 1000), 1000, N <= 2_000_000))
+    for N in (100_000, 200_000, 400_000, 800_000, 1_000_000, 2_000_000, 10_000_000, 100_000_000):
+        cases.append((f"series 3-D K=4 (paper Table 3 shape): N={N}",
+                      datagen.spec("C2", N=N, K=4, seed=34000 + N // 1000), 1000, N <= 2_000_000))
+    for name, s, max_iter, with_oracle in cases:
         X, _ = datagen.generate(s)
         Xd = torch.from_numpy(X).cuda()
         mu0 = datagen.init_sample(X, s.N, s.K, s.init_seed)
         g_s, g_T, g_J = gpu_time(Xd, mu0, max_iter)
         row = {"workload": name, "N": s.N, "d": s.d, "K": s.K, "T": g_T,
                "gpu_ms": g_s * 1e3, "gpu_point_updates_per_s": s.N * g_T / g_s, "oracle": {}}
-        big = s.N * s.K > 5e7
-        for p in thread_counts:
-            # a bounded number of updates on one thread for the largest case
-            cap = 5 if (big and p == 1) else None
-            o_s, o_T, o_J = oracle_time(X, mu0, max_iter, p, cap)
-            row["oracle"][str(p)] = {"s": o_s, "T": o_T, "point_updates_per_s": s.N * o_T / o_s}
-            if cap is None:
-                # the same run: same number of updates, same objective
-                row["oracle"][str(p)]["same_T"] = o_T == g_T
-                row["oracle"][str(p)]["J_rel_diff"] = abs(o_J - g_J) / max(abs(o_J), 1e-300)
+        if with_oracle:
+            big = s.N * s.K > 5e7
+            for p in thread_counts:
+                # a bounded number of updates on one thread for the largest case
+                cap = 5 if (big and p == 1) else None
+                o_s, o_T, o_J = oracle_time(X, mu0, max_iter, p, cap)
+                row["oracle"][str(p)] = {"s": o_s, "T": o_T, "point_updates_per_s": s.N * o_T / o_s}
+                if cap is None:
+                    # the same run: same number of updates, same objective
+                    row["oracle"][str(p)]["same_T"] = o_T == g_T
+                    row["oracle"][str(p)]["J_rel_diff"] = abs(o_J - g_J) / max(abs(o_J), 1e-300)
+            # speedup psi_p = T_1 / T_p and efficiency eps_p = psi_p / p of the
+            # oracle's threads (the paper's scaling measures), and the GPU's
+            # speedup over one and over all host threads; a capped one-thread
+            # run is scaled to the full T from its rate
+            o1 = row["oracle"]["1"]
+            t1 = o1["s"] if o1["T"] == g_T else o1["s"] * g_T / o1["T"]
+            row["t1_estimated_from_rate"] = o1["T"] != g_T
+            tp = {p: (t1 if p == "1" else row["oracle"][p]["s"]) for p in row["oracle"]}
+            row["speedup"] = {p: t1 / tp[p] for p in row["oracle"]}
+            row["efficiency"] = {p: row["speedup"][p] / int(p) for p in row["oracle"]}
+            row["gpu_speedup_vs_1_thread"] = t1 / g_s
+            row["gpu_speedup_vs_all_threads"] = row["oracle"][str(all_threads)]["s"] / g_s
         rows.append(row)
-        log(f"{name}: T={g_T} GPU {g_s * 1e3:.2f} ms, oracle {all_threads} threads "
-            f"{row['oracle'][str(all_threads)]['s'] * 1e3:.1f} ms")
+        msg = f"{name}: T={g_T} GPU {g_s * 1e3:.2f} ms"
+        if with_oracle:
+            msg += f", oracle {all_threads} threads {row['oracle'][str(all_threads)]['s'] * 1e3:.1f} ms"
+        log(msg)
         del Xd
     oracle.threads(all_threads)
     km.close()
@@ -601,6 +625,7 @@ def main():
             weights = torch.from_numpy(initnet.load_weights(initnet.DEFAULT_WEIGHTS)).cuda()
             seeds = [9_000_000 + i for i in range(args.learned_instances)]
             summ = learned_vs_plain(km, seeds, weights, repeats=3)
+            summ.pop("per_instance")
             ttc["learned_vs_plain"] = {
                 "workload": f"{len(seeds)} held-out instances (seeds 9000000+i), N=1e6, d=3, "
                             "K=16 axis-aligned mixture with 1% noise; E<1e-6 or 300 updates; "
