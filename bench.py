@@ -521,6 +521,9 @@ def main():
                     help="before the workload, copy a device buffer of BYTES twice (a plain "
                          "copy kernel of known size, to calibrate traffic counters)")
     ap.add_argument("--print-source-hash", action="store_true")
+    ap.add_argument("--track", action="store_true",
+                    help="time the fits with indicator tracking on (KM_OPT_TRACK: labels read "
+                         "and rewritten every update, changed-label counts)")
     ap.add_argument("--keys", type=int, default=0, choices=[0, 1, 2],
                     help="reassignment scan (KM_OPT_KEYS): 0 automatic (matrix cores at K = 64), "
                          "1 VALU, 2 matrix cores")
@@ -562,7 +565,7 @@ def main():
     import torch
 
     import datagen
-    from paper_2405_12052_amd import KM_OPT_KEYS, KM_OPT_TIMING, KMeans
+    from paper_2405_12052_amd import KM_OPT_KEYS, KM_OPT_TIMING, KM_OPT_TRACK, KMeans
 
     s = datagen.spec("C3") if args.N is None else datagen.spec("C3", N=args.N)
     K = s.K if args.K is None else args.K
@@ -576,6 +579,7 @@ def main():
     km = KMeans(0)
     km.set_option(KM_OPT_TIMING, 1)
     km.set_option(KM_OPT_KEYS, args.keys)
+    km.set_option(KM_OPT_TRACK, 1 if args.track else 0)
     for i in range(args.warmup):
         r = km.fit(Xd, mu0, tol=0.0, max_iter=args.iters)
         log(f"warmup {i}: T={r.iters} J={r.objective:.6e}")
@@ -590,6 +594,9 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t
     assert r.iters == args.iters
+    if args.track:
+        log(f"changed labels per update: {km.changes()[:5].tolist()} ... {km.changes()[-3:].tolist()}")
+        km.set_option(KM_OPT_TRACK, 0)
     log(f"timed {args.steps} fits in {el:.3f}s; iteration kernel {kern_ms / kern_n * 1e3:.1f} us")
 
     pt_iters = s.N * args.iters * args.steps
@@ -600,8 +607,10 @@ def main():
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
             "traffic": (traffic_from_profile("lloyd_iter_C3_traffic.json")
-                        if args.keys == 0 and args.N is None and args.K is None else None),
-            "kernel": f"lloyd_iter<{s.d},true,{scan_tiles(K, args.keys)}>",
+                        if args.keys == 0 and args.N is None and args.K is None
+                        and not args.track else None),
+            "kernel": f"lloyd_iter{'_track' if args.track else ''}<{s.d},true,"
+                      f"{scan_tiles(K, args.keys)}>",
             "avg_launch_us": avg_kernel_s * 1e6,
             "alg_flops_per_launch": flops,
             "alg_bytes_per_launch": alg_bytes_per_point(s.d) * s.N,
@@ -649,7 +658,8 @@ def main():
                                f"Gaussian mixture, float32 SoA, seeded-sample init, "
                                f"{args.iters} updates (tol=0) + final labels",
                    "N": s.N, "d": s.d, "K": K, "iterations": args.iters,
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU",
+                   **({"indicator_tracking": True} if args.track else {})},
         "roofline": roof,
         "cpu_baseline": cpu,
         "measured_peaks": measured,

@@ -128,10 +128,29 @@ enum km_option {
                              one persistent cooperative launch whenever the
                              VALU scan is used and the grid fits on the
                              device.  Results do not depend on it.             */
-    KM_OPT_WIDE = 7       /* 1: run kmeans_fit and kmeans_assign on the
+    KM_OPT_WIDE = 7,      /* 1: run kmeans_fit and kmeans_assign on the
                              general-shape kernels for every shape (a cross-
                              check of the two implementations); 0 (default):
                              only for shapes outside d in {2, 3}, K <= 64.     */
+    KM_OPT_TRACK = 8      /* indicator tracking ("The Lloyd's Algorithm": the
+                             iteration has converged once no cluster indicator
+                             changes).  1: kmeans_fit keeps every point's label
+                             in labels_out (required, device, N int32) from
+                             update to update -- each update reads a point's
+                             previous label and writes the new one where it
+                             differs (4 to 8 more bytes of traffic per point
+                             and update) -- counts the points whose label
+                             changed (kmeans_get_changes; the first update
+                             counts all N) and also stops after the first
+                             update that changes none (converged = 1).  The
+                             per-cluster sums are exact, so that update's E is
+                             0 and the centres, labels and T are those of
+                             tol = 4.9e-324 unless an update trades points
+                             between clusters without changing any sum (two
+                             distinct points equal on the sums' grid of
+                             2^(ilogb(max|x|) - 43) swapping clusters).  0
+                             (default): off.  Not with kmeans_fit_batched or
+                             kmeans_fit_noalloc.                              */
 };
 
 /*
@@ -228,6 +247,14 @@ int kmeans_set_option(kmeans_ctx *ctx, int32_t option, int64_t value);
  * negative status).
  */
 int kmeans_get_history(kmeans_ctx *ctx, double *E, double *J, int32_t cap);
+
+/*
+ * With KM_OPT_TRACK on during the last kmeans_fit on `ctx`: the number of
+ * points whose label changed in each update (the first update: N).  Copies
+ * min(cap, T) entries into `changed` (host, may be NULL) and returns that
+ * count; KM_EINVAL if the last fit did not track its indicators.
+ */
+int kmeans_get_changes(kmeans_ctx *ctx, int64_t *changed, int32_t cap);
 
 /*
  * With KM_OPT_TIMING on: total device time (ms, HIP events on the context's

@@ -175,3 +175,33 @@ def fit(X, mu0, tol=1e-6, max_iter=100, N=None, assign_f32=True, labels=True):
             "J": J.value, "converged": bool(conv.value),
             "E_hist": Eh[:T.value].copy(), "J_hist": Jh[:T.value].copy(),
             "empty_events": ev.value}
+
+
+def fit_track(X, mu0, tol=0.0, max_iter=100, N=None, assign_f32=True):
+    """Lloyd's algorithm with the indicators tracked from update to update
+    (section "The Lloyd's Algorithm": the iteration has converged once no
+    cluster indicator changes).  Update t assigns every point to its nearest
+    centre of mu^t (the step above), counts the points whose label differs
+    from update t-1's (every point at t = 0, when there is none) and forms
+    mu^{t+1}; the loop stops after the first update that changes no label,
+    or whose E is below tol, or after max_iter updates.  Returns a dict with
+    the final centres, T, E, the per-update changed counts and E history,
+    whether it converged, and the labels of the last update."""
+    mu = np.ascontiguousarray(mu0, dtype=np.float64)
+    prev = None
+    changed, E_hist = [], []
+    conv = False
+    r = None
+    for t in range(max_iter):
+        r = step(X, mu, N=N, assign_f32=assign_f32)
+        lab = r["labels"]
+        c = int(lab.shape[0]) if prev is None else int(np.count_nonzero(lab != prev))
+        changed.append(c)
+        E_hist.append(r["E"])
+        mu = r["mu"]
+        prev = lab
+        if c == 0 or r["E"] < tol:
+            conv = True
+            break
+    return {"mu": mu, "T": len(changed), "E": r["E"], "changed": np.array(changed, np.int64),
+            "E_hist": np.array(E_hist), "converged": conv, "labels": prev}

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libkmeans_mi355x.so")
 KM_OK, KM_EINVAL, KM_ENODEV, KM_EHIP, KM_ENOMEM, KM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 KM_OPT_GRAPH, KM_OPT_UNROLL, KM_OPT_BLOCKS, KM_OPT_TIMING, KM_OPT_KEYS, KM_OPT_PERSIST = 1, 2, 3, 4, 5, 6
 KM_OPT_WIDE = 7
+KM_OPT_TRACK = 8
 
 
 class KMeansError(RuntimeError):
@@ -77,6 +78,7 @@ def load_library():
         "kmeans_fit": (C.c_int, [vp, f32p, C.c_int64, C.c_int64, C.c_int32, C.c_int32, f64p,
                                  C.c_double, C.c_int32, f64p, i32p, C.POINTER(km_result)]),
         "kmeans_get_history": (C.c_int, [vp, f64p, f64p, C.c_int32]),
+        "kmeans_get_changes": (C.c_int, [vp, vp, C.c_int32]),
         "kmeans_get_timing": (C.c_int, [vp, f64p, C.POINTER(C.c_int64)]),
         "kmeans_fit_batched": (C.c_int, [vp, C.c_int32, C.POINTER(km_instance), C.c_double,
                                          C.c_int32]),
@@ -384,6 +386,14 @@ class KMeans:
         if n < 0:
             self._check(n)
         return E[:n].copy(), J[:n].copy()
+
+    def changes(self, cap: int = 1 << 20):
+        """Per-update changed-label counts of the last fit (KM_OPT_TRACK)."""
+        out = np.empty(cap, np.int64)
+        n = self._lib.kmeans_get_changes(self._ctx, out.ctypes.data_as(C.c_void_p), cap)
+        if n < 0:
+            self._check(n)
+        return out[:n].copy()
 
     def timing(self):
         ms = C.c_double()

@@ -13,9 +13,10 @@
 namespace km {
 
 struct GraphKey {
-    int d, vec, keys, grid, unroll;
+    int d, vec, keys, track, grid, unroll;
     bool operator<(const GraphKey& o) const {
-        return std::tie(d, vec, keys, grid, unroll) < std::tie(o.d, o.vec, o.keys, o.grid, o.unroll);
+        return std::tie(d, vec, keys, track, grid, unroll) <
+               std::tie(o.d, o.vec, o.keys, o.track, o.grid, o.unroll);
     }
 };
 
@@ -42,7 +43,8 @@ struct kmeans_ctx {
     unsigned long long* gpart = nullptr;  // [MAX_GROUPS][PART]
     double* gjpart = nullptr;          // [MAX_GROUPS]
     uint32_t* gticket = nullptr;       // [MAX_GROUPS]
-    double* hist = nullptr;            // [2 * hist_cap]: E then J
+    double* hist = nullptr;            // [3 * hist_cap]: E, J, then the changed-label
+                                       // counts (int64) of indicator tracking
     int hist_cap = 0;
     double* hist_h = nullptr;          // pinned copy of the history
     std::string err;
@@ -53,6 +55,8 @@ struct kmeans_ctx {
     int timing = 0;
     int keys = 0;                      // KM_OPT_KEYS
     int persist = 0;                   // KM_OPT_PERSIST
+    int track = 0;                     // KM_OPT_TRACK
+    int last_track = 0;                // the last fit tracked its indicators
     int persist_bpc[2][2] = {{0, 0}, {0, 0}};  // resident blocks per CU of lloyd_persist [d==3][vec]
     // graph cache
     std::map<km::GraphKey, hipGraphExec_t> graphs;
@@ -78,7 +82,8 @@ namespace km {
 // return `code`.
 int fail(kmeans_ctx* c, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
 int check_device_ptr(kmeans_ctx* c, const void* p, const char* what);
-// Device history of E and J with room for cap updates (kmeans_api.hip).
+// Device history of E, J and the changed-label counts with room for cap
+// updates (kmeans_api.hip).
 int ensure_hist(kmeans_ctx* c, int cap);
 // At least n timing events in c->ev (kmeans_api.hip).
 int ensure_events(kmeans_ctx* c, size_t n);
@@ -112,7 +117,8 @@ struct FitBufs {
     unsigned long long* gpart;
     double* gjpart;
     uint32_t* gticket;
-    double* hist;   // [2 * hist_cap]: E then J
+    double* hist;   // [hist_cap] E, then [hist_cap] J
+    int64_t* chist; // [hist_cap] changed-label counts, or null (no tracking)
     int hist_cap;
 };
 // Host copy of the state of a fit (or reassignment) of the given problem.

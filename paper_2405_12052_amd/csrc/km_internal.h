@@ -52,6 +52,10 @@ struct alignas(16) State {
     uint32_t* gticket;     // [MAX_GROUPS] blocks finished per group
     double* E_hist;        // [hist_cap]
     double* J_hist;        // [hist_cap]
+    int32_t* track;        // indicator tracking (KM_OPT_TRACK): every update reads
+                           // each point's previous label here and writes its new
+                           // one (N int32, -1 before the first update); null: off
+    int64_t* C_hist;       // [hist_cap] labels changed per update (with track)
     // ---- progress (device-written; read back by the host) ----
     int32_t t;             // updates performed
     int32_t done;          // 1: no further update runs
@@ -61,6 +65,7 @@ struct alignas(16) State {
     double E;              // E of the last update
     double J;              // objective of the last reassignment-only pass
     int64_t empty_events;  // clusters left empty, summed over updates
+    int64_t changed;       // labels changed by the last update (with track)
     float minus_inf;       // -infinity, read at run time by the kernels
     int32_t pad1;
     // ---- device scratch ----
@@ -146,7 +151,8 @@ int batched_max_blocks_per_cu();
 // Launchers (lloyd_kernels.hip).  `vec`: X is 16-byte aligned with ld % 4 == 0.
 // `keys`: 0 = VALU scan, 1 / 2 = matrix-core scan with 1 / 2 tiles of 32 centres.
 hipError_t launch_scan(State* st, int d, bool vec, int grid, hipStream_t s);
-hipError_t launch_iter(State* st, int d, bool vec, int keys, int grid, hipStream_t s);
+hipError_t launch_iter(State* st, int d, bool vec, int keys, bool track, int grid,
+                       hipStream_t s);
 hipError_t launch_label(State* st, int32_t* labels, int d, bool vec, int keys, int grid,
                         hipStream_t s);
 // The whole fit as one cooperative launch (VALU scan); grid must fit on the

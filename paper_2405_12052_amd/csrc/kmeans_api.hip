@@ -54,9 +54,9 @@ int km::ensure_hist(kmeans_ctx* c, int cap) {
     while (n < cap) n *= 2;
     double* dv = nullptr;
     double* hv = nullptr;
-    if (hipMalloc(&dv, sizeof(double) * 2 * (size_t)n) != hipSuccess)
+    if (hipMalloc(&dv, sizeof(double) * 3 * (size_t)n) != hipSuccess)
         return fail(c, KM_ENOMEM, "hipMalloc of the history (%d entries) failed", n);
-    if (hipHostMalloc(&hv, sizeof(double) * 2 * (size_t)n, 0) != hipSuccess) {
+    if (hipHostMalloc(&hv, sizeof(double) * 3 * (size_t)n, 0) != hipSuccess) {
         (void)hipFree(dv);
         return fail(c, KM_ENOMEM, "hipHostMalloc of the history failed");
     }
@@ -173,6 +173,8 @@ void km::stage_state(State* h, const FitBufs& b, const float* X, int64_t N, int6
     h->gticket = b.gticket;
     h->E_hist = b.hist;
     h->J_hist = b.hist + b.hist_cap;
+    h->C_hist = b.chist;
+    h->track = nullptr;
     h->E = INFINITY;
     h->minus_inf = -INFINITY;
     for (int k = 0; k < K; ++k) {
@@ -196,13 +198,15 @@ int grid_for(kmeans_ctx* c, int64_t N) { return km::grid_blocks(c->n_cu, c->bloc
 
 void stage(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, int K,
            const double* mu, double tol, int max_iter) {
-    const km::FitBufs b{c->jpart, c->part, c->gpart, c->gjpart, c->gticket, c->hist, c->hist_cap};
+    const km::FitBufs b{c->jpart, c->part,  c->gpart, c->gjpart, c->gticket,
+                        c->hist,  reinterpret_cast<int64_t*>(c->hist + 2 * (size_t)c->hist_cap),
+                        c->hist_cap};
     km::stage_state(c->st_h, b, X, N, ld, d, K, mu, tol, max_iter);
 }
 
-int get_graph(kmeans_ctx* c, int d, bool vec, int keys, int grid, int unroll,
+int get_graph(kmeans_ctx* c, int d, bool vec, int keys, bool track, int grid, int unroll,
               hipGraphExec_t* out) {
-    km::GraphKey key{d, vec ? 1 : 0, keys, grid, unroll};
+    km::GraphKey key{d, vec ? 1 : 0, keys, track ? 1 : 0, grid, unroll};
     auto it = c->graphs.find(key);
     if (it != c->graphs.end()) {
         *out = it->second;
@@ -211,7 +215,7 @@ int get_graph(kmeans_ctx* c, int d, bool vec, int keys, int grid, int unroll,
     hipGraph_t g = nullptr;
     KM_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     for (int i = 0; i < unroll; ++i) {
-        hipError_t e = km::launch_iter(c->st, d, vec, keys, grid, c->cap_stream);
+        hipError_t e = km::launch_iter(c->st, d, vec, keys, track, grid, c->cap_stream);
         if (e != hipSuccess) {
             hipGraph_t junk = nullptr;
             (void)hipStreamEndCapture(c->cap_stream, &junk);
@@ -229,15 +233,15 @@ int get_graph(kmeans_ctx* c, int d, bool vec, int keys, int grid, int unroll,
     return KM_OK;
 }
 
-int run_iterations(kmeans_ctx* c, int d, bool vec, int keys, int grid, int n_iter) {
+int run_iterations(kmeans_ctx* c, int d, bool vec, int keys, bool track, int grid, int n_iter) {
     if (c->use_graph) {
         hipGraphExec_t ex;
-        int rc = get_graph(c, d, vec, keys, grid, n_iter, &ex);
+        int rc = get_graph(c, d, vec, keys, track, grid, n_iter, &ex);
         if (rc) return rc;
         KM_HIP(c, hipGraphLaunch(ex, c->stream));
     } else {
         for (int i = 0; i < n_iter; ++i)
-            KM_HIP(c, km::launch_iter(c->st, d, vec, keys, grid, c->stream));
+            KM_HIP(c, km::launch_iter(c->st, d, vec, keys, track, grid, c->stream));
     }
     return KM_OK;
 }
@@ -255,7 +259,7 @@ int run_iterations(kmeans_ctx* c, int d, bool vec, int keys, int grid, int n_ite
 // the persistent fit adds a grid-wide wait per update.
 bool use_persist(kmeans_ctx* c, int64_t N, int keys) {
     (void)N;
-    return keys == 0 && c->persist == 2;
+    return keys == 0 && c->persist == 2 && !c->track;
 }
 
 int scan_keys(kmeans_ctx* c, int K) {
@@ -403,6 +407,10 @@ int kmeans_set_option(kmeans_ctx* c, int32_t option, int64_t value) {
             if (value != 0 && value != 1) return fail(c, KM_EINVAL, "KM_OPT_WIDE takes 0 or 1");
             c->wide = (int)value;
             return KM_OK;
+        case KM_OPT_TRACK:
+            if (value != 0 && value != 1) return fail(c, KM_EINVAL, "KM_OPT_TRACK takes 0 or 1");
+            c->track = (int)value;
+            return KM_OK;
         default:
             return fail(c, KM_EINVAL, "unknown option %d", option);
     }
@@ -444,8 +452,11 @@ int kmeans_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int32_t d, 
     if (!rc && labels_out) rc = check_device_ptr(c, labels_out, "labels_out");
     if (!rc) rc = check_centres(c, init, K, d, "init");
     if (!rc && !centroids_out) rc = fail(c, KM_EINVAL, "centroids_out is NULL");
+    if (!rc && c->track && !labels_out)
+        rc = fail(c, KM_EINVAL, "KM_OPT_TRACK needs labels_out (the tracked labels live there)");
     if (rc) return rc;
     KM_HIP(c, hipSetDevice(c->device));
+    c->last_track = c->track;
     if (km::wide_shape(c, d, K))
         return km::wide_fit(c, X, N, ld, d, K, init, tol, max_iter, centroids_out, labels_out, res);
     rc = ensure_hist(c, max_iter);
@@ -454,7 +465,13 @@ int kmeans_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int32_t d, 
     const int grid = grid_for(c, N);
     const int U = c->unroll > 0 ? (c->unroll < max_iter ? c->unroll : max_iter) : km::auto_unroll(N, max_iter);
 
+    const bool track = c->track != 0;
     stage(c, X, N, ld, d, K, init, tol, max_iter);
+    if (track) {
+        // no label before the first update: every point counts as changed
+        c->st_h->track = labels_out;
+        KM_HIP(c, hipMemsetAsync(labels_out, 0xff, sizeof(int32_t) * (size_t)N, c->stream));
+    }
     KM_HIP(c, hipMemcpyAsync(c->st, c->st_h, km::kUploadBytes, hipMemcpyHostToDevice, c->stream));
     KM_HIP(c, km::launch_scan(c->st, d, vec, grid, c->stream));
 
@@ -498,12 +515,12 @@ int kmeans_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int32_t d, 
             if (rc) return rc;
             KM_HIP(c, hipEventRecord(c->ev[2 * batches], c->stream));
         }
-        rc = run_iterations(c, d, vec, keys, grid, n);
+        rc = run_iterations(c, d, vec, keys, track, grid, n);
         if (rc) return rc;
         if (c->timing) KM_HIP(c, hipEventRecord(c->ev[2 * batches + 1], c->stream));
         launched += n;
         batches += 1;
-        if (tol > 0.0 && launched < max_iter) {
+        if ((tol > 0.0 || track) && launched < max_iter) {
             KM_HIP(c, hipMemcpyAsync(reinterpret_cast<char*>(h) + km::kProgressOffset,
                                      reinterpret_cast<char*>(c->st) + km::kProgressOffset,
                                      km::kProgressBytes, hipMemcpyDeviceToHost, c->stream));
@@ -527,6 +544,10 @@ int kmeans_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int32_t d, 
             KM_HIP(c, hipMemcpyAsync(c->hist_h + c->hist_cap, c->hist + c->hist_cap,
                                      sizeof(double) * (size_t)nc, hipMemcpyDeviceToHost,
                                      c->stream));
+            if (track)
+                KM_HIP(c, hipMemcpyAsync(c->hist_h + 2 * c->hist_cap, c->hist + 2 * c->hist_cap,
+                                         sizeof(double) * (size_t)nc, hipMemcpyDeviceToHost,
+                                         c->stream));
         }
     }
     KM_HIP(c, hipStreamSynchronize(c->stream));
@@ -547,13 +568,22 @@ int kmeans_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int32_t d, 
     memcpy(centroids_out, h->mu64, sizeof(double) * (size_t)K * d);
     if (res) {
         res->iters = T;
-        res->converged = h->E < tol ? 1 : 0;
+        res->converged = (h->E < tol || (track && h->changed == 0)) ? 1 : 0;
         res->E = h->E;
         res->shift_l2 = sqrt(h->E);
         res->objective = h->J;
         res->empty_events = h->empty_events;
     }
     return KM_OK;
+}
+
+int kmeans_get_changes(kmeans_ctx* c, int64_t* changed, int32_t cap) {
+    if (!c || cap < 0) return KM_EINVAL;
+    if (!c->last_track) return fail(c, KM_EINVAL, "the last fit did not track its indicators");
+    int n = c->last_T < cap ? c->last_T : cap;
+    if (n > c->hist_cap) n = c->hist_cap;
+    if (changed) memcpy(changed, c->hist_h + 2 * c->hist_cap, sizeof(int64_t) * (size_t)n);
+    return n;
 }
 
 int kmeans_get_history(kmeans_ctx* c, double* E, double* J, int32_t cap) {

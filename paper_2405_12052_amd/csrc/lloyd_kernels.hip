@@ -316,6 +316,7 @@ struct IterSmem {
         } fin;
     } u;
     double sred[NW];
+    uint32_t schg[NW];  // labels changed per wave (indicator tracking)
     float4 sbnd;
     double sJ;
     int sflag;
@@ -358,7 +359,13 @@ __device__ __forceinline__ void wr4(float4* p, float4 v) {
 // denominators of its mean step), reduced across the grid.  Returns true in
 // the one final block, with the grid's integer sums | counts in sm.sacc
 // and the objective of this pass in sm.sJ.
-template <int D, bool VEC, int KT>
+// TRACK (indicator tracking): each point's label of the previous update is
+// read from st->track, the new one written there where it differs, and the
+// block's number of changed labels travels with the counts through the
+// reduction: it is added, times 2^32, to cluster 0's count (a block counts
+// at most 2^19 points and a fit at most 2^31 - 1, so the two fields never
+// overlap).
+template <int D, bool VEC, int KT, bool TRACK>
 __device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm, int K, int xe,
                             float4 bnd, float ninf) {
     constexpr int R = D + 1;  // per cluster: D sums, 1 count
@@ -378,8 +385,16 @@ __device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm
     const double fscale = fxp_scale(xe);
     unsigned long long* myacc = &sm.sacc[(tid % copies) * KR];
     unsigned int* mycnt = &sm.scnt[(tid % copies) * KS];
+    int32_t* __restrict__ track = st->track;
+    uint32_t nchg = 0;
     scan_points<D, VEC, KT>(X, ld, N, sm.scand, sm.smu, K, bnd, ninf, xe, sm.u.squeue[w],
-                            [&](int64_t, float x0, float x1, float x2, int k, float dist) {
+                            [&](int64_t i, float x0, float x1, float x2, int k, float dist) {
+        if constexpr (TRACK) {
+            if (track[i] != k) {
+                track[i] = k;
+                ++nchg;
+            }
+        }
         // coordinate-major slots [j * KS + k]: the 64 lanes' clusters spread
         // over the LDS banks (a cluster-major stride of 4 int64 would put
         // every cluster on one of a few bank groups)
@@ -393,7 +408,11 @@ __device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm
         jl += (double)dist;
     });
     jl = wave_sum(jl);
-    if ((tid & 63) == 0) sm.sred[w] = jl;
+    if constexpr (TRACK) nchg = wave_sum_u32(nchg);
+    if ((tid & 63) == 0) {
+        sm.sred[w] = jl;
+        sm.schg[w] = nchg;
+    }
     __syncthreads();
     // block totals, cluster-major [k * R + j]: the sums of q (each slot less
     // FXP_MAGIC_BITS per point it received) and the counts
@@ -405,6 +424,12 @@ __device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm
         if (j < D) {
             s = 0ull - n * FXP_MAGIC_BITS;
             for (int c = 0; c < copies; ++c) s += sm.sacc[c * KR + j * KS + k];
+        }
+        if (TRACK && i == D) {
+            unsigned long long c = 0ull;
+#pragma unroll
+            for (int v = 0; v < NW; ++v) c += sm.schg[v];
+            s += c << 32;
         }
         sm.u.stot[i] = s;
     }
@@ -422,14 +447,16 @@ __device__ __forceinline__ bool update_pass(State* __restrict__ st, IterSmem& sm
 // left in sm (smu, scand, sbnd, sdone) and stored to the state.  COH: the
 // state is also read by other blocks of a persistent kernel, so every access
 // to it is device-coherent.
-template <int D, bool COH>
+template <int D, bool COH, bool TRACK>
 __device__ __forceinline__ void finalize_update(State* __restrict__ st, IterSmem& sm, int K, int xe) {
     constexpr int R = D + 1;
     const int tid = threadIdx.x;
     const i128* tot = reinterpret_cast<const i128*>(sm.sacc);
     if (tid < K) {
         const int k = tid;
-        const unsigned long long cnt = tot[k * R + D].lo;
+        // the count's low 32 bits (cluster 0's carries the changed labels
+        // above them, see update_pass)
+        const unsigned long long cnt = tot[k * R + D].lo & 0xffffffffull;
         double e = 0.0;
         float m32[DMAX] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -457,7 +484,14 @@ __device__ __forceinline__ void finalize_update(State* __restrict__ st, IterSmem
         for (int k = 0; k < K; ++k) { E += sm.u.fin.sE[k]; emp += sm.u.fin.sEmpty[k]; }
         const int t = rd<COH>(&st->t);
         if (t < st->hist_cap) { st->E_hist[t] = E; st->J_hist[t] = sm.sJ; }
-        const int done = (E < st->tol || t + 1 >= st->max_iter) ? 1 : 0;
+        int done = (E < st->tol || t + 1 >= st->max_iter) ? 1 : 0;
+        if constexpr (TRACK) {
+            // the paper's other criterion: no indicator changed
+            const long long chg = (long long)(tot[D].lo >> 32);
+            if (t < st->hist_cap) st->C_hist[t] = chg;
+            st->changed = chg;
+            if (chg == 0) done = 1;
+        }
         wr<COH>(&st->t, t + 1);
         wr<COH>(&st->E, E);
         wr<COH>(&st->empty_events, rd<COH>(&st->empty_events) + emp);
@@ -469,15 +503,28 @@ __device__ __forceinline__ void finalize_update(State* __restrict__ st, IterSmem
 
 // One update per launch (replayed from a graph): the update's pass, then the
 // final block's update of the centres.
+template <int D, bool VEC, int KT, bool TRACK>
+__device__ __forceinline__ void iter_body(State* __restrict__ st, IterSmem& sm) {
+    const int K = st->K;
+    stage_centres(st, K, sm.scand, sm.smu);
+    __syncthreads();
+    if (!update_pass<D, VEC, KT, TRACK>(st, sm, K, st->xe, st->bnd, st->minus_inf)) return;
+    finalize_update<D, false, TRACK>(st, sm, K, st->xe);
+}
+
 template <int D, bool VEC, int KT>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) void lloyd_iter(State* __restrict__ st) {
     if (st->done) return;
     __shared__ IterSmem sm;
-    const int K = st->K;
-    stage_centres(st, K, sm.scand, sm.smu);
-    __syncthreads();
-    if (!update_pass<D, VEC, KT>(st, sm, K, st->xe, st->bnd, st->minus_inf)) return;
-    finalize_update<D, false>(st, sm, K, st->xe);
+    iter_body<D, VEC, KT, false>(st, sm);
+}
+
+// The same with indicator tracking (KM_OPT_TRACK).
+template <int D, bool VEC, int KT>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) void lloyd_iter_track(State* __restrict__ st) {
+    if (st->done) return;
+    __shared__ IterSmem sm;
+    iter_body<D, VEC, KT, true>(st, sm);
 }
 
 // The whole fit in one cooperative launch (every block resident), for small
@@ -502,8 +549,8 @@ __global__ __launch_bounds__(BLOCK) void lloyd_persist(State* __restrict__ st) {
     float4 bnd = st->bnd;
     __syncthreads();
     for (uint32_t round = 1;; ++round) {
-        if (update_pass<D, VEC, KT>(st, sm, K, xe, bnd, ninf)) {
-            finalize_update<D, true>(st, sm, K, xe);
+        if (update_pass<D, VEC, KT, false>(st, sm, K, xe, bnd, ninf)) {
+            finalize_update<D, true, false>(st, sm, K, xe);
             wait_mem();
             __syncthreads();
             if (tid == 0) st_agent(&st->gen, round);
@@ -624,9 +671,11 @@ hipError_t launch_scan(State* st, int d, bool vec, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_iter(State* st, int d, bool vec, int keys, int grid, hipStream_t s) {
+hipError_t launch_iter(State* st, int d, bool vec, int keys, bool track, int grid,
+                       hipStream_t s) {
     if (grid < 1 || grid > MAX_BLOCKS) return hipErrorInvalidValue;
-    KM_DISPATCH_SCAN(lloyd_iter, grid, s, st);
+    if (track) KM_DISPATCH_SCAN(lloyd_iter_track, grid, s, st);
+    else KM_DISPATCH_SCAN(lloyd_iter, grid, s, st);
     return hipGetLastError();
 }
 

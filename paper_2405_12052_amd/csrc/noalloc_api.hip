@@ -144,7 +144,7 @@ extern "C" int kmeans_fit_noalloc(int device, void* hip_stream, const float* X, 
                     reinterpret_cast<unsigned long long*>(base + NA_GPART),
                     reinterpret_cast<double*>(base + NA_GJPART),
                     reinterpret_cast<uint32_t*>(base + NA_GTICKET),
-                    reinterpret_cast<double*>(base + NA_HIST_OFF), NA_HIST};
+                    reinterpret_cast<double*>(base + NA_HIST_OFF), nullptr, NA_HIST};
     const bool vec = vec_ok(X, ld);
     const int grid = grid_blocks(s->n_cu, 0, N);
     const int U = auto_unroll(N, max_iter);
@@ -163,7 +163,7 @@ extern "C" int kmeans_fit_noalloc(int device, void* hip_stream, const float* X, 
     int launched = 0;
     while (launched < max_iter) {
         const int n = (max_iter - launched) < U ? (max_iter - launched) : U;
-        for (int i = 0; i < n; ++i) NA_HIP(launch_iter(st, d, vec, keys, grid, stream));
+        for (int i = 0; i < n; ++i) NA_HIP(launch_iter(st, d, vec, keys, false, grid, stream));
         launched += n;
         if (tol > 0.0 && launched < max_iter) {
             NA_HIP(hipMemcpyAsync(reinterpret_cast<char*>(&h) + kProgressOffset,

@@ -77,6 +77,9 @@ struct alignas(16) WState {
     double* jpart;         // [grid] per-block objective partials
     double* E_hist;        // [hist_cap]
     double* J_hist;        // [hist_cap]
+    int32_t* track;        // indicator tracking: previous labels (N int32, -1 before
+                           // the first update), rewritten by every update; null: off
+    int64_t* C_hist;       // [hist_cap] labels changed per update (with track)
     // ---- progress (device-written; read back by the host) ----
     int32_t t;             // updates performed
     int32_t done;          // 1: no further update runs
@@ -85,6 +88,7 @@ struct alignas(16) WState {
     double E;              // E of the last update
     double J;              // objective of the last reassignment pass
     int64_t empty_events;  // clusters left empty, summed over updates
+    int64_t changed;       // labels changed by the last update (with track)
     float plus_inf;        // +infinity, read at run time by the kernels
     int32_t pad1;
     // ---- device scratch ----
@@ -100,7 +104,7 @@ constexpr size_t kWProgressBytes = offsetof(WState, absmax_bits) - offsetof(WSta
 // Launchers (wide_kernels.hip); each returns hipErrorInvalidValue for a
 // shape or grid outside the limits above.
 hipError_t launch_wide_scan(WState* st, int grid, hipStream_t s);
-hipError_t launch_wide_update(WState* st, int d, int K, int grid, hipStream_t s);
+hipError_t launch_wide_update(WState* st, int d, int K, bool track, int grid, hipStream_t s);
 hipError_t launch_wide_reduce(WState* st, int d, int K, int grid_update, hipStream_t s);
 hipError_t launch_wide_label(WState* st, int32_t* labels, int d, int K, int grid,
                              hipStream_t s);

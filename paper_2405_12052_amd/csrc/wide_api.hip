@@ -28,7 +28,7 @@ struct WideWS {
     float* hh = nullptr;       // key constants, WK_MAX + 4 floats
     float* amax = nullptr;     // bound coefficients, WD_MAX + 1 floats
     size_t part_cap = 0;       // int64 slots of part
-    std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;  // (d, K, grid, unroll)
+    std::map<std::tuple<int, int, int, int, int>, hipGraphExec_t> graphs;  // (d, K, track, grid, unroll)
     std::map<std::pair<int, size_t>, int> bpc;  // (width, LDS bytes) -> blocks per CU
 };
 
@@ -119,9 +119,10 @@ int scan_grid(kmeans_ctx* c, int64_t N) {
 }
 
 // Host staging of the state and centres, then the upload (one copy of the
-// state, one of the centres) on the context's stream.
+// state, one of the centres) on the context's stream.  track: the labels of
+// indicator tracking, or null.
 int stage_upload(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, int K,
-                 const double* mu, double tol, int max_iter, int grid) {
+                 const double* mu, double tol, int max_iter, int grid, int32_t* track) {
     WideWS* w = c->wws;
     const int DS = wide_stride(wide_width(d));
     const int nacc = K * (d + 1);
@@ -151,6 +152,8 @@ int stage_upload(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, in
     h->plus_inf = INFINITY;
     h->E_hist = c->hist;
     h->J_hist = c->hist + c->hist_cap;
+    h->C_hist = reinterpret_cast<int64_t*>(c->hist + 2 * (size_t)c->hist_cap);
+    h->track = track;
     h->E = INFINITY;
     double* m64 = w->mu_h;
     float* m32 = reinterpret_cast<float*>(w->mu_h + (size_t)K * d);
@@ -169,16 +172,17 @@ int stage_upload(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, in
     return KM_OK;
 }
 
-int launch_one_update(kmeans_ctx* c, int d, int K, int grid, hipStream_t s) {
-    hipError_t e = launch_wide_update(c->wws->st, d, K, grid, s);
+int launch_one_update(kmeans_ctx* c, int d, int K, bool track, int grid, hipStream_t s) {
+    hipError_t e = launch_wide_update(c->wws->st, d, K, track, grid, s);
     if (e == hipSuccess) e = launch_wide_reduce(c->wws->st, d, K, grid, s);
     if (e != hipSuccess) return fail(c, KM_EHIP, "launch of a general-shape update failed: %s", hipGetErrorString(e));
     return KM_OK;
 }
 
-int get_graph(kmeans_ctx* c, int d, int K, int grid, int unroll, hipGraphExec_t* out) {
+int get_graph(kmeans_ctx* c, int d, int K, bool track, int grid, int unroll,
+              hipGraphExec_t* out) {
     WideWS* w = c->wws;
-    const auto key = std::make_tuple(d, K, grid, unroll);
+    const auto key = std::make_tuple(d, K, track ? 1 : 0, grid, unroll);
     auto it = w->graphs.find(key);
     if (it != w->graphs.end()) {
         *out = it->second;
@@ -186,7 +190,7 @@ int get_graph(kmeans_ctx* c, int d, int K, int grid, int unroll, hipGraphExec_t*
     }
     KM_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     for (int i = 0; i < unroll; ++i) {
-        hipError_t e = launch_wide_update(w->st, d, K, grid, c->cap_stream);
+        hipError_t e = launch_wide_update(w->st, d, K, track, grid, c->cap_stream);
         if (e == hipSuccess) e = launch_wide_reduce(w->st, d, K, grid, c->cap_stream);
         if (e != hipSuccess) {
             hipGraph_t junk = nullptr;
@@ -225,8 +229,12 @@ int wide_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, int K,
     if (rc) return rc;
     WideWS* w = c->wws;
     const int grid = update_grid(c, d, K, N);
-    rc = stage_upload(c, X, N, ld, d, K, init, tol, max_iter, grid);
+    const bool track = c->track != 0;
+    rc = stage_upload(c, X, N, ld, d, K, init, tol, max_iter, grid, track ? labels_out : nullptr);
     if (rc) return rc;
+    // no label before the first update: every point counts as changed
+    if (track)
+        KM_HIP(c, hipMemsetAsync(labels_out, 0xff, sizeof(int32_t) * (size_t)N, c->stream));
     KM_HIP(c, launch_wide_scan(w->st, scan_grid(c, N), c->stream));
 
     int U = c->unroll > 0 ? c->unroll : (N >= (1 << 24) ? 10 : (N >= (1 << 20) ? 16 : 32));
@@ -243,17 +251,17 @@ int wide_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, int K,
         }
         if (c->use_graph) {
             hipGraphExec_t ex;
-            rc = get_graph(c, d, K, grid, n, &ex);
+            rc = get_graph(c, d, K, track, grid, n, &ex);
             if (rc) return rc;
             KM_HIP(c, hipGraphLaunch(ex, c->stream));
         } else {
-            for (int i = 0; i < n && !rc; ++i) rc = launch_one_update(c, d, K, grid, c->stream);
+            for (int i = 0; i < n && !rc; ++i) rc = launch_one_update(c, d, K, track, grid, c->stream);
             if (rc) return rc;
         }
         if (c->timing) KM_HIP(c, hipEventRecord(c->ev[2 * batches + 1], c->stream));
         launched += n;
         batches += 1;
-        if (tol > 0.0 && launched < max_iter) {
+        if ((tol > 0.0 || track) && launched < max_iter) {
             rc = read_progress(c, kWProgressBytes);
             if (rc) return rc;
             if (w->st_h->done) break;
@@ -273,6 +281,10 @@ int wide_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, int K,
             KM_HIP(c, hipMemcpyAsync(c->hist_h + c->hist_cap, c->hist + c->hist_cap,
                                      sizeof(double) * (size_t)nc, hipMemcpyDeviceToHost,
                                      c->stream));
+            if (track)
+                KM_HIP(c, hipMemcpyAsync(c->hist_h + 2 * c->hist_cap, c->hist + 2 * c->hist_cap,
+                                         sizeof(double) * (size_t)nc, hipMemcpyDeviceToHost,
+                                         c->stream));
         }
     }
     rc = read_progress(c, kWProgressBytes);
@@ -293,7 +305,7 @@ int wide_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, int K,
     memcpy(centroids_out, m64, sizeof(double) * (size_t)K * d);
     if (res) {
         res->iters = T;
-        res->converged = h->E < tol ? 1 : 0;
+        res->converged = (h->E < tol || (track && h->changed == 0)) ? 1 : 0;
         res->E = h->E;
         res->shift_l2 = sqrt(h->E);
         res->objective = h->J;
@@ -308,7 +320,7 @@ int wide_assign(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, int
     if (rc) return rc;
     WideWS* w = c->wws;
     const int grid = update_grid(c, d, K, N);
-    rc = stage_upload(c, X, N, ld, d, K, centroids, 0.0, 1, grid);
+    rc = stage_upload(c, X, N, ld, d, K, centroids, 0.0, 1, grid, nullptr);
     if (rc) return rc;
     KM_HIP(c, launch_wide_scan(w->st, scan_grid(c, N), c->stream));
     KM_HIP(c, launch_wide_label(w->st, labels, d, K, grid, c->stream));

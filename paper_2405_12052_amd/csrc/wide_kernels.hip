@@ -414,11 +414,14 @@ __global__ __launch_bounds__(WBLOCK) void wide_scan(WState* __restrict__ st) {
     }
 }
 
-// Reassignment and per-block sums of one update.
-template <int D>
-__global__ __launch_bounds__(WBLOCK) void wide_update(WState* __restrict__ st) {
-    extern __shared__ __align__(16) unsigned char wsm[];
-    if (st->done) return;
+// Reassignment and per-block sums of one update.  TRACK (indicator
+// tracking): each point's previous label is read from st->track and the new
+// one written there where it differs; the block's number of changed labels
+// is added, times 2^32, to cluster 0's count in its partial row (a block
+// counts at most 2^19 points and a fit at most 2^31 - 1, so the fields never
+// overlap).
+template <int D, bool TRACK>
+__device__ __forceinline__ void wide_update_body(WState* __restrict__ st, unsigned char* wsm) {
     using S = WShape<D>;
     const int tid = threadIdx.x;
     const int d = st->d, K = st->K, nacc = K * (d + 1);
@@ -434,9 +437,17 @@ __global__ __launch_bounds__(WBLOCK) void wide_update(WState* __restrict__ st) {
     for (int i = tid; i < nacc; i += WBLOCK) acc[i] = 0ull;
     __syncthreads();
     double jl = 0.0;
+    int32_t* __restrict__ track = st->track;
+    uint32_t nchg = 0;
     wide_points<D>(st, cm, hh, amax, K, d, wq,
-                   [&](const float (&xr)[D], int64_t, int k, float dist) {
+                   [&](const float (&xr)[D], int64_t i, int k, float dist) {
         jl += (double)dist;
+        if constexpr (TRACK) {
+            if (track[i] != k) {
+                track[i] = k;
+                ++nchg;
+            }
+        }
         // coordinate-major slots [j * K + k]: the lanes' clusters spread over
         // the LDS banks
         unsigned long long* a = acc + k;
@@ -448,15 +459,43 @@ __global__ __launch_bounds__(WBLOCK) void wide_update(WState* __restrict__ st) {
         }
         __hip_atomic_fetch_add(&a[d * K], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     });
+    unsigned long long chg = 0ull;
+    if constexpr (TRACK) {
+        nchg = wave_sum_u32(nchg);
+        // per-wave counts in the first word of each wave's re-scan queue
+        // (empty once the pass is over)
+        int* q0 = reinterpret_cast<int*>(amax + 36);
+        if ((tid & 63) == 0) q0[(tid >> 6) * WQCAP] = (int)nchg;
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < NW; ++v) chg += (uint32_t)q0[v * WQCAP];
+    }
     const double jb = block_sum(jl, sw);  // also orders the LDS atomics before the copy-out
     // the row: the sums of q (each slot less FXP_MAGIC_BITS per point it
     // received, the count of its cluster) and the counts
     unsigned long long* row = st->part + (size_t)blockIdx.x * nacc;
     for (int i = tid; i < nacc; i += WBLOCK) {
         const int k = i % K;
-        row[i] = i < d * K ? acc[i] - acc[d * K + k] * FXP_MAGIC_BITS : acc[i];
+        unsigned long long v = i < d * K ? acc[i] - acc[d * K + k] * FXP_MAGIC_BITS : acc[i];
+        if (TRACK && i == d * K) v += chg << 32;
+        row[i] = v;
     }
     if (tid == 0) st->jpart[blockIdx.x] = jb;
+}
+
+template <int D>
+__global__ __launch_bounds__(WBLOCK) void wide_update(WState* __restrict__ st) {
+    extern __shared__ __align__(16) unsigned char wsm[];
+    if (st->done) return;
+    wide_update_body<D, false>(st, wsm);
+}
+
+// The same with indicator tracking (KM_OPT_TRACK).
+template <int D>
+__global__ __launch_bounds__(WBLOCK) void wide_update_track(WState* __restrict__ st) {
+    extern __shared__ __align__(16) unsigned char wsm[];
+    if (st->done) return;
+    wide_update_body<D, true>(st, wsm);
 }
 
 // Totals of the partial rows, then (last block) the float64 mean step.
@@ -519,8 +558,13 @@ __global__ __launch_bounds__(WBLOCK) void wide_reduce(WState* __restrict__ st) {
     const int xe = data_exponent(st->absmax_bits);
     const int DS = wide_stride(wide_width(d));
     int emp = 0;
+    long long chg = 0;
     for (int k = tid; k < K; k += WBLOCK) {
-        const unsigned long long cnt = total(d * K + k).lo;   // slots [j * K + k]
+        // slots [j * K + k]; the count in the low 32 bits (cluster 0's
+        // carries the changed labels above them, see wide_update_body)
+        const unsigned long long ct = total(d * K + k).lo;
+        const unsigned long long cnt = ct & 0xffffffffull;
+        if (k == 0) chg = (long long)(ct >> 32);
         double e = 0.0;
         for (int j = 0; j < d; ++j) {
             const i128 sj = total(j * K + k);
@@ -550,7 +594,14 @@ __global__ __launch_bounds__(WBLOCK) void wide_reduce(WState* __restrict__ st) {
         st->t = t + 1;
         st->E = E;
         st->empty_events += sempty;
-        st->done = (E < st->tol || t + 1 >= st->max_iter) ? 1 : 0;
+        int done = (E < st->tol || t + 1 >= st->max_iter) ? 1 : 0;
+        if (st->track) {
+            // the paper's other criterion: no indicator changed
+            if (t < st->hist_cap) st->C_hist[t] = chg;
+            st->changed = chg;
+            if (chg == 0) done = 1;
+        }
+        st->done = done;
         st_agent(&st->ticket, 0u);
     }
 }
@@ -620,12 +671,16 @@ hipError_t launch_wide_scan(WState* st, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_wide_update(WState* st, int d, int K, int grid, hipStream_t s) {
+hipError_t launch_wide_update(WState* st, int d, int K, bool track, int grid, hipStream_t s) {
     const size_t lds = wide_lds_bytes(d, K);
     if (grid < 1 || grid > WMAX_GRID || d < 1 || d > WD_MAX || K < 1 || K > WK_MAX ||
         lds > (size_t)WLDS_MAX)
         return hipErrorInvalidValue;
-    KM_WIDE_DISPATCH(wide_update, d, grid, lds, s, st)
+    if (track) {
+        KM_WIDE_DISPATCH(wide_update_track, d, grid, lds, s, st)
+    } else {
+        KM_WIDE_DISPATCH(wide_update, d, grid, lds, s, st)
+    }
     return hipGetLastError();
 }
 

@@ -368,3 +368,65 @@ def test_smallest_positive_tol_is_the_indicator_stability_rule():
     assert np.array_equal(prev["labels"], f["labels"])
     nxt = oracle.step(X, f["mu"])
     assert nxt["E"] == 0.0 and np.array_equal(nxt["labels"], f["labels"])
+
+
+def test_fit_track_worked_example():
+    # hand-counted indicator changes of the worked example: all 4 points at
+    # the first update (no labels before it), then the point (2, 0), then none
+    g = json.load(open(os.path.join(GOLD, "worked_example_k2.json")))
+    X = soa(g["points_xy"])
+    f = oracle.fit_track(X, np.array(g["init"], np.float64), tol=0.0, max_iter=50)
+    assert f["changed"].tolist() == [s["changed"] for s in g["steps"]]
+    assert f["T"] == g["T"] and f["converged"]
+    assert np.array_equal(f["mu"], np.array(g["steps"][-1]["mu_next"], np.float64))
+    assert f["labels"].tolist() == g["steps"][-1]["labels"]
+    # max_iter reached first: not converged
+    f1 = oracle.fit_track(X, np.array(g["init"], np.float64), tol=0.0, max_iter=2)
+    assert f1["T"] == 2 and not f1["converged"] and f1["changed"].tolist() == [4, 1]
+
+
+def _brute_labels(P, mu):
+    # first-index argmin of the float64 squared distance (distinct points,
+    # generic centres: no ties)
+    return [min(range(len(mu)), key=lambda k: sum((p[j] - mu[k][j]) ** 2 for j in range(len(p))))
+            for p in P]
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_fit_track_counts_against_brute_force(seed):
+    # the changed counts of each update equal those of a brute-force Lloyd
+    # loop (Python floats, math.fsum means) over the same tiny data
+    rng = np.random.default_rng(seed)
+    N, d, K = 40, 2, 4
+    P = rng.normal(size=(N, d)).astype(np.float32).astype(np.float64)
+    mu = [list(P[i]) for i in rng.choice(N, K, replace=False)]
+    f = oracle.fit_track(P.T.astype(np.float32), np.array(mu), tol=0.0, max_iter=100,
+                         assign_f32=False)
+    prev, counts = None, []
+    for _ in range(100):
+        lab = _brute_labels(P.tolist(), mu)
+        counts.append(N if prev is None else sum(a != b for a, b in zip(lab, prev)))
+        for k in range(K):
+            mem = [P[i] for i in range(N) if lab[i] == k]
+            if mem:
+                mu[k] = [math.fsum(p[j] for p in mem) / len(mem) for j in range(d)]
+        prev = lab
+        if counts[-1] == 0:
+            break
+    assert f["changed"].tolist() == counts
+    assert f["labels"].tolist() == prev
+    assert np.allclose(f["mu"], np.array(mu), rtol=0, atol=1e-12)
+
+
+def test_fit_track_stops_with_the_e_zero_rule():
+    # on data without repeated points the first update that changes no label
+    # is the first with E == 0: the same T, centres and labels as tol = 5e-324
+    s = datagen.spec("C1", N=20_000, seed=78)
+    X, _ = datagen.generate(s)
+    mu0 = datagen.init_sample(X, s.N, s.K, 4)
+    f = oracle.fit_track(X, mu0, tol=0.0, max_iter=1000)
+    g = oracle.fit(X, mu0, tol=5e-324, max_iter=1000)
+    assert f["converged"] and f["T"] == g["T"]
+    assert f["changed"][0] == s.N and f["changed"][-1] == 0 and np.all(f["changed"][:-1] > 0)
+    assert np.array_equal(f["E_hist"], g["E_hist"])
+    assert np.array_equal(f["mu"], g["mu"]) and np.array_equal(f["labels"], g["labels"])
