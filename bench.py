@@ -177,7 +177,8 @@ def bench_wide(args):
     import datagen
     from paper_2405_12052_amd import KM_OPT_TIMING, KMeans
 
-    s = datagen.spec("W1") if args.N is None else datagen.spec("W1", N=args.N)
+    over = {k: v for k, v in (("N", args.N), ("K", args.K)) if v is not None}
+    s = datagen.spec("W1", **over)
     iters = s.max_iter
     t0 = time.time()
     X, _ = datagen.generate(s)
@@ -210,7 +211,8 @@ def bench_wide(args):
     fma_peak = 2.0 * peaks["fma_lane_ops_per_s"] / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-            "kernel": f"wide_update<{s.d}> + wide_reduce (one update)",
+            "kernel": f"wide_update{'_tiled' if wide_tiled(s.d, s.K) else ''}<{s.d}> + "
+                      f"wide_reduce (one update)",
             "avg_update_us": per_update_s * 1e6, "alg_flops_per_update": flops,
             "alg_bytes_per_update": alg_bytes_per_point(s.d) * s.N,
             "frac_of_measured_nonpacked_fma_peak": achieved / fma_peak}
@@ -235,6 +237,16 @@ def bench_wide(args):
     }
     print(json.dumps(out), flush=True)
     km.close()
+
+
+def wide_tiled(d, K):
+    """Whether (d, K) exceeds one block's LDS and takes the tiled general-shape
+    kernels (the shape rule stated in include/kmeans.h)."""
+    w = d if d <= 4 else next(v for v in (6, 8, 12, 16, 24, 32) if d <= v)
+    s = (w + 3) & ~3
+    kp = 3 * ((K + 2) // 3)
+    r16 = lambda n: (n + 15) & ~15
+    return r16(8 * K * (d + 1)) + 4 * kp * s + r16(4 * kp) + 2224 > 65536
 
 
 def _c5_instance(seed):

@@ -47,17 +47,18 @@
  *     Results do not depend on the launch configuration and repeat bit for
  *     bit from run to run.
  *   - An empty cluster keeps its previous centre and is counted.
- *   - Supported shapes: 1 <= d <= 32, 1 <= K <= 1024, K <= N <= 2^31 - 1,
- *     where, outside d in {2, 3} with K <= 64, one block's tables must fit
- *     in 64 KB of LDS: 8*K*(d+1) + 4*Kp*s + 4*Kp (the first and last rounded
- *     up to 16) + 2224 <= 65536 bytes, Kp = K rounded up to a multiple of 3,
- *     s = the padded width (d for d <= 4; then 6, 8, 12, 16, 24 or 32)
- *     rounded up to a multiple of 4.  (d <= 4: K <= 1024; d = 8: K <= 585;
- *     d = 16: K <= 309; d = 32: K <= 159.)  d in {2, 3} with K <= 64 runs
- *     the 2-D/3-D kernels, every other shape the general-shape kernels
- *     (same definitions, same results up to the objective's summation
- *     order).  kmeans_fit_batched: d in {2, 3}, K <= 32, N <= 2^27, up to 8
- *     restarts.
+ *   - Supported shapes: 1 <= d <= 32, 1 <= K <= 4096, K <= N <= 2^31 - 1.
+ *     d in {2, 3} with K <= 64 runs the 2-D/3-D kernels, every other shape
+ *     the general-shape kernels (same definitions, same results up to the
+ *     objective's summation order).  Those keep one block's sums and centre
+ *     tables in LDS when 8*K*(d+1) + 4*Kp*s + 4*Kp (the first and last
+ *     rounded up to 16) + 2224 <= 65536 bytes, Kp = K rounded up to a
+ *     multiple of 3, s = the padded width (d for d <= 4; then 6, 8, 12, 16,
+ *     24 or 32) rounded up to a multiple of 4 (d <= 4: K <= 1024; d = 8:
+ *     K <= 585; d = 16: K <= 309; d = 32: K <= 159); larger K takes their
+ *     tiled form (centres staged through LDS in tiles, sums in device
+ *     memory), with the same results.  kmeans_fit_batched: d in {2, 3},
+ *     K <= 32, N <= 2^27, up to 8 restarts.
  *   - Every call is synchronous with respect to the host: it returns after
  *     its device work on the context's stream has completed.  There is no
  *     host synchronisation between iterations of a fit.

@@ -98,11 +98,6 @@ int km::validate(kmeans_ctx* c, int64_t N, int64_t ld, int32_t d, int32_t K, dou
     if (d > km::WD_MAX) return fail(c, KM_EUNSUPPORTED, "d=%d > %d", d, km::WD_MAX);
     if (K < 1) return fail(c, KM_EINVAL, "K=%d < 1", K);
     if (K > km::WK_MAX) return fail(c, KM_EUNSUPPORTED, "K=%d > %d", K, km::WK_MAX);
-    // shapes outside the 2-D/3-D, K <= 64 kernels: the general-shape kernels
-    // keep K*(d+1) int64 sums and K float32 centres of one block in LDS
-    if (km::wide_lds_bytes(d, K) > (size_t)km::WLDS_MAX && !((d == 2 || d == 3) && K <= km::KMAX))
-        return fail(c, KM_EUNSUPPORTED, "d=%d, K=%d: K*(d+1) sums and K centres exceed one block's LDS",
-                    d, K);
     if (K > N) return fail(c, KM_EINVAL, "K=%d > N=%lld", K, (long long)N);
     if (!(tol >= 0.0) || !isfinite(tol)) return fail(c, KM_EINVAL, "tol must be finite and >= 0");
     if (max_iter < 1) return fail(c, KM_EINVAL, "max_iter=%d < 1", max_iter);

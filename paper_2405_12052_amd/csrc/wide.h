@@ -21,7 +21,7 @@
 namespace km {
 
 constexpr int WD_MAX = 32;        // largest d
-constexpr int WK_MAX = 1024;      // largest K
+constexpr int WK_MAX = 4096;      // largest K
 constexpr int WBLOCK = 256;       // threads per block of the wide kernels
 constexpr int WMAX_GRID = 4096;   // cap of the update grid (rows of partials)
 constexpr int WCHUNK = 32;        // partials summed per thread in wide_reduce
@@ -55,6 +55,24 @@ __host__ __device__ constexpr size_t wide_lds_bytes(int d, int K) {
     return (((size_t)K * (d + 1) * 8 + 15) & ~(size_t)15) + wide_table_bytes(d, K);
 }
 
+// Shapes whose sums and tables exceed WLDS_MAX take the tiled kernels: the
+// centres pass through LDS in tiles of wide_tile_k(stride) rows (whole
+// chunks of 32 triples, about 24 KB), the sums go to the block's row of
+// partials in device memory.
+__host__ __device__ constexpr int wide_tile_k(int DS) {
+    return 96 * ((6144 / (96 * DS)) > 0 ? (6144 / (96 * DS)) : 1);
+}
+__host__ __device__ constexpr bool wide_tiled(int d, int K) {
+    return wide_lds_bytes(d, K) > (size_t)WLDS_MAX;
+}
+// LDS of a tiled block: one tile of float32 centres and constants, the bound
+// coefficients (36 floats), the per-wave re-scan queues and objective sums.
+__host__ __device__ constexpr size_t wide_tiled_lds_bytes(int d) {
+    return (size_t)wide_tile_k(wide_stride(wide_width(d))) * wide_stride(wide_width(d)) * 4 +
+           (((size_t)wide_tile_k(wide_stride(wide_width(d))) * 4 + 15) & ~(size_t)15) + 36 * 4 +
+           (size_t)(WBLOCK / 64) * WQCAP * 4 + (WBLOCK / 64) * 8;
+}
+
 struct alignas(16) WState {
     // ---- problem (host-written) ----
     const float* X;        // d rows of N float32, row j at X + j*ld
@@ -68,10 +86,12 @@ struct alignas(16) WState {
     int32_t grid;          // blocks of wide_update (rows of part)
     int32_t vec;           // rows 16-byte aligned and ld % 4 == 0
     double* mu64;          // [K * d] float64 centres, row-major
-    float* mu32;           // [K * stride] the same rounded to float32, zero padded
+    float* mu32;           // [Kpad * stride] the same rounded to float32, zero padded
+                           // (coordinates past d, rows past K up to a whole triple)
     float* hh;             // [Kpad] -|m_k|^2 / 2 of the float32 centres (pads: -2^127)
     float* amax;           // [WD_MAX + 1] max_k |m_kj| for j < d; [WD_MAX]: max_k |m_k|^2
-    unsigned long long* part;  // [grid][K * (d + 1)] per-block sums | counts (int64)
+    unsigned long long* part;  // [grid][K * (d + 1)] per-block sums | counts (int64;
+                               // the tiled kernels add into it directly)
     unsigned long long* tot;   // [2][K * (d + 1)] totals as two limbs, value =
                                // tot[1][i] 2^32 + tot[0][i] (zero between updates)
     double* jpart;         // [grid] per-block objective partials
@@ -108,7 +128,8 @@ hipError_t launch_wide_update(WState* st, int d, int K, bool track, int grid, hi
 hipError_t launch_wide_reduce(WState* st, int d, int K, int grid_update, hipStream_t s);
 hipError_t launch_wide_label(WState* st, int32_t* labels, int d, int K, int grid,
                              hipStream_t s);
-// Resident wide_update blocks per compute unit for (d, K); 0 on error.
-int wide_blocks_per_cu(int d, size_t lds);
+// Resident update blocks per compute unit for (d, K) (the tiled kernel when
+// wide_tiled(d, K)); 0 on error.
+int wide_blocks_per_cu(int d, int K);
 
 }  // namespace km

@@ -29,7 +29,7 @@ struct WideWS {
     float* amax = nullptr;     // bound coefficients, WD_MAX + 1 floats
     size_t part_cap = 0;       // int64 slots of part
     std::map<std::tuple<int, int, int, int, int>, hipGraphExec_t> graphs;  // (d, K, track, grid, unroll)
-    std::map<std::pair<int, size_t>, int> bpc;  // (width, LDS bytes) -> blocks per CU
+    std::map<std::pair<int, int>, int> bpc;  // (d, K) -> blocks per CU
 };
 
 void wide_ws_free(WideWS* w) {
@@ -51,7 +51,8 @@ void wide_ws_free(WideWS* w) {
 namespace {
 
 constexpr size_t kMu64Max = (size_t)WK_MAX * WD_MAX;  // float64 centres
-constexpr size_t kMu32Max = (size_t)WK_MAX * WD_MAX;  // float32 centres (stride <= WD_MAX)
+constexpr size_t kMu32Max = (size_t)(WK_MAX + 2) * WD_MAX;  // float32 centres (stride <=
+                                                            // WD_MAX, whole triples)
 constexpr size_t kTotMax = (size_t)WK_MAX * (WD_MAX + 1);
 
 int ensure_ws(kmeans_ctx* c) {
@@ -97,9 +98,16 @@ int points_per_lane(int d) { return wide_width(d) <= 16 ? 4 : 2; }
 // ceil(groups / (grid WBLOCK)) groups of P points per thread, at most
 // FXP_BLOCK_POINTS / (WBLOCK P) of them (N < 2^31 needs at most 4096 blocks).
 int update_grid(kmeans_ctx* c, int d, int K, int64_t N) {
-    const size_t lds = wide_lds_bytes(d, K);
-    int& b = c->wws->bpc[{wide_width(d), lds}];
-    if (b == 0) b = wide_blocks_per_cu(d, lds);
+    int& b = c->wws->bpc[{d, K}];
+    if (b == 0) {
+        b = wide_blocks_per_cu(d, K);
+        // widths of 12 and more: at most 2 blocks per compute unit.  At d =
+        // 16 the registers and LDS admit 3, which was measured slower (N =
+        // 1e7, K = 256, per update: 512 blocks 1287 us, 768 blocks 1540 us,
+        // 1024 blocks 1367 us; tiled, K = 2048, N = 2e6: 512 blocks 3522 us,
+        // 768 blocks 4781 us).
+        if (wide_width(d) >= 12 && b > 2) b = 2;
+    }
     const int P = points_per_lane(d);
     const int64_t groups = (N + P - 1) / P;
     const int64_t need = (groups + WBLOCK - 1) / WBLOCK;
@@ -157,9 +165,10 @@ int stage_upload(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, in
     h->E = INFINITY;
     double* m64 = w->mu_h;
     float* m32 = reinterpret_cast<float*>(w->mu_h + (size_t)K * d);
-    for (int k = 0; k < K; ++k) {
+    const int kp = wide_kpad(K);  // zero rows up to a whole triple
+    for (int k = 0; k < kp; ++k) {
         for (int j = 0; j < DS; ++j) m32[(size_t)k * DS + j] = 0.0f;
-        for (int j = 0; j < d; ++j) {
+        for (int j = 0; j < d && k < K; ++j) {
             m64[(size_t)k * d + j] = mu[(size_t)k * d + j];
             m32[(size_t)k * DS + j] = (float)mu[(size_t)k * d + j];  // round to nearest even
         }
@@ -167,7 +176,7 @@ int stage_upload(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, in
     KM_HIP(c, hipMemcpyAsync(w->st, h, kWUploadBytes, hipMemcpyHostToDevice, c->stream));
     KM_HIP(c, hipMemcpyAsync(w->mu64, m64, sizeof(double) * (size_t)K * d, hipMemcpyHostToDevice,
                              c->stream));
-    KM_HIP(c, hipMemcpyAsync(w->mu32, m32, sizeof(float) * (size_t)K * DS, hipMemcpyHostToDevice,
+    KM_HIP(c, hipMemcpyAsync(w->mu32, m32, sizeof(float) * (size_t)kp * DS, hipMemcpyHostToDevice,
                              c->stream));
     return KM_OK;
 }

@@ -111,6 +111,189 @@ __device__ __forceinline__ double wide_direct64(const float (&x)[D], const float
     return s;
 }
 
+// The scan of one lane's P points x against the centre triples [0, ntri) of
+// a table in LDS (cm4: rows of NB float4, hh: the key constants): keys
+// m_k . x - |m_k|^2 / 2 (the largest is the nearest centre), the largest of
+// each triple with the triple's number within its chunk of 32 in its 5
+// lowest bits, folded into the running two largest g1v, g2v; gch is the
+// chunk of g1v, as a triple number counted from cbase (the first triple of
+// the table).
+template <int D, int P>
+__device__ __forceinline__ void scan_table(const float (&x)[P][D], const float4* cm4,
+                                           const float* hh, int ntri, int cbase, float pinf,
+                                           float (&g1v)[P], float (&g2v)[P], int (&gch)[P]) {
+    constexpr int NB = WShape<D>::NB;
+    for (int c0 = 0; c0 < ntri; c0 += 32) {
+        const int c1 = c0 + 32 < ntri ? c0 + 32 : ntri;
+        float m1[P], m2[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) { m1[p] = -INFINITY; m2[p] = -INFINITY; }
+        for (int t = c0; t < c1; ++t) {
+            float sk[3][P];
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                const int k = 3 * t + u;
+                const float h = hh[k];
+#pragma unroll
+                for (int p = 0; p < P; ++p) sk[u][p] = h;
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const float4 m = cm4[k * NB + b];
+                    const float mv[4] = {m.x, m.y, m.z, m.w};
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int j = 4 * b + v;
+                        if (j < D) {
+#pragma unroll
+                            for (int p = 0; p < P; ++p) sk[u][p] = fmaf(x[p][j], mv[v], sk[u][p]);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const float gmax = fmaxf(fmaxf(sk[0][p], sk[1][p]), sk[2][p]);
+                const float gp = with_index(gmax, t - c0);
+                m2[p] = __builtin_amdgcn_fmed3f(m1[p], gp, m2[p]);
+                m1[p] = __builtin_amdgcn_fmed3f(m1[p], gp, pinf);
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            // merge the chunk's two largest into the running two largest
+            const float hi2 = fmaxf(g2v[p], m2[p]);
+            g2v[p] = __builtin_amdgcn_fmed3f(g1v[p], m1[p], hi2);
+            gch[p] = m1[p] > g1v[p] ? cbase + c0 : gch[p];
+            g1v[p] = fmaxf(g1v[p], m1[p]);
+        }
+    }
+}
+
+// Per-point constants of the certificate (see finish_points).
+struct WBound {
+    float kc, dc, hmax;
+};
+
+// The rounding of the two keys of a comparison: each key is d FMAs on
+// -fl32(|m|^2)/2, within gamma_{d+1} mag(x) of the exact key, gamma_n =
+// n u / (1 - n u), u = 2^-24, so both within (d + 1) 2^-23 mag(x) (with
+// 2^-10 to spare for the float32 evaluation of mag and of the gap); and,
+// with a factor of 16 to spare, twice the float64 rounding of the direct
+// form of the two distances (the near-tie rule): (d + 2) 2^-53 (D1 + D2)
+// with D1 + D2 <= 2 (|x|^2 + 2 |t1| + gap).
+__device__ __forceinline__ WBound wide_bound(int d, const float* amax) {
+    return WBound{(float)(d + 1) * 0x1.004p-23f, (float)(d + 2) * 0x1p-49f, 0.5f * amax[WD_MAX]};
+}
+
+// The end of the scan for one lane's P points: the winning triple's keys
+// formed again (bit-identical) from the centre rows crow (NB float4 each,
+// zero rows past K up to a whole triple) and constants hrow -- in LDS, or in
+// device memory when the centres were staged in tiles -- its largest key,
+// the first index attaining it and the triple's second largest; the
+// certificate; certified points to sink(x, i, k, dist), the others to
+// queue(flag, i) (every lane calls it, flag false for a point it does not
+// queue).
+template <int D, int P, typename Sink, typename Queue>
+__device__ __forceinline__ void finish_points(const float (&x)[P][D], int n, int64_t i0,
+                                              const float (&g1v)[P], const float (&g2v)[P],
+                                              const int (&gch)[P], const float4* crow,
+                                              const float* hrow, int K, int d,
+                                              const float* amax, WBound wb, Sink&& sink,
+                                              Queue&& queue) {
+    constexpr int NB = WShape<D>::NB;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int t = gch[p] + (int)(__float_as_uint(g1v[p]) & TRI_BITS);
+        const int k0 = 3 * t;
+        float s3[3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            float v = hrow[k0 + u];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const float4 m = crow[(k0 + u) * NB + b];
+                const float mv[4] = {m.x, m.y, m.z, m.w};
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    const int j = 4 * b + w;
+                    if (j < D) v = fmaf(x[p][j], mv[w], v);
+                }
+            }
+            s3[u] = v;
+        }
+        const float t1 = fmaxf(fmaxf(s3[0], s3[1]), s3[2]);
+        const float t2 = __builtin_amdgcn_fmed3f(s3[0], s3[1], s3[2]);
+        const int k = s3[0] == t1 ? k0 : (s3[1] == t1 ? k0 + 1 : k0 + 2);
+        // certificate: the gap to the runner-up exceeds the rounding of
+        // both keys and the float64 rounding of the direct form (so that
+        // it, too, ranks them so).  Every other triple's largest key is
+        // at most its packed maximum plus the index bits (31 units in the
+        // last place, below 2^-18 of it), and that packed maximum is at
+        // most g2v: so at most g2v + 2^-17 |g2v| (p + 2^-18 |p| grows
+        // with p).  With a single triple g2v = -inf, the sum is a NaN and
+        // fmaxf returns t2.
+        const float sec = fmaxf(t2, g2v[p] + ldexpf(fabsf(g2v[p]), -17));
+        const float gap = t1 - sec;
+        float mag = wb.hmax, xx = 0.0f;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const float a = j < d ? amax[j] : 0.0f;
+            mag = fmaf(a, fabsf(x[p][j]), mag);
+            xx = fmaf(x[p][j], x[p][j], xx);
+        }
+        const float bound = fmaf(wb.kc, mag, wb.dc * (xx + 2.0f * fabsf(t1) + fabsf(gap)));
+        const bool valid = p < n;
+        const bool ok = gap > bound && k < K;
+        if (valid && ok) sink(x[p], i0 + p, k, wide_direct<D>(x[p], crow + k * NB));
+        queue(valid && !ok, i0 + p);
+    }
+}
+
+// A wave's queue of uncertified points (wq, LDS, WQCAP entries), re-scanned
+// 64 at a time, one per lane, in the float64 direct form over all K centre
+// rows crow (LDS or device memory), first index of the minimum.
+template <int D, typename Sink>
+struct WQueue {
+    const float* X;
+    int64_t ld;
+    int d, K;
+    const float4* crow;
+    int* wq;
+    Sink& sink;
+    int qn = 0;  // queue length (the same in every lane)
+
+    __device__ __forceinline__ void drain(int cnt) {
+        constexpr int NB = WShape<D>::NB;
+        const int lane = threadIdx.x & 63;
+        __builtin_amdgcn_wave_barrier();
+        if (lane < cnt) {
+            const int64_t i = wq[qn - cnt + lane];
+            float xr[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) xr[j] = j < d ? X[(int64_t)j * ld + i] : 0.0f;
+            double bq = INFINITY;
+            int bk = 0;
+#pragma unroll 1
+            for (int k = 0; k < K; ++k) {
+                const double dk = wide_direct64<D>(xr, crow + k * NB);
+                if (dk < bq) { bq = dk; bk = k; }
+            }
+            sink(xr, i, bk, wide_direct<D>(xr, crow + bk * NB));
+        }
+        __builtin_amdgcn_wave_barrier();
+        qn -= cnt;
+    }
+    __device__ __forceinline__ void push(bool f, int64_t i) {
+        const int lane = threadIdx.x & 63;
+        const uint64_t mq = __ballot(f);
+        if (mq) {
+            if (f) wq[qn + __popcll(mq & ((1ull << lane) - 1ull))] = (int)i;
+            qn += __popcll(mq);
+            if (qn >= 64) drain(64);
+        }
+    }
+};
+
 // Reassignment of this thread's grid-stride share of the points against the
 // K centres cm (LDS, Kpad rows of stride DS, zero padded) with the key
 // constants hh and the bound coefficients amax (see the file header).
@@ -122,46 +305,16 @@ __device__ __forceinline__ void wide_points(const WState* __restrict__ st, const
                                             const float* hh, const float* amax, int K, int d,
                                             int* __restrict__ wq, Sink&& sink) {
     using S = WShape<D>;
-    constexpr int P = S::P, NB = S::NB;
+    constexpr int P = S::P;
     const int64_t N = st->N, ld = st->ld;
     const float* __restrict__ X = st->X;
     const bool vec = st->vec != 0;
     const float pinf = st->plus_inf;
     const int ntri = (K + 2) / 3;
     const int lane = threadIdx.x & 63;
-    const uint64_t below = (1ull << lane) - 1ull;
     const float4* cm4 = reinterpret_cast<const float4*>(cm);
-    // the rounding of the two keys of a comparison: each key is d FMAs on
-    // -fl32(|m|^2)/2, within gamma_{d+1} mag(x) of the exact key, gamma_n =
-    // n u / (1 - n u), u = 2^-24, so both within (d + 1) 2^-23 mag(x) (with
-    // 2^-10 to spare for the float32 evaluation of mag and of the gap); and,
-    // with a factor of 16 to spare, twice the float64 rounding of the direct
-    // form of the two distances (the near-tie rule): (d + 2) 2^-53 (D1 + D2)
-    // with D1 + D2 <= 2 (|x|^2 + 2 |t1| + gap)
-    const float kc = (float)(d + 1) * 0x1.004p-23f;
-    const float dc = (float)(d + 2) * 0x1p-49f;
-    const float hmax = 0.5f * amax[WD_MAX];
-    int qn = 0;  // this wave's queue length (the same in every lane)
-
-    auto drain = [&](int cnt) {
-        __builtin_amdgcn_wave_barrier();
-        if (lane < cnt) {
-            const int64_t i = wq[qn - cnt + lane];
-            float xr[D];
-#pragma unroll
-            for (int j = 0; j < D; ++j) xr[j] = j < d ? X[(int64_t)j * ld + i] : 0.0f;
-            double bq = INFINITY;
-            int bk = 0;
-#pragma unroll 1
-            for (int k = 0; k < K; ++k) {
-                const double dk = wide_direct64<D>(xr, cm4 + k * NB);
-                if (dk < bq) { bq = dk; bk = k; }
-            }
-            sink(xr, i, bk, wide_direct<D>(xr, cm4 + bk * NB));
-        }
-        __builtin_amdgcn_wave_barrier();
-        qn -= cnt;
-    };
+    const WBound wb = wide_bound(d, amax);
+    WQueue<D, Sink> q{X, ld, d, K, cm4, wq, sink};
 
     const int64_t ngroups = (N + P - 1) / P;
     // the loop runs over whole waves (the queue and its ballots need every
@@ -180,112 +333,82 @@ __device__ __forceinline__ void wide_points(const WState* __restrict__ st, const
 #pragma unroll
                 for (int j = 0; j < D; ++j) x[p][j] = 0.0f;
         }
-        // keys m_k . x - |m_k|^2 / 2 (the largest is the nearest centre),
-        // triples of centres, 32 triples to a chunk (5 index bits)
         float g1v[P], g2v[P];
         int gch[P];
 #pragma unroll
         for (int p = 0; p < P; ++p) { g1v[p] = -INFINITY; g2v[p] = -INFINITY; gch[p] = 0; }
-        for (int c0 = 0; c0 < ntri; c0 += 32) {
-            const int c1 = c0 + 32 < ntri ? c0 + 32 : ntri;
-            float m1[P], m2[P];
-#pragma unroll
-            for (int p = 0; p < P; ++p) { m1[p] = -INFINITY; m2[p] = -INFINITY; }
-            for (int t = c0; t < c1; ++t) {
-                float sk[3][P];
-#pragma unroll
-                for (int u = 0; u < 3; ++u) {
-                    const int k = 3 * t + u;
-                    const float h = hh[k];
-#pragma unroll
-                    for (int p = 0; p < P; ++p) sk[u][p] = h;
-#pragma unroll
-                    for (int b = 0; b < NB; ++b) {
-                        const float4 m = cm4[k * NB + b];
-                        const float mv[4] = {m.x, m.y, m.z, m.w};
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int j = 4 * b + v;
-                            if (j < D) {
-#pragma unroll
-                                for (int p = 0; p < P; ++p) sk[u][p] = fmaf(x[p][j], mv[v], sk[u][p]);
-                            }
-                        }
-                    }
-                }
-#pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    const float gmax = fmaxf(fmaxf(sk[0][p], sk[1][p]), sk[2][p]);
-                    const float gp = with_index(gmax, t - c0);
-                    m2[p] = __builtin_amdgcn_fmed3f(m1[p], gp, m2[p]);
-                    m1[p] = __builtin_amdgcn_fmed3f(m1[p], gp, pinf);
-                }
-            }
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-                // merge the chunk's two largest into the running two largest
-                const float hi2 = fmaxf(g2v[p], m2[p]);
-                g2v[p] = __builtin_amdgcn_fmed3f(g1v[p], m1[p], hi2);
-                gch[p] = m1[p] > g1v[p] ? c0 : gch[p];
-                g1v[p] = fmaxf(g1v[p], m1[p]);
-            }
-        }
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            // the winning triple's keys again (bit-identical): its largest, the
-            // first index attaining it, and the triple's second largest
-            const int t = gch[p] + (int)(__float_as_uint(g1v[p]) & TRI_BITS);
-            const int k0 = 3 * t;
-            float s3[3];
-#pragma unroll
-            for (int u = 0; u < 3; ++u) {
-                float v = hh[k0 + u];
-#pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    const float4 m = cm4[(k0 + u) * NB + b];
-                    const float mv[4] = {m.x, m.y, m.z, m.w};
-#pragma unroll
-                    for (int w = 0; w < 4; ++w) {
-                        const int j = 4 * b + w;
-                        if (j < D) v = fmaf(x[p][j], mv[w], v);
-                    }
-                }
-                s3[u] = v;
-            }
-            const float t1 = fmaxf(fmaxf(s3[0], s3[1]), s3[2]);
-            const float t2 = __builtin_amdgcn_fmed3f(s3[0], s3[1], s3[2]);
-            const int k = s3[0] == t1 ? k0 : (s3[1] == t1 ? k0 + 1 : k0 + 2);
-            // certificate: the gap to the runner-up exceeds the rounding of
-            // both keys and the float64 rounding of the direct form (so that
-            // it, too, ranks them so).  Every other triple's largest key is
-            // at most its packed maximum plus the index bits (31 units in the
-            // last place, below 2^-18 of it), and that packed maximum is at
-            // most g2v: so at most g2v + 2^-17 |g2v| (p + 2^-18 |p| grows
-            // with p).  With a single triple g2v = -inf, the sum is a NaN and
-            // fmaxf returns t2.
-            const float sec = fmaxf(t2, g2v[p] + ldexpf(fabsf(g2v[p]), -17));
-            const float gap = t1 - sec;
-            float mag = hmax, xx = 0.0f;
-#pragma unroll
-            for (int j = 0; j < D; ++j) {
-                const float a = j < d ? amax[j] : 0.0f;
-                mag = fmaf(a, fabsf(x[p][j]), mag);
-                xx = fmaf(x[p][j], x[p][j], xx);
-            }
-            const float bound = fmaf(kc, mag, dc * (xx + 2.0f * fabsf(t1) + fabsf(gap)));
-            const bool valid = p < n;
-            const bool ok = gap > bound && k < K;
-            if (valid && ok) sink(x[p], i0 + p, k, wide_direct<D>(x[p], cm4 + k * NB));
-            const bool f = valid && !ok;
-            const uint64_t mq = __ballot(f);
-            if (mq) {
-                if (f) wq[qn + __popcll(mq & below)] = (int)(i0 + p);
-                qn += __popcll(mq);
-                if (qn >= 64) drain(64);
-            }
-        }
+        scan_table<D, P>(x, cm4, hh, ntri, 0, pinf, g1v, g2v, gch);
+        finish_points<D, P>(x, n, i0, g1v, g2v, gch, cm4, hh, K, d, amax, wb, sink,
+                            [&](bool f, int64_t i) { q.push(f, i); });
     }
-    if (qn > 0) drain(qn);
+    if (q.qn > 0) q.drain(q.qn);
+}
+
+// Centres per LDS tile of the tiled scan (wide.h).
+template <int D>
+struct WTile {
+    static constexpr int KT = wide_tile_k(WShape<D>::DS);
+};
+
+// The same reassignment for K whose tables exceed one block's LDS: the
+// block's threads take groups of points in step (a whole block per round,
+// lanes past the end carry none), and each round stages the centres into LDS
+// tile by tile (cm: WTile<D>::KT rows, hh: their constants), two barriers
+// per tile, folding every tile into the running two largest keys.  The
+// winning triple's keys, the certificate's direct distance and the float64
+// re-scan read the centre rows and constants from device memory (st->mu32,
+// st->hh: L2-resident, zero rows past K up to a whole triple).
+template <int D, typename Sink>
+__device__ __forceinline__ void wide_points_tiled(const WState* __restrict__ st, float* cm,
+                                                  float* hh, const float* amax, int K, int d,
+                                                  int* __restrict__ wq, Sink&& sink) {
+    using S = WShape<D>;
+    constexpr int P = S::P, DS = S::DS, KT = WTile<D>::KT;
+    const int tid = threadIdx.x;
+    const int64_t N = st->N, ld = st->ld;
+    const float* __restrict__ X = st->X;
+    const bool vec = st->vec != 0;
+    const float pinf = st->plus_inf;
+    const float* __restrict__ gmu = st->mu32;
+    const float* __restrict__ ghh = st->hh;
+    const float4* grow = reinterpret_cast<const float4*>(gmu);
+    const float4* cm4 = reinterpret_cast<const float4*>(cm);
+    const WBound wb = wide_bound(d, amax);
+    WQueue<D, Sink> q{X, ld, d, K, grow, wq, sink};
+
+    const int64_t ngroups = (N + P - 1) / P;
+    for (int64_t base = (int64_t)blockIdx.x * WBLOCK; base < ngroups;
+         base += (int64_t)gridDim.x * WBLOCK) {
+        const int64_t g = base + tid;
+        const int64_t i0 = g * P;
+        const int n = g < ngroups ? ((N - i0) < P ? (int)(N - i0) : P) : 0;
+        float x[P][D];
+        if (n > 0) {
+            wide_load<D, P>(X, ld, d, vec, i0, n, x);
+        } else {
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+#pragma unroll
+                for (int j = 0; j < D; ++j) x[p][j] = 0.0f;
+        }
+        float g1v[P], g2v[P];
+        int gch[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) { g1v[p] = -INFINITY; g2v[p] = -INFINITY; gch[p] = 0; }
+        for (int k0 = 0; k0 < K; k0 += KT) {
+            const int kn = K - k0 < KT ? K - k0 : KT;
+            const int kpn = wide_kpad(kn);
+            __syncthreads();  // every wave is done with the previous tile
+            for (int i = tid; i < kpn * DS; i += WBLOCK)
+                cm[i] = k0 * DS + i < K * DS ? gmu[(size_t)k0 * DS + i] : 0.0f;
+            for (int i = tid; i < kpn; i += WBLOCK) hh[i] = ghh[k0 + i];
+            __syncthreads();
+            scan_table<D, P>(x, cm4, hh, kpn / 3, k0 / 3, pinf, g1v, g2v, gch);
+        }
+        finish_points<D, P>(x, n, i0, g1v, g2v, gch, grow, ghh, K, d, amax, wb, sink,
+                            [&](bool f, int64_t i) { q.push(f, i); });
+    }
+    if (q.qn > 0) q.drain(q.qn);
 }
 
 // Key tables of the float32 centres mu32 (K rows of stride DS): hh[k] =
@@ -498,6 +621,85 @@ __global__ __launch_bounds__(WBLOCK) void wide_update_track(WState* __restrict__
     wide_update_body<D, true>(st, wsm);
 }
 
+// The update for shapes beyond one block's LDS (wide_tiled): the tiled scan,
+// and each point's fixed-point coordinates and count added straight into the
+// block's own row of partials in device memory (integer atomics of the
+// block's threads only; the row is cleared first, and the next kernel,
+// wide_reduce, reads it).  q = rint(x 2^F) is the bit pattern of fxp_bits
+// less FXP_MAGIC_BITS, so the row holds the sums of q themselves.  TRACK as
+// in wide_update_body.
+template <int D, bool TRACK>
+__device__ __forceinline__ void wide_update_tiled_body(WState* __restrict__ st,
+                                                       unsigned char* wsm) {
+    using S = WShape<D>;
+    constexpr int KT = WTile<D>::KT;
+    const int tid = threadIdx.x;
+    const int d = st->d, K = st->K, nacc = K * (d + 1);
+    float* cm = reinterpret_cast<float*>(wsm);
+    float* hh = cm + (size_t)KT * S::DS;
+    float* amax = hh + ((KT + 3) & ~3);
+    int* q0 = reinterpret_cast<int*>(amax + 36);
+    int* wq = q0 + (tid >> 6) * WQCAP;
+    double* sw = reinterpret_cast<double*>(q0 + NW * WQCAP);
+    const double fscale = fxp_scale(data_exponent(st->absmax_bits));
+    unsigned long long* row = st->part + (size_t)blockIdx.x * nacc;
+    for (int i = tid; i < nacc; i += WBLOCK) row[i] = 0ull;
+    for (int i = tid; i <= WD_MAX; i += WBLOCK) amax[i] = st->amax[i];
+    wait_mem();  // the cleared row is in L2 before any thread adds to it
+    __syncthreads();
+    double jl = 0.0;
+    int32_t* __restrict__ track = st->track;
+    uint32_t nchg = 0;
+    wide_points_tiled<D>(st, cm, hh, amax, K, d, wq,
+                         [&](const float (&xr)[D], int64_t i, int k, float dist) {
+        jl += (double)dist;
+        if constexpr (TRACK) {
+            if (track[i] != k) {
+                track[i] = k;
+                ++nchg;
+            }
+        }
+        unsigned long long* a = row + k;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            if (j < d)
+                __hip_atomic_fetch_add(&a[j * K], fxp_bits(xr[j], fscale) - FXP_MAGIC_BITS,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        __hip_atomic_fetch_add(&a[d * K], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    });
+    if constexpr (TRACK) {
+        nchg = wave_sum_u32(nchg);
+        // per-wave counts in the first word of each wave's (drained) queue
+        if ((tid & 63) == 0) q0[(tid >> 6) * WQCAP] = (int)nchg;
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long chg = 0ull;
+#pragma unroll
+            for (int v = 0; v < NW; ++v) chg += (uint32_t)q0[v * WQCAP];
+            if (chg)
+                __hip_atomic_fetch_add(&row[d * K], chg << 32, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+    const double jb = block_sum(jl, sw);
+    if (tid == 0) st->jpart[blockIdx.x] = jb;
+}
+
+template <int D>
+__global__ __launch_bounds__(WBLOCK) void wide_update_tiled(WState* __restrict__ st) {
+    extern __shared__ __align__(16) unsigned char wsm[];
+    if (st->done) return;
+    wide_update_tiled_body<D, false>(st, wsm);
+}
+
+template <int D>
+__global__ __launch_bounds__(WBLOCK) void wide_update_tiled_track(WState* __restrict__ st) {
+    extern __shared__ __align__(16) unsigned char wsm[];
+    if (st->done) return;
+    wide_update_tiled_body<D, true>(st, wsm);
+}
+
 // Totals of the partial rows, then (last block) the float64 mean step.
 // Grid: x = tiles of WBLOCK slots, y = chunks of WCHUNK rows.
 __global__ __launch_bounds__(WBLOCK) void wide_reduce(WState* __restrict__ st) {
@@ -648,6 +850,48 @@ __global__ __launch_bounds__(WBLOCK) void wide_label(WState* __restrict__ st,
     }
 }
 
+// Reassignment only, for shapes beyond one block's LDS (the tiled scan).
+template <int D>
+__global__ __launch_bounds__(WBLOCK) void wide_label_tiled(WState* __restrict__ st,
+                                                           int32_t* __restrict__ labels) {
+    extern __shared__ __align__(16) unsigned char wsm[];
+    __shared__ double sw[64];
+    __shared__ int sflag;
+    using S = WShape<D>;
+    constexpr int KT = WTile<D>::KT;
+    const int tid = threadIdx.x;
+    const int d = st->d, K = st->K;
+    float* cm = reinterpret_cast<float*>(wsm);
+    float* hh = cm + (size_t)KT * S::DS;
+    float* amax = hh + ((KT + 3) & ~3);
+    int* wq = reinterpret_cast<int*>(amax + 36) + (tid >> 6) * WQCAP;
+    for (int i = tid; i <= WD_MAX; i += WBLOCK) amax[i] = st->amax[i];
+    __syncthreads();
+    double jl = 0.0;
+    wide_points_tiled<D>(st, cm, hh, amax, K, d, wq,
+                         [&](const float (&)[D], int64_t i, int k, float dist) {
+        jl += (double)dist;
+        if (labels) labels[i] = k;
+    });
+    const double jb = block_sum(jl, sw);
+    if (tid == 0) {
+        st_agent(&st->jpart[blockIdx.x], jb);
+        wait_mem();
+        const uint32_t old = __hip_atomic_fetch_add(&st->ticket, 1u, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        sflag = old == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!sflag) return;
+    const int nb = gridDim.x;
+    const double* jp = st->jpart;
+    const double J = ordered_sum(nb, [&](int b) { return ld_agent(&jp[b]); }, sw);
+    if (tid == 0) {
+        st->J = J;
+        st_agent(&st->ticket, 0u);
+    }
+}
+
 #define KM_WIDE_DISPATCH(KERN, d, grid, lds, s, ...)                                          \
     switch (wide_width(d)) {                                                                 \
         case 1: hipLaunchKernelGGL(KERN<1>, dim3(grid), dim3(WBLOCK), lds, s, __VA_ARGS__); break;   \
@@ -672,14 +916,22 @@ hipError_t launch_wide_scan(WState* st, int grid, hipStream_t s) {
 }
 
 hipError_t launch_wide_update(WState* st, int d, int K, bool track, int grid, hipStream_t s) {
-    const size_t lds = wide_lds_bytes(d, K);
-    if (grid < 1 || grid > WMAX_GRID || d < 1 || d > WD_MAX || K < 1 || K > WK_MAX ||
-        lds > (size_t)WLDS_MAX)
+    if (grid < 1 || grid > WMAX_GRID || d < 1 || d > WD_MAX || K < 1 || K > WK_MAX)
         return hipErrorInvalidValue;
-    if (track) {
-        KM_WIDE_DISPATCH(wide_update_track, d, grid, lds, s, st)
+    if (wide_tiled(d, K)) {
+        const size_t lds = wide_tiled_lds_bytes(d);
+        if (track) {
+            KM_WIDE_DISPATCH(wide_update_tiled_track, d, grid, lds, s, st)
+        } else {
+            KM_WIDE_DISPATCH(wide_update_tiled, d, grid, lds, s, st)
+        }
     } else {
-        KM_WIDE_DISPATCH(wide_update, d, grid, lds, s, st)
+        const size_t lds = wide_lds_bytes(d, K);
+        if (track) {
+            KM_WIDE_DISPATCH(wide_update_track, d, grid, lds, s, st)
+        } else {
+            KM_WIDE_DISPATCH(wide_update, d, grid, lds, s, st)
+        }
     }
     return hipGetLastError();
 }
@@ -698,31 +950,42 @@ hipError_t launch_wide_reduce(WState* st, int d, int K, int grid_update, hipStre
 
 hipError_t launch_wide_label(WState* st, int32_t* labels, int d, int K, int grid,
                              hipStream_t s) {
-    const size_t lds = wide_table_bytes(d, K);
-    if (grid < 1 || grid > WMAX_GRID || d < 1 || d > WD_MAX || K < 1 || K > WK_MAX ||
-        lds > (size_t)WLDS_MAX)
+    if (grid < 1 || grid > WMAX_GRID || d < 1 || d > WD_MAX || K < 1 || K > WK_MAX)
         return hipErrorInvalidValue;
-    KM_WIDE_DISPATCH(wide_label, d, grid, lds, s, st, labels)
+    if (wide_tiled(d, K)) {
+        const size_t lds = wide_tiled_lds_bytes(d);
+        KM_WIDE_DISPATCH(wide_label_tiled, d, grid, lds, s, st, labels)
+    } else {
+        const size_t lds = wide_table_bytes(d, K);
+        KM_WIDE_DISPATCH(wide_label, d, grid, lds, s, st, labels)
+    }
     return hipGetLastError();
 }
 
-int wide_blocks_per_cu(int d, size_t lds) {
-    int n = 0;
-    hipError_t e = hipErrorInvalidValue;
-    switch (wide_width(d)) {
-        case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(wide_update<1>), WBLOCK, lds); break;
-        case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(wide_update<2>), WBLOCK, lds); break;
-        case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(wide_update<3>), WBLOCK, lds); break;
-        case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(wide_update<4>), WBLOCK, lds); break;
-        case 6: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(wide_update<6>), WBLOCK, lds); break;
-        case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(wide_update<8>), WBLOCK, lds); break;
-        case 12: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(wide_update<12>), WBLOCK, lds); break;
-        case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(wide_update<16>), WBLOCK, lds); break;
-        case 24: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(wide_update<24>), WBLOCK, lds); break;
-        case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(wide_update<32>), WBLOCK, lds); break;
-        default: break;
+#define KM_WIDE_OCC(KERN)                                                                      \
+    [](int w, size_t lds) {                                                                    \
+        int n = 0;                                                                             \
+        hipError_t e = hipErrorInvalidValue;                                                   \
+        switch (w) {                                                                           \
+            case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(KERN<1>), WBLOCK, lds); break;   \
+            case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(KERN<2>), WBLOCK, lds); break;   \
+            case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(KERN<3>), WBLOCK, lds); break;   \
+            case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(KERN<4>), WBLOCK, lds); break;   \
+            case 6: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(KERN<6>), WBLOCK, lds); break;   \
+            case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(KERN<8>), WBLOCK, lds); break;   \
+            case 12: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(KERN<12>), WBLOCK, lds); break; \
+            case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(KERN<16>), WBLOCK, lds); break; \
+            case 24: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(KERN<24>), WBLOCK, lds); break; \
+            case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(KERN<32>), WBLOCK, lds); break; \
+            default: break;                                                                    \
+        }                                                                                      \
+        return e == hipSuccess ? n : 0;                                                        \
     }
-    return e == hipSuccess ? n : 0;
+
+int wide_blocks_per_cu(int d, int K) {
+    const int w = wide_width(d);
+    if (wide_tiled(d, K)) return KM_WIDE_OCC(wide_update_tiled)(w, wide_tiled_lds_bytes(d));
+    return KM_WIDE_OCC(wide_update)(w, wide_lds_bytes(d, K));
 }
 
 }  // namespace km

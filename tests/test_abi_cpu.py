@@ -48,13 +48,13 @@ def test_abi_version():
     ((100, 100, 3, 65, 1e-6, 10), km.KM_OK),
     ((2000, 2000, 3, 1024, 1e-6, 10), km.KM_OK),
     ((2000, 2000, 16, 309, 1e-6, 10), km.KM_OK),
-    ((2000, 2000, 16, 310, 1e-6, 10), km.KM_EUNSUPPORTED),
-    ((2000, 2000, 32, 159, 1e-6, 10), km.KM_OK),
-    ((2000, 2000, 32, 160, 1e-6, 10), km.KM_EUNSUPPORTED),
-    ((2000, 2000, 8, 585, 1e-6, 10), km.KM_OK),
-    ((2000, 2000, 8, 586, 1e-6, 10), km.KM_EUNSUPPORTED),
+    ((2000, 2000, 16, 310, 1e-6, 10), km.KM_OK),       # the tiled general-shape kernels
+    ((2000, 2000, 32, 160, 1e-6, 10), km.KM_OK),
+    ((5000, 5000, 16, 4096, 1e-6, 10), km.KM_OK),
+    ((5000, 5000, 32, 4096, 1e-6, 10), km.KM_OK),
+    ((5000, 5000, 16, 4097, 1e-6, 10), km.KM_EUNSUPPORTED),
     ((2000, 2000, 33, 2, 1e-6, 10), km.KM_EUNSUPPORTED),
-    ((2000, 2000, 2, 1025, 1e-6, 10), km.KM_EUNSUPPORTED),
+    ((5000, 5000, 2, 4097, 1e-6, 10), km.KM_EUNSUPPORTED),
     ((100, 100, 0, 4, 1e-6, 10), km.KM_EINVAL),
     ((10, 10, 2, 11, 1e-6, 10), km.KM_EINVAL),
     ((0, 0, 2, 1, 1e-6, 10), km.KM_EINVAL),

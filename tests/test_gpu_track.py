@@ -95,7 +95,8 @@ def test_tracked_without_graphs_and_at_max_iter(km):
     assert r2.iters == 3 and not r2.converged and chg2.tolist() == chg[:3].tolist()
 
 
-@pytest.mark.parametrize("d,K,N,wide", [(5, 40, 30_000, 0), (16, 100, 20_001, 0), (3, 16, 25_000, 1)])
+@pytest.mark.parametrize("d,K,N,wide", [(5, 40, 30_000, 0), (16, 100, 20_001, 0), (3, 16, 25_000, 1),
+                                        (16, 500, 12_001, 0)])
 def test_tracked_general_shapes(km, d, K, N, wide):
     log(f"track general d={d} K={K} N={N} wide={wide}")
     s = datagen.spec("C2", N=N, d=d, K=K, seed=96 + d)

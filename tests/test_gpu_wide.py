@@ -37,7 +37,9 @@ def mixture(N, d, K, seed):
 @pytest.mark.parametrize("d,K,N", [
     (1, 70, 10_001), (2, 100, 50_003), (3, 1024, 30_001), (4, 65, 20_000), (5, 200, 40_007),
     (8, 585, 20_003), (12, 300, 10_001), (16, 309, 25_001), (24, 210, 9_999), (32, 159, 12_345),
-    (16, 3, 5), (7, 1, 1), (9, 128, 130)])
+    (16, 3, 5), (7, 1, 1), (9, 128, 130),
+    # beyond one block's LDS: the tiled kernels (several tiles, ragged last tile)
+    (16, 310, 9_001), (16, 2048, 30_001), (32, 512, 10_001), (3, 4096, 20_011), (8, 1700, 7_777)])
 def test_assign_matches_oracle(km, d, K, N):
     log(f"wide assign d={d} K={K} N={N}")
     s, X, Xd = mixture(N, d, max(K, 2), 5000 + d * 1000 + K)
@@ -84,7 +86,9 @@ def test_far_points_and_large_offsets(km):
 # -------------------------------------------------------------- step parity
 @pytest.mark.parametrize("d,K,N,steps", [(5, 70, 60_001, 8), (16, 256, 40_000, 6),
                                          (3, 500, 80_001, 6), (32, 100, 20_001, 5),
-                                         (1, 129, 10_000, 8)])
+                                         (1, 129, 10_000, 8),
+                                         (16, 2048, 30_000, 3), (32, 512, 20_001, 3),
+                                         (2, 4096, 60_001, 3)])
 def test_stepwise_parity(km, d, K, N, steps):
     """Each update from the GPU's float64 centres mu^t: labels against the
     oracle's reassignment, mu^{t+1}, E and the empty-cluster count against the
@@ -110,7 +114,8 @@ def test_stepwise_parity(km, d, K, N, steps):
 
 # ---------------------------------------------------------------- end to end
 @pytest.mark.parametrize("d,K,N", [(5, 70, 20_000), (16, 100, 20_000), (2, 200, 30_000),
-                                   (32, 40, 8_000), (4, 16, 50_001)])
+                                   (32, 40, 8_000), (4, 16, 50_001),
+                                   (16, 700, 15_000), (32, 300, 6_000)])
 def test_fit_end_to_end(km, d, K, N):
     s, X, Xd = mixture(N, d, K, 9000 + d + K)
     mu0 = datagen.init_sample(X, N, K, 4)
@@ -203,6 +208,49 @@ def test_bitwise_repeat_and_grid_independence(km):
         assert np.array_equal(a.labels.cpu().numpy(), b.labels.cpu().numpy())
 
 
+def test_tiled_bitwise_repeat_and_grid_independence(km):
+    """The tiled kernels (centres staged through LDS tile by tile, sums added
+    into each block's row in device memory): the same results for every grid
+    and with or without graphs."""
+    from paper_2405_12052_amd import KM_OPT_BLOCKS, KM_OPT_GRAPH
+    s, X, Xd = mixture(50_001, 16, 1000, 2468)
+    mu0 = datagen.init_sample(X, s.N, 1000, 3)
+    outs = []
+    for blocks, graph in ((0, 1), (0, 1), (1, 1), (37, 0), (512, 1)):
+        km.set_option(KM_OPT_BLOCKS, blocks)
+        km.set_option(KM_OPT_GRAPH, graph)
+        outs.append(km.fit(Xd, mu0, tol=0.0, max_iter=4))
+    km.set_option(KM_OPT_BLOCKS, 0)
+    km.set_option(KM_OPT_GRAPH, 1)
+    a = outs[0]
+    for b in outs[1:]:
+        assert np.array_equal(a.centroids, b.centroids) and a.E == b.E and b.iters == 4
+        assert np.array_equal(a.labels.cpu().numpy(), b.labels.cpu().numpy())
+    label_check(a.labels.cpu().numpy(), X, a.centroids)
+
+
+def test_tiled_empty_clusters_and_tiny(km):
+    """K beyond the LDS limit with far-away centres that stay empty, and a
+    tiled shape with fewer points than a block takes."""
+    d, N, K = 16, 20_000, 400
+    s, X, Xd = mixture(N, d, K, 97)
+    mu0 = datagen.init_sample(X, N, K - 3, 5)
+    mu0 = np.vstack([mu0, np.full((3, d), 1e5) + np.arange(3)[:, None]])
+    r = km.fit(Xd, mu0, tol=1e-6, max_iter=40)
+    ref = oracle.fit(X, mu0, tol=1e-6, max_iter=40)
+    assert r.iters == ref["T"] and r.empty_events == ref["empty_events"] > 0
+    centre_check(r.centroids, ref["mu"])
+    e_check(r.E, ref["E"])
+    assert np.array_equal(r.centroids[K - 3:], mu0[K - 3:])
+    Xs = np.ascontiguousarray(X[:, :700])
+    mu1 = Xs[:, :400].T.astype(np.float64)
+    r1 = km.fit(torch.from_numpy(Xs).cuda(), mu1, tol=1e-6, max_iter=10)
+    ref1 = oracle.fit(Xs, mu1, tol=1e-6, max_iter=10)
+    assert r1.iters == ref1["T"]
+    centre_check(r1.centroids, ref1["mu"])
+    assert np.array_equal(r1.labels.cpu().numpy(), ref1["labels"])
+
+
 def test_resume_equals_one_long_run(km):
     s, X, Xd = mixture(100_000, 6, 80, 777)
     mu0 = datagen.init_sample(X, s.N, 80, 2)
@@ -279,7 +327,7 @@ def test_error_paths(km):
     X = np.random.default_rng(0).normal(size=(16, 2000)).astype(np.float32)
     Xd = torch.from_numpy(X).cuda()
     with pytest.raises(KMeansError) as e:
-        km.fit(Xd, np.zeros((310, 16)))                  # K*(d+1) sums exceed one block's LDS
+        km.fit(Xd, np.zeros((4097, 16)))                 # K beyond the largest supported
     assert e.value.code == KM_EUNSUPPORTED
     X33 = torch.zeros((33, 100), dtype=torch.float32, device="cuda")
     with pytest.raises(KMeansError) as e:
