@@ -175,7 +175,7 @@ def bench_wide(args):
     import torch
 
     import datagen
-    from paper_2405_12052_amd import KM_OPT_TIMING, KMeans
+    from paper_2405_12052_amd import KM_OPT_KEYS, KM_OPT_TIMING, KMeans
 
     over = {k: v for k, v in (("N", args.N), ("K", args.K)) if v is not None}
     s = datagen.spec("W1", **over)
@@ -188,6 +188,7 @@ def bench_wide(args):
     torch.cuda.synchronize()
     km = KMeans(0)
     km.set_option(KM_OPT_TIMING, 1)
+    km.set_option(KM_OPT_KEYS, args.keys)
     for i in range(args.warmup):
         r = km.fit(Xd, mu0, tol=0.0, max_iter=iters)
         log(f"warmup {i}: T={r.iters} J={r.objective:.6e}")
@@ -211,7 +212,7 @@ def bench_wide(args):
     fma_peak = 2.0 * peaks["fma_lane_ops_per_s"] / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-            "kernel": f"wide_update{'_tiled' if wide_tiled(s.d, s.K) else ''}<{s.d}> + "
+            "kernel": f"wide_update{wide_variant(s.d, s.K, args.keys)}<{s.d}> + "
                       f"wide_reduce (one update)",
             "avg_update_us": per_update_s * 1e6, "alg_flops_per_update": flops,
             "alg_bytes_per_update": alg_bytes_per_point(s.d) * s.N,
@@ -237,6 +238,19 @@ def bench_wide(args):
     }
     print(json.dumps(out), flush=True)
     km.close()
+
+
+def wide_variant(d, K, keys):
+    """The general-shape update kernel's suffix for (d, K) and KM_OPT_KEYS
+    (the selection rules stated in include/kmeans.h)."""
+    w = d if d <= 4 else next(v for v in (6, 8, 12, 16, 24, 32) if d <= v)
+    if w in (8, 12, 16) and keys != 1 and (keys == 2 or K >= 64):
+        kt = (K + 31) // 32
+        steps = (3 * (w // 2) + 7) // 8
+        lds = ((8 * K * (d + 1) + 63) & ~63) + kt * steps * 1024 + kt * 128 + 2224
+        if lds <= 65536:
+            return "_mfma"
+    return "_tiled" if wide_tiled(d, K) else ""
 
 
 def wide_tiled(d, K):

@@ -73,6 +73,31 @@ __host__ __device__ constexpr size_t wide_tiled_lds_bytes(int d) {
            (size_t)(WBLOCK / 64) * WQCAP * 4 + (WBLOCK / 64) * 8;
 }
 
+// The matrix-core keys (wide_kernels.hip) for widths 8, 12 and 16: per tile
+// of 32 centres, S k-steps of A operands (S = ceil(3 (width / 2) / 8): 2 at
+// width 8, 3 at 12 and 16; 1 KB per step) and 32 accumulator inputs in LDS,
+// in place of the float32 centre table.
+__host__ __device__ constexpr bool wide_mfma_width(int d) {
+    return wide_width(d) == 8 || wide_width(d) == 12 || wide_width(d) == 16;
+}
+__host__ __device__ constexpr int wide_mfma_steps(int d) {
+    return (3 * (wide_width(d) / 2) + 7) / 8;
+}
+// LDS of the reassignment-only kernel: operands, accumulator inputs, bound
+// coefficients, re-scan queues and objective sums.
+__host__ __device__ constexpr size_t wide_mfma_table_bytes(int d, int K) {
+    return (size_t)((K + 31) / 32) * wide_mfma_steps(d) * 1024 + (size_t)((K + 31) / 32) * 128 +
+           36 * 4 + (size_t)(WBLOCK / 64) * WQCAP * 4 + (WBLOCK / 64) * 8;
+}
+// LDS of the update kernel: the integer sums and counts first (rounded to 64
+// bytes), then the tables.
+__host__ __device__ constexpr size_t wide_mfma_lds_bytes(int d, int K) {
+    return (((size_t)K * (d + 1) * 8 + 63) & ~(size_t)63) + wide_mfma_table_bytes(d, K);
+}
+__host__ __device__ constexpr bool wide_mfma_fits(int d, int K) {
+    return wide_mfma_width(d) && wide_mfma_lds_bytes(d, K) <= (size_t)WLDS_MAX;
+}
+
 struct alignas(16) WState {
     // ---- problem (host-written) ----
     const float* X;        // d rows of N float32, row j at X + j*ld
@@ -124,12 +149,13 @@ constexpr size_t kWProgressBytes = offsetof(WState, absmax_bits) - offsetof(WSta
 // Launchers (wide_kernels.hip); each returns hipErrorInvalidValue for a
 // shape or grid outside the limits above.
 hipError_t launch_wide_scan(WState* st, int grid, hipStream_t s);
-hipError_t launch_wide_update(WState* st, int d, int K, bool track, int grid, hipStream_t s);
+hipError_t launch_wide_update(WState* st, int d, int K, bool track, bool mfma, int grid,
+                              hipStream_t s);
 hipError_t launch_wide_reduce(WState* st, int d, int K, int grid_update, hipStream_t s);
-hipError_t launch_wide_label(WState* st, int32_t* labels, int d, int K, int grid,
+hipError_t launch_wide_label(WState* st, int32_t* labels, int d, int K, bool mfma, int grid,
                              hipStream_t s);
-// Resident update blocks per compute unit for (d, K) (the tiled kernel when
-// wide_tiled(d, K)); 0 on error.
-int wide_blocks_per_cu(int d, int K);
+// Resident update blocks per compute unit for (d, K) (the matrix-core kernel
+// with mfma, else the tiled kernel when wide_tiled(d, K)); 0 on error.
+int wide_blocks_per_cu(int d, int K, bool mfma);
 
 }  // namespace km

@@ -28,8 +28,9 @@ struct WideWS {
     float* hh = nullptr;       // key constants, WK_MAX + 4 floats
     float* amax = nullptr;     // bound coefficients, WD_MAX + 1 floats
     size_t part_cap = 0;       // int64 slots of part
-    std::map<std::tuple<int, int, int, int, int>, hipGraphExec_t> graphs;  // (d, K, track, grid, unroll)
-    std::map<std::pair<int, int>, int> bpc;  // (d, K) -> blocks per CU
+    // (d, K, track, matrix-core keys, grid, unroll)
+    std::map<std::tuple<int, int, int, int, int, int>, hipGraphExec_t> graphs;
+    std::map<std::tuple<int, int, int>, int> bpc;  // (d, K, matrix-core keys) -> blocks per CU
 };
 
 void wide_ws_free(WideWS* w) {
@@ -97,10 +98,18 @@ int points_per_lane(int d) { return wide_width(d) <= 16 ? 4 : 2; }
 // but never fewer than one block per FXP_BLOCK_POINTS points: a block takes
 // ceil(groups / (grid WBLOCK)) groups of P points per thread, at most
 // FXP_BLOCK_POINTS / (WBLOCK P) of them (N < 2^31 needs at most 4096 blocks).
-int update_grid(kmeans_ctx* c, int d, int K, int64_t N) {
-    int& b = c->wws->bpc[{d, K}];
+// Whether the scan takes the matrix-core keys (KM_OPT_KEYS: 0 automatic --
+// widths 8 to 16 with K >= 64 whose operands fit in LDS --, 1 never, 2
+// wherever they fit).
+bool use_mfma(const kmeans_ctx* c, int d, int K) {
+    if (c->keys == 1 || !wide_mfma_fits(d, K)) return false;
+    return c->keys == 2 || K >= 64;
+}
+
+int update_grid(kmeans_ctx* c, int d, int K, int64_t N, bool mfma) {
+    int& b = c->wws->bpc[std::make_tuple(d, K, mfma ? 1 : 0)];
     if (b == 0) {
-        b = wide_blocks_per_cu(d, K);
+        b = wide_blocks_per_cu(d, K, mfma);
         // widths of 12 and more: at most 2 blocks per compute unit.  At d =
         // 16 the registers and LDS admit 3, which was measured slower (N =
         // 1e7, K = 256, per update: 512 blocks 1287 us, 768 blocks 1540 us,
@@ -181,17 +190,18 @@ int stage_upload(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, in
     return KM_OK;
 }
 
-int launch_one_update(kmeans_ctx* c, int d, int K, bool track, int grid, hipStream_t s) {
-    hipError_t e = launch_wide_update(c->wws->st, d, K, track, grid, s);
+int launch_one_update(kmeans_ctx* c, int d, int K, bool track, bool mfma, int grid,
+                      hipStream_t s) {
+    hipError_t e = launch_wide_update(c->wws->st, d, K, track, mfma, grid, s);
     if (e == hipSuccess) e = launch_wide_reduce(c->wws->st, d, K, grid, s);
     if (e != hipSuccess) return fail(c, KM_EHIP, "launch of a general-shape update failed: %s", hipGetErrorString(e));
     return KM_OK;
 }
 
-int get_graph(kmeans_ctx* c, int d, int K, bool track, int grid, int unroll,
+int get_graph(kmeans_ctx* c, int d, int K, bool track, bool mfma, int grid, int unroll,
               hipGraphExec_t* out) {
     WideWS* w = c->wws;
-    const auto key = std::make_tuple(d, K, track ? 1 : 0, grid, unroll);
+    const auto key = std::make_tuple(d, K, track ? 1 : 0, mfma ? 1 : 0, grid, unroll);
     auto it = w->graphs.find(key);
     if (it != w->graphs.end()) {
         *out = it->second;
@@ -199,7 +209,7 @@ int get_graph(kmeans_ctx* c, int d, int K, bool track, int grid, int unroll,
     }
     KM_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     for (int i = 0; i < unroll; ++i) {
-        hipError_t e = launch_wide_update(w->st, d, K, track, grid, c->cap_stream);
+        hipError_t e = launch_wide_update(w->st, d, K, track, mfma, grid, c->cap_stream);
         if (e == hipSuccess) e = launch_wide_reduce(w->st, d, K, grid, c->cap_stream);
         if (e != hipSuccess) {
             hipGraph_t junk = nullptr;
@@ -237,7 +247,8 @@ int wide_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, int K,
     if (!rc) rc = ensure_hist(c, max_iter);
     if (rc) return rc;
     WideWS* w = c->wws;
-    const int grid = update_grid(c, d, K, N);
+    const bool mfma = use_mfma(c, d, K);
+    const int grid = update_grid(c, d, K, N, mfma);
     const bool track = c->track != 0;
     rc = stage_upload(c, X, N, ld, d, K, init, tol, max_iter, grid, track ? labels_out : nullptr);
     if (rc) return rc;
@@ -260,11 +271,12 @@ int wide_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, int K,
         }
         if (c->use_graph) {
             hipGraphExec_t ex;
-            rc = get_graph(c, d, K, track, grid, n, &ex);
+            rc = get_graph(c, d, K, track, mfma, grid, n, &ex);
             if (rc) return rc;
             KM_HIP(c, hipGraphLaunch(ex, c->stream));
         } else {
-            for (int i = 0; i < n && !rc; ++i) rc = launch_one_update(c, d, K, track, grid, c->stream);
+            for (int i = 0; i < n && !rc; ++i)
+                rc = launch_one_update(c, d, K, track, mfma, grid, c->stream);
             if (rc) return rc;
         }
         if (c->timing) KM_HIP(c, hipEventRecord(c->ev[2 * batches + 1], c->stream));
@@ -276,7 +288,7 @@ int wide_fit(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, int K,
             if (w->st_h->done) break;
         }
     }
-    KM_HIP(c, launch_wide_label(w->st, labels_out, d, K, grid, c->stream));
+    KM_HIP(c, launch_wide_label(w->st, labels_out, d, K, mfma, grid, c->stream));
     double* m64 = w->mu_h;
     KM_HIP(c, hipMemcpyAsync(m64, w->mu64, sizeof(double) * (size_t)K * d, hipMemcpyDeviceToHost,
                              c->stream));
@@ -328,11 +340,12 @@ int wide_assign(kmeans_ctx* c, const float* X, int64_t N, int64_t ld, int d, int
     int rc = ensure_ws(c);
     if (rc) return rc;
     WideWS* w = c->wws;
-    const int grid = update_grid(c, d, K, N);
+    const bool mfma = use_mfma(c, d, K);
+    const int grid = update_grid(c, d, K, N, mfma);
     rc = stage_upload(c, X, N, ld, d, K, centroids, 0.0, 1, grid, nullptr);
     if (rc) return rc;
     KM_HIP(c, launch_wide_scan(w->st, scan_grid(c, N), c->stream));
-    KM_HIP(c, launch_wide_label(w->st, labels, d, K, grid, c->stream));
+    KM_HIP(c, launch_wide_label(w->st, labels, d, K, mfma, grid, c->stream));
     rc = read_progress(c, kWProgressBytes);
     if (rc) return rc;
     if (w->st_h->flags & FLAG_NONFINITE) return fail(c, KM_EINVAL, "X holds a NaN or an infinity");

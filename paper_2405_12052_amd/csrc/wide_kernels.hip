@@ -28,6 +28,7 @@
 // centres of the squared shift) and applies the tolerance test.
 #include "wide.h"
 #include "lloyd_device.h"
+#include "lloyd_mfma.h"
 
 namespace km {
 namespace {
@@ -411,6 +412,328 @@ __device__ __forceinline__ void wide_points_tiled(const WState* __restrict__ st,
     if (q.qn > 0) q.drain(q.qn);
 }
 
+// ----------------------------------------- matrix-core keys (widths 8 to 16)
+// The keys of all K centres for 64 points at a time on the matrix cores
+// (v_mfma_f32_32x32x16_f16), in the convention of the 2-D/3-D matrix-core
+// scan (lloyd_mfma.h): the smallest key is the nearest centre,
+//   s_k = |m_k|^2 / 2 - m_k . x   (= -(the VALU scan's key)),
+// all scaled by 2^(2e), with points and centres scaled by 2^e so that every
+// |x'|, |m'| < 2^13.  Each scaled value is split v = vh + vl into two fp16
+// pieces and the product m' x' is taken as mh xh + mh xl + ml xh (each exact
+// in float32).  Rows are centres (32 to a tile), columns points (32 to a
+// chunk).  Lane half h takes the coordinates [h H, h H + H) of its point,
+// H = D / 2, so that both halves run the same instructions: its 8 inner
+// entries of k-step s are the entries 8 s .. 8 s + 7 of the sequence
+//   (mh_0, xh_0), (mh_0, xl_0), (ml_0, xh_0), (mh_1, xh_1), ...
+// over its H coordinates, zero past 3 H (S = ceil(3 H / 8) steps: 2 at
+// width 8, 3 at 12 and 16).  |m|^2 / 2 enters exactly, as the float32
+// accumulator input (pads: 2^120, above every real key).
+//
+// Each lane holds, per chunk, 16 keys of one point (result register r: the
+// centre 8 (r / 4) + 4 h + r % 4 of the tile).  Tiles are taken in pairs:
+// the packed quad minima (lloyd_mfma.h: a 3-bit number 4 (tile % 2) + quad
+// in the low mantissa bits) of a pair go through the same tournament as the
+// 2-D/3-D scan, and the pair's smallest and second smallest are merged into
+// the point's running W (with its pair) and L.  The two lane halves of a
+// point are then merged (one lane swap per value), half h finishing chunk h,
+// and the winning quad's four centres are keyed again on the VALU exactly as
+// the VALU scan keys them (its t1, first index, and t2).
+//
+// Certificate.  mag(x) = max_k |m_k|^2 / 2 + sum_j max_k |m_kj| |x_j| bounds
+// every |s_k|.  A matrix key differs from the exact key by at most e_m: the
+// split remainders and the dropped ml xl leave <= 3.01 2^-22 |m'_j||x'_j| +
+// 2^-25 (|m'_j| + |x'_j|) per coordinate, the float32 sum of the 3 D
+// products and the accumulator input, in any order and rounded to nearest or
+// toward zero, <= 3 D 2^-23 (1 + 2^-10) mag'; f16 subnormal pieces flushed
+// to zero would drop < 0.5 per product.  Packing moves a quad minimum by at
+// most 7 units in its last place.  So when
+//   L - W > 2 (3 D + 13.05) 2^-23 (1 + 2^-10) mag' + 5 D + 2^(2e) dc (|x|^2 + 2 |t1|)
+// every centre outside the winning quad is farther, in exact arithmetic,
+// than the quad's nearest by more than the float64 rounding of the direct
+// form (the dc term of the VALU certificate); when in addition the VALU
+// certificate holds for t1 against the quad's t2, the label is the
+// first-index float64 direct-form argmin.  Other points go to the float64
+// re-scan.  Scales outside e in [-24, 60] (data or centres beyond about
+// 2^36 or below 2^-48) send every point to the re-scan.
+template <int D>
+struct WMfma {
+    static constexpr int H = D / 2;            // coordinates per lane half
+    static constexpr int S = (3 * H + 7) / 8;  // k-steps of 16 inner entries
+};
+
+// Scale exponent e (|x| 2^e < 2^13, |m| 2^e < 2^13) from the data exponent
+// and the bound coefficients amax (LDS); false outside [-24, 60].
+__device__ __forceinline__ bool wide_mfma_scale(int xe, const float* amax, int d, int& e) {
+    float a = 0.0f;
+    for (int j = 0; j < d; ++j) a = fmaxf(a, amax[j]);
+    e = 12 - xe;
+    if (a > 0.0f) {
+        const int ea = 12 - ilogbf(a);
+        e = ea < e ? ea : e;
+    }
+    return e >= -24 && e <= 60;
+}
+
+// The A operands of every tile (record ((t S + s) 2 + h) 32 + c: centre
+// 32 t + c, k-step s, lane half h) and the accumulator inputs (Cs[(t 2 + h)
+// 16 + r]: centre 32 t + 8 (r / 4) + 4 h + r % 4), from the float32 centres
+// and key constants in device memory.  Whole block.
+template <int D>
+__device__ __forceinline__ void stage_mfma(const WState* __restrict__ st, int K, int d, int e,
+                                           u32x4* As, float* Cs) {
+    using M = WMfma<D>;
+    constexpr int H = M::H, S = M::S, DS = WShape<D>::DS;
+    const int KT = (K + 31) / 32;
+    const float sc = ldexpf(1.0f, e);
+    const float* __restrict__ gmu = st->mu32;
+    for (int idx = threadIdx.x; idx < KT * 64; idx += WBLOCK) {
+        const int c = idx & 31, h = (idx >> 5) & 1, t = idx >> 6;
+        const int k = 32 * t + c;
+        _Float16 hi[H], lo[H];
+#pragma unroll
+        for (int jj = 0; jj < H; ++jj) {
+            const int j = h * H + jj;
+            const float m = k < K && j < d ? -gmu[(size_t)k * DS + j] * sc : 0.0f;
+            split_f16(m, hi[jj], lo[jj]);
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            u32x4 r;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                _Float16 e2[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int v = 8 * s + 2 * w + u;
+                    e2[u] = v < 3 * H ? (v % 3 == 2 ? lo[v / 3] : hi[v / 3]) : (_Float16)0;
+                }
+                r[w] = pack2(e2[0], e2[1]);
+            }
+            As[((t * S + s) * 2 + h) * 32 + c] = r;
+        }
+    }
+    const float s2 = ldexpf(1.0f, 2 * e);
+    for (int idx = threadIdx.x; idx < KT * 32; idx += WBLOCK) {
+        const int r = idx & 15, h = (idx >> 4) & 1, t = idx >> 5;
+        const int k = 32 * t + 8 * (r >> 2) + 4 * h + (r & 3);
+        Cs[idx] = k < K ? -st->hh[k] * s2 : 0x1p120f;
+    }
+}
+
+// The B operand of one point for this lane half: its H scaled coordinates u.
+template <int D>
+__device__ __forceinline__ void point_operand_w(const float (&u)[WMfma<D>::H],
+                                                f16x8 (&B)[WMfma<D>::S]) {
+    using M = WMfma<D>;
+    constexpr int H = M::H, S = M::S;
+    _Float16 hi[H], lo[H];
+#pragma unroll
+    for (int jj = 0; jj < H; ++jj) split_f16(u[jj], hi[jj], lo[jj]);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        u32x4 r;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            _Float16 e2[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int v = 8 * s + 2 * w + q;
+                e2[q] = v < 3 * H ? (v % 3 == 1 ? lo[v / 3] : hi[v / 3]) : (_Float16)0;
+            }
+            r[w] = pack2(e2[0], e2[1]);
+        }
+        B[s] = __builtin_bit_cast(f16x8, r);
+    }
+}
+
+// The 16 keys of one tile (A: its S operands, C: its accumulator inputs)
+// for one chunk of points (B).
+template <int S>
+__device__ __forceinline__ f32x16 tile_keys(const f16x8 (&A)[S], const f16x8 (&B)[S],
+                                            const f32x16& C) {
+    f32x16 acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[0], B[0], C, 0, 0, 0);
+#pragma unroll
+    for (int s = 1; s < S; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[s], B[s], acc, 0, 0, 0);
+    return acc;
+}
+
+// Reassignment with the matrix-core keys (see above) of this wave's share of
+// the grid, 64 points at a time; same contract as wide_points.  As, Cs: the
+// staged operands (stage_mfma); amax: the bound coefficients (LDS); e, mok:
+// the scale and whether it is in range.
+template <int D, typename Sink>
+__device__ __forceinline__ void wide_points_mfma(const WState* __restrict__ st, const u32x4* As,
+                                                 const float* Cs, const float* amax, int K,
+                                                 int d, int e, bool mok, int* __restrict__ wq,
+                                                 Sink&& sink) {
+    using M = WMfma<D>;
+    constexpr int H = M::H, S = M::S, NB = WShape<D>::NB, DS = WShape<D>::DS;
+    const int lane = threadIdx.x & 63;
+    const int c = lane & 31, h = lane >> 5;
+    const int64_t N = st->N, ld = st->ld;
+    const float* __restrict__ X = st->X;
+    const bool vec = st->vec != 0;
+    const float ninf = -st->plus_inf;
+    const float4* grow = reinterpret_cast<const float4*>(st->mu32);
+    const float* __restrict__ ghh = st->hh;
+    const WBound wb = wide_bound(d, amax);
+    const int KT = (K + 31) / 32;
+    const float sc = ldexpf(1.0f, e);
+    const float s2 = ldexpf(1.0f, 2 * e);
+    const float kcm = 2.0f * (3.0f * D + 13.05f) * 0x1.004p-23f;
+    const float habs = 5.0f * D;
+    WQueue<D, Sink> q{X, ld, d, K, grow, wq, sink};
+
+    const int64_t nchunks = (N + 63) / 64;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int64_t ch = (int64_t)blockIdx.x * NW + wid; ch < nchunks;
+         ch += (int64_t)gridDim.x * NW) {
+        const int64_t i0 = ch * 64 + 2 * c;  // this lane's two points
+        const int rem = N - ch * 64 < 64 ? (int)(N - ch * 64) : 64;
+        // this half's coordinates h H .. h H + H - 1 of points i0, i0 + 1
+        float x[H][2];
+#pragma unroll
+        for (int jj = 0; jj < H; ++jj) {
+            const int j = h * H + jj;
+            if (j < d) {
+                const float* row = X + (int64_t)j * ld + i0;
+                if (vec && i0 + 2 <= N) {
+                    const float2 v = *reinterpret_cast<const float2*>(row);
+                    x[jj][0] = v.x;
+                    x[jj][1] = v.y;
+                } else {
+                    x[jj][0] = i0 < N ? row[0] : 0.0f;
+                    x[jj][1] = i0 + 1 < N ? row[1] : 0.0f;
+                }
+            } else {
+                x[jj][0] = 0.0f;
+                x[jj][1] = 0.0f;
+            }
+        }
+        float W[2] = {0.0f, 0.0f}, L[2] = {0.0f, 0.0f};
+        int G[2] = {0, 0};
+        if (mok) {
+            f16x8 B[2][S];
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                float u[H];
+#pragma unroll
+                for (int jj = 0; jj < H; ++jj) u[jj] = x[jj][p] * sc;
+                point_operand_w<D>(u, B[p]);
+            }
+            W[0] = W[1] = L[0] = L[1] = INFINITY;
+            for (int g = 0; g < KT; g += 2) {
+                float pm[2][8];
+#pragma unroll
+                for (int tt = 0; tt < 2; ++tt) {
+                    const int t = g + tt;
+                    if (tt == 1 && t >= KT) {
+#pragma unroll
+                        for (int p = 0; p < 2; ++p)
+#pragma unroll
+                            for (int r = 4; r < 8; ++r) pm[p][r] = INFINITY;
+                        break;
+                    }
+                    f16x8 A[S];
+#pragma unroll
+                    for (int s = 0; s < S; ++s)
+                        A[s] = __builtin_bit_cast(f16x8, As[((t * S + s) * 2 + h) * 32 + c]);
+                    const f32x16 C = *reinterpret_cast<const f32x16*>(Cs + (t * 2 + h) * 16);
+#pragma unroll
+                    for (int p = 0; p < 2; ++p) {
+                        const f32x16 kk = tile_keys<S>(A, B[p], C);
+                        if (tt == 0) tile_minima<0>(kk, ninf, reinterpret_cast<float(&)[4]>(pm[p][0]));
+                        else tile_minima<1>(kk, ninf, reinterpret_cast<float(&)[4]>(pm[p][4]));
+                    }
+                }
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    float a1, a2, b1, b2;
+                    top2_3(pm[p][0], pm[p][1], pm[p][2], a1, a2);
+                    top2_3(pm[p][3], pm[p][4], pm[p][5], b1, b2);
+                    top2_merge(a1, a2, b1, b2);
+                    top2_merge(a1, a2, vmin2(pm[p][6], pm[p][7]), vmax2(pm[p][6], pm[p][7]));
+                    // into the running pair
+                    L[p] = vmin3(vmax2(W[p], a1), L[p], a2);
+                    G[p] = a1 < W[p] ? g : G[p];
+                    W[p] = vmin2(W[p], a1);
+                }
+            }
+        }
+        // lane half h finishes chunk h (point i0 + h): after each swap, w0
+        // is the h = 0 lane's value for that point, w1 the h = 1 lane's
+        const auto ws = __builtin_amdgcn_permlane32_swap(__float_as_uint(W[0]),
+                                                          __float_as_uint(W[1]), false, false);
+        const auto ls = __builtin_amdgcn_permlane32_swap(__float_as_uint(L[0]),
+                                                          __float_as_uint(L[1]), false, false);
+        const auto gs = __builtin_amdgcn_permlane32_swap((uint32_t)G[0], (uint32_t)G[1], false,
+                                                          false);
+        const float w0 = __uint_as_float(ws[0]), w1 = __uint_as_float(ws[1]);
+        const float l0 = __uint_as_float(ls[0]), l1 = __uint_as_float(ls[1]);
+        const float Wc = vmin2(w0, w1);
+        const float Lc = vmin3(vmax2(w0, w1), l0, l1);
+        const int hw = w1 < w0 ? 1 : 0;
+        const int gw = hw ? (int)gs[1] : (int)gs[0];
+        // the point's coordinates: this half's H and the other half's
+        float xp[D];
+#pragma unroll
+        for (int jj = 0; jj < H; ++jj) {
+            const auto xs = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[jj][0]),
+                                                              __float_as_uint(x[jj][1]), false,
+                                                              false);
+            xp[jj] = __uint_as_float(xs[0]);
+            xp[H + jj] = __uint_as_float(xs[1]);
+        }
+        // the winning quad: centres 32 (gw + tile) + 8 quad + 4 hw + 0..3,
+        // keyed as the VALU scan keys them (rows past K: -2^127, never chosen)
+        const uint32_t bits = __float_as_uint(Wc) & 7u;
+        const int base = 32 * (gw + (int)(bits >> 2)) + 8 * (int)(bits & 3u) + 4 * hw;
+        float s4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = base + u;
+            const int kk = k < K ? k : K - 1;
+            float v = ghh[kk];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const float4 m = grow[kk * NB + b];
+                const float mv[4] = {m.x, m.y, m.z, m.w};
+#pragma unroll
+                for (int w2 = 0; w2 < 4; ++w2) {
+                    const int j = 4 * b + w2;
+                    if (j < D) v = fmaf(xp[j], mv[w2], v);
+                }
+            }
+            s4[u] = k < K ? v : -0x1p127f;
+        }
+        const float a3 = fmaxf(fmaxf(s4[0], s4[1]), s4[2]);
+        const float t1 = fmaxf(a3, s4[3]);
+        const float t2 = fmaxf(__builtin_amdgcn_fmed3f(s4[0], s4[1], s4[2]), fminf(a3, s4[3]));
+        int kq = 3;
+        kq = s4[2] == t1 ? 2 : kq;
+        kq = s4[1] == t1 ? 1 : kq;
+        kq = s4[0] == t1 ? 0 : kq;
+        const int k = base + kq;
+        float mag = wb.hmax, xx = 0.0f;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const float a = j < d ? amax[j] : 0.0f;
+            mag = fmaf(a, fabsf(xp[j]), mag);
+            xx = fmaf(xp[j], xp[j], xx);
+        }
+        const float gap = t1 - t2;
+        const float bound = fmaf(wb.kc, mag, wb.dc * (xx + 2.0f * fabsf(t1) + fabsf(gap)));
+        const float thr = fmaf(fmaf(kcm, mag, wb.dc * (xx + 2.0f * fabsf(t1))), s2, habs);
+        const int64_t i = i0 + h;
+        const bool valid = 2 * c + h < rem;
+        const bool ok = mok && Lc - Wc > thr && gap > bound && k < K;
+        if (valid && ok) sink(xp, i, k, wide_direct<D>(xp, grow + k * NB));
+        q.push(valid && !ok, i);
+        (void)DS;
+    }
+    if (q.qn > 0) q.drain(q.qn);
+}
+
 // Key tables of the float32 centres mu32 (K rows of stride DS): hh[k] =
 // -fl32(sum_j m_kj^2) / 2 (the sum of squares in float64 FMAs, rounded
 // once), pads up to a whole triple -2^127; amax[j] = max_k |m_kj| (j < d),
@@ -543,6 +866,70 @@ __global__ __launch_bounds__(WBLOCK) void wide_scan(WState* __restrict__ st) {
 // is added, times 2^32, to cluster 0's count in its partial row (a block
 // counts at most 2^19 points and a fit at most 2^31 - 1, so the fields never
 // overlap).
+// A point's share of one update in the block's LDS sums: its fixed-point
+// coordinates and a count of one into the coordinate-major slots [j K + k]
+// (the lanes' clusters spread over the LDS banks), its distance into the
+// thread's objective, and with TRACK its label into st->track.
+template <int D, bool TRACK>
+struct LdsSums {
+    unsigned long long* acc;
+    int K, d;
+    double fscale;
+    int32_t* track;
+    double jl = 0.0;
+    uint32_t nchg = 0;
+
+    __device__ __forceinline__ void add(const float (&xr)[D], int64_t i, int k, float dist) {
+        jl += (double)dist;
+        if constexpr (TRACK) {
+            if (track[i] != k) {
+                track[i] = k;
+                ++nchg;
+            }
+        }
+        unsigned long long* a = acc + k;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            if (j < d)
+                __hip_atomic_fetch_add(&a[j * K], fxp_bits(xr[j], fscale), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        __hip_atomic_fetch_add(&a[d * K], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+
+    // After the pass: the block's row of partials -- the sums of q (each
+    // slot less FXP_MAGIC_BITS per point it received, the count of its
+    // cluster) and the counts; with TRACK the block's changed labels added,
+    // times 2^32, to cluster 0's count (a block counts at most 2^19 points
+    // and a fit at most 2^31 - 1, so the fields never overlap) -- and its
+    // objective partial.  q0: the waves' re-scan queues (empty by now, their
+    // first words carry the per-wave counts); sw: NW doubles.  Whole block.
+    __device__ __forceinline__ void publish(WState* __restrict__ st, int* q0, double* sw) {
+        const int tid = threadIdx.x, nacc = K * (d + 1);
+        unsigned long long chg = 0ull;
+        if constexpr (TRACK) {
+            const uint32_t nw = wave_sum_u32(nchg);
+            if ((tid & 63) == 0) q0[(tid >> 6) * WQCAP] = (int)nw;
+            __syncthreads();
+#pragma unroll
+            for (int v = 0; v < NW; ++v) chg += (uint32_t)q0[v * WQCAP];
+        }
+        const double jb = block_sum(jl, sw);  // also orders the LDS atomics before the copy-out
+        unsigned long long* row = st->part + (size_t)blockIdx.x * nacc;
+        for (int i = tid; i < nacc; i += WBLOCK) {
+            const int k = i % K;
+            unsigned long long v = i < d * K ? acc[i] - acc[d * K + k] * FXP_MAGIC_BITS : acc[i];
+            if (TRACK && i == d * K) v += chg << 32;
+            row[i] = v;
+        }
+        if (tid == 0) st->jpart[blockIdx.x] = jb;
+    }
+};
+
+// Reassignment and per-block sums of one update.  TRACK (indicator
+// tracking): each point's previous label is read from st->track and the new
+// one written there where it differs, and the block's number of changed
+// labels travels with the counts (LdsSums::publish).
 template <int D, bool TRACK>
 __device__ __forceinline__ void wide_update_body(WState* __restrict__ st, unsigned char* wsm) {
     using S = WShape<D>;
@@ -553,57 +940,46 @@ __device__ __forceinline__ void wide_update_body(WState* __restrict__ st, unsign
     float* cm = reinterpret_cast<float*>(wsm + (((size_t)nacc * 8 + 15) & ~(size_t)15));
     float* hh = cm + (size_t)kp * S::DS;
     float* amax = hh + ((kp + 3) & ~3);
-    int* wq = reinterpret_cast<int*>(amax + 36) + (tid >> 6) * WQCAP;
-    double* sw = reinterpret_cast<double*>(reinterpret_cast<int*>(amax + 36) + NW * WQCAP);
-    const double fscale = fxp_scale(data_exponent(st->absmax_bits));
+    int* q0 = reinterpret_cast<int*>(amax + 36);
+    int* wq = q0 + (tid >> 6) * WQCAP;
+    double* sw = reinterpret_cast<double*>(q0 + NW * WQCAP);
     stage_tables<D>(st, K, cm, hh, amax);
     for (int i = tid; i < nacc; i += WBLOCK) acc[i] = 0ull;
     __syncthreads();
-    double jl = 0.0;
-    int32_t* __restrict__ track = st->track;
-    uint32_t nchg = 0;
+    LdsSums<D, TRACK> sums{acc, K, d, fxp_scale(data_exponent(st->absmax_bits)), st->track};
     wide_points<D>(st, cm, hh, amax, K, d, wq,
-                   [&](const float (&xr)[D], int64_t i, int k, float dist) {
-        jl += (double)dist;
-        if constexpr (TRACK) {
-            if (track[i] != k) {
-                track[i] = k;
-                ++nchg;
-            }
-        }
-        // coordinate-major slots [j * K + k]: the lanes' clusters spread over
-        // the LDS banks
-        unsigned long long* a = acc + k;
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            if (j < d)
-                __hip_atomic_fetch_add(&a[j * K], fxp_bits(xr[j], fscale), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
-        __hip_atomic_fetch_add(&a[d * K], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    });
-    unsigned long long chg = 0ull;
-    if constexpr (TRACK) {
-        nchg = wave_sum_u32(nchg);
-        // per-wave counts in the first word of each wave's re-scan queue
-        // (empty once the pass is over)
-        int* q0 = reinterpret_cast<int*>(amax + 36);
-        if ((tid & 63) == 0) q0[(tid >> 6) * WQCAP] = (int)nchg;
-        __syncthreads();
-#pragma unroll
-        for (int v = 0; v < NW; ++v) chg += (uint32_t)q0[v * WQCAP];
-    }
-    const double jb = block_sum(jl, sw);  // also orders the LDS atomics before the copy-out
-    // the row: the sums of q (each slot less FXP_MAGIC_BITS per point it
-    // received, the count of its cluster) and the counts
-    unsigned long long* row = st->part + (size_t)blockIdx.x * nacc;
-    for (int i = tid; i < nacc; i += WBLOCK) {
-        const int k = i % K;
-        unsigned long long v = i < d * K ? acc[i] - acc[d * K + k] * FXP_MAGIC_BITS : acc[i];
-        if (TRACK && i == d * K) v += chg << 32;
-        row[i] = v;
-    }
-    if (tid == 0) st->jpart[blockIdx.x] = jb;
+                   [&](const float (&xr)[D], int64_t i, int k, float dist) { sums.add(xr, i, k, dist); });
+    sums.publish(st, q0, sw);
+}
+
+// The same update with the matrix-core keys (widths 8 to 16, wide_mfma_lds_bytes
+// of LDS): the A operands and accumulator inputs of every tile are staged in
+// LDS in place of the float32 centre table.
+template <int D, bool TRACK>
+__device__ __forceinline__ void wide_update_mfma_body(WState* __restrict__ st, unsigned char* wsm) {
+    using M = WMfma<D>;
+    const int tid = threadIdx.x;
+    const int d = st->d, K = st->K, nacc = K * (d + 1);
+    const int KT = (K + 31) / 32;
+    unsigned long long* acc = reinterpret_cast<unsigned long long*>(wsm);
+    u32x4* As = reinterpret_cast<u32x4*>(wsm + (((size_t)nacc * 8 + 63) & ~(size_t)63));
+    float* Cs = reinterpret_cast<float*>(As + (size_t)KT * M::S * 64);
+    float* amax = Cs + KT * 32;
+    int* q0 = reinterpret_cast<int*>(amax + 36);
+    int* wq = q0 + (tid >> 6) * WQCAP;
+    double* sw = reinterpret_cast<double*>(q0 + NW * WQCAP);
+    const int xe = data_exponent(st->absmax_bits);
+    for (int i = tid; i < nacc; i += WBLOCK) acc[i] = 0ull;
+    for (int i = tid; i <= WD_MAX; i += WBLOCK) amax[i] = st->amax[i];
+    __syncthreads();
+    int e = 0;
+    const bool mok = wide_mfma_scale(xe, amax, d, e);
+    if (mok) stage_mfma<D>(st, K, d, e, As, Cs);
+    __syncthreads();
+    LdsSums<D, TRACK> sums{acc, K, d, fxp_scale(xe), st->track};
+    wide_points_mfma<D>(st, As, Cs, amax, K, d, e, mok, wq,
+                        [&](const float (&xr)[D], int64_t i, int k, float dist) { sums.add(xr, i, k, dist); });
+    sums.publish(st, q0, sw);
 }
 
 template <int D>
@@ -619,6 +995,20 @@ __global__ __launch_bounds__(WBLOCK) void wide_update_track(WState* __restrict__
     extern __shared__ __align__(16) unsigned char wsm[];
     if (st->done) return;
     wide_update_body<D, true>(st, wsm);
+}
+
+template <int D>
+__global__ __launch_bounds__(WBLOCK) void wide_update_mfma(WState* __restrict__ st) {
+    extern __shared__ __align__(64) unsigned char wsm[];
+    if (st->done) return;
+    wide_update_mfma_body<D, false>(st, wsm);
+}
+
+template <int D>
+__global__ __launch_bounds__(WBLOCK) void wide_update_mfma_track(WState* __restrict__ st) {
+    extern __shared__ __align__(64) unsigned char wsm[];
+    if (st->done) return;
+    wide_update_mfma_body<D, true>(st, wsm);
 }
 
 // The update for shapes beyond one block's LDS (wide_tiled): the tiled scan,
@@ -892,6 +1282,61 @@ __global__ __launch_bounds__(WBLOCK) void wide_label_tiled(WState* __restrict__ 
     }
 }
 
+// Reassignment only with the matrix-core keys.
+template <int D>
+__global__ __launch_bounds__(WBLOCK) void wide_label_mfma(WState* __restrict__ st,
+                                                          int32_t* __restrict__ labels) {
+    extern __shared__ __align__(64) unsigned char wsm[];
+    __shared__ double sw[64];
+    __shared__ int sflag;
+    using M = WMfma<D>;
+    const int tid = threadIdx.x;
+    const int d = st->d, K = st->K;
+    const int KT = (K + 31) / 32;
+    u32x4* As = reinterpret_cast<u32x4*>(wsm);
+    float* Cs = reinterpret_cast<float*>(As + (size_t)KT * M::S * 64);
+    float* amax = Cs + KT * 32;
+    int* wq = reinterpret_cast<int*>(amax + 36) + (tid >> 6) * WQCAP;
+    for (int i = tid; i <= WD_MAX; i += WBLOCK) amax[i] = st->amax[i];
+    __syncthreads();
+    int e = 0;
+    const bool mok = wide_mfma_scale(data_exponent(st->absmax_bits), amax, d, e);
+    if (mok) stage_mfma<D>(st, K, d, e, As, Cs);
+    __syncthreads();
+    double jl = 0.0;
+    wide_points_mfma<D>(st, As, Cs, amax, K, d, e, mok, wq,
+                        [&](const float (&)[D], int64_t i, int k, float dist) {
+        jl += (double)dist;
+        if (labels) labels[i] = k;
+    });
+    const double jb = block_sum(jl, sw);
+    if (tid == 0) {
+        st_agent(&st->jpart[blockIdx.x], jb);
+        wait_mem();
+        const uint32_t old = __hip_atomic_fetch_add(&st->ticket, 1u, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        sflag = old == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!sflag) return;
+    const int nb = gridDim.x;
+    const double* jp = st->jpart;
+    const double J = ordered_sum(nb, [&](int b) { return ld_agent(&jp[b]); }, sw);
+    if (tid == 0) {
+        st->J = J;
+        st_agent(&st->ticket, 0u);
+    }
+}
+
+// The matrix-core kernels exist for widths 8, 12 and 16.
+#define KM_WIDE_MFMA_DISPATCH(KERN, d, grid, lds, s, ...)                                      \
+    switch (wide_width(d)) {                                                                 \
+        case 8: hipLaunchKernelGGL(KERN<8>, dim3(grid), dim3(WBLOCK), lds, s, __VA_ARGS__); break;   \
+        case 12: hipLaunchKernelGGL(KERN<12>, dim3(grid), dim3(WBLOCK), lds, s, __VA_ARGS__); break; \
+        case 16: hipLaunchKernelGGL(KERN<16>, dim3(grid), dim3(WBLOCK), lds, s, __VA_ARGS__); break; \
+        default: return hipErrorInvalidValue;                                                \
+    }
+
 #define KM_WIDE_DISPATCH(KERN, d, grid, lds, s, ...)                                          \
     switch (wide_width(d)) {                                                                 \
         case 1: hipLaunchKernelGGL(KERN<1>, dim3(grid), dim3(WBLOCK), lds, s, __VA_ARGS__); break;   \
@@ -915,10 +1360,19 @@ hipError_t launch_wide_scan(WState* st, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_wide_update(WState* st, int d, int K, bool track, int grid, hipStream_t s) {
+hipError_t launch_wide_update(WState* st, int d, int K, bool track, bool mfma, int grid,
+                              hipStream_t s) {
     if (grid < 1 || grid > WMAX_GRID || d < 1 || d > WD_MAX || K < 1 || K > WK_MAX)
         return hipErrorInvalidValue;
-    if (wide_tiled(d, K)) {
+    if (mfma) {
+        if (!wide_mfma_fits(d, K)) return hipErrorInvalidValue;
+        const size_t lds = wide_mfma_lds_bytes(d, K);
+        if (track) {
+            KM_WIDE_MFMA_DISPATCH(wide_update_mfma_track, d, grid, lds, s, st)
+        } else {
+            KM_WIDE_MFMA_DISPATCH(wide_update_mfma, d, grid, lds, s, st)
+        }
+    } else if (wide_tiled(d, K)) {
         const size_t lds = wide_tiled_lds_bytes(d);
         if (track) {
             KM_WIDE_DISPATCH(wide_update_tiled_track, d, grid, lds, s, st)
@@ -948,11 +1402,15 @@ hipError_t launch_wide_reduce(WState* st, int d, int K, int grid_update, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_wide_label(WState* st, int32_t* labels, int d, int K, int grid,
+hipError_t launch_wide_label(WState* st, int32_t* labels, int d, int K, bool mfma, int grid,
                              hipStream_t s) {
     if (grid < 1 || grid > WMAX_GRID || d < 1 || d > WD_MAX || K < 1 || K > WK_MAX)
         return hipErrorInvalidValue;
-    if (wide_tiled(d, K)) {
+    if (mfma) {
+        if (!wide_mfma_fits(d, K)) return hipErrorInvalidValue;
+        const size_t lds = wide_mfma_table_bytes(d, K);
+        KM_WIDE_MFMA_DISPATCH(wide_label_mfma, d, grid, lds, s, st, labels)
+    } else if (wide_tiled(d, K)) {
         const size_t lds = wide_tiled_lds_bytes(d);
         KM_WIDE_DISPATCH(wide_label_tiled, d, grid, lds, s, st, labels)
     } else {
@@ -982,8 +1440,21 @@ hipError_t launch_wide_label(WState* st, int32_t* labels, int d, int K, int grid
         return e == hipSuccess ? n : 0;                                                        \
     }
 
-int wide_blocks_per_cu(int d, int K) {
+int wide_blocks_per_cu(int d, int K, bool mfma) {
     const int w = wide_width(d);
+    if (mfma) {
+        if (!wide_mfma_fits(d, K)) return 0;
+        const size_t lds = wide_mfma_lds_bytes(d, K);
+        int n = 0;
+        hipError_t e = hipErrorInvalidValue;
+        switch (w) {
+            case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(wide_update_mfma<8>), WBLOCK, lds); break;
+            case 12: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(wide_update_mfma<12>), WBLOCK, lds); break;
+            case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(wide_update_mfma<16>), WBLOCK, lds); break;
+            default: break;
+        }
+        return e == hipSuccess ? n : 0;
+    }
     if (wide_tiled(d, K)) return KM_WIDE_OCC(wide_update_tiled)(w, wide_tiled_lds_bytes(d));
     return KM_WIDE_OCC(wide_update)(w, wide_lds_bytes(d, K));
 }

@@ -1,8 +1,9 @@
 """The two reassignment scans (keys on the vector ALUs, KM_OPT_KEYS = 1, and
 on the matrix cores, KM_OPT_KEYS = 2) must give identical labels, centres, E
-and T: both certify the exact argmin of the keys of the float32 centres and
-re-scan the rest in the direct form.  Only the objective's float64 summation
-order differs.  (Parity of the default scan, the VALU one, with the oracle is
+and T, in the 2-D/3-D kernels and in the general-shape kernels (widths 8 to
+16): both certify only winners that are the first-index float64 direct-form
+argmin and re-scan the rest in that form.  Only the objective's float64
+summation order differs.  (Parity of the default scans with the oracle is
 covered by the other GPU test files.)"""
 import numpy as np
 import pytest
@@ -134,3 +135,91 @@ def test_scales_identical_across_scans(km, d, xs, ms):
     mism, near, _, _ = label_check(b, X, mu, N)
     log(f"    mismatches vs oracle {mism} (near-ties {near})")
     assert Jb == pytest.approx(Ja, rel=1e-12)
+
+
+# ------------------------------------------------------------ general shapes
+# The general-shape kernels take the matrix-core keys for widths 8 to 16
+# (KM_OPT_KEYS = 0: K >= 64; 2: any K whose operands fit in LDS).
+
+@pytest.mark.parametrize("d,K,N", [
+    (16, 256, 100_003), (8, 100, 60_001), (12, 300, 40_001), (9, 64, 50_000),
+    (13, 128, 30_011), (16, 40, 20_000), (16, 5, 7), (11, 1, 100), (16, 33, 64)])
+def test_general_fit_identical_across_scans(km, d, K, N):
+    log(f"general keys fit d={d} K={K} N={N}")
+    s = datagen.spec("C2", N=N, d=d, K=K, seed=7300 + d + K)
+    X, _ = datagen.generate(s)
+    Xd = torch.from_numpy(X).cuda()
+    mu0 = datagen.init_sample(X, N, K, 3)
+    a, b = both(km, lambda: km.fit(Xd, mu0, tol=1e-6, max_iter=30))
+    assert a.iters == b.iters
+    assert np.array_equal(a.centroids, b.centroids)
+    assert a.E == b.E
+    assert np.array_equal(a.labels.cpu().numpy(), b.labels.cpu().numpy())
+    assert b.objective == pytest.approx(a.objective, rel=1e-9)
+    mism, near, _, _ = label_check(b.labels.cpu().numpy(), X, b.centroids, N)
+    log(f"  T={b.iters} mismatches vs oracle {mism} (near-ties {near})")
+
+
+@pytest.mark.parametrize("d", [8, 16])
+def test_general_ties_identical_across_scans(km, d):
+    """Integer points and half-integer centres: exact ties everywhere, which
+    the matrix-core certificate must reject (the float64 re-scan then takes
+    the lowest index)."""
+    rng = np.random.default_rng(170 + d)
+    N, K = 100_003, 96
+    X = rng.integers(-3, 4, size=(d, N)).astype(np.float32)
+    mu = (rng.integers(-3, 3, size=(K, d)) + 0.5).astype(np.float64)
+    mu[:, : d // 2] = np.round(mu[:, : d // 2])
+    Xd = torch.from_numpy(X).cuda()
+    (la, Ja), (lb, Jb) = both(km, lambda: km.assign(Xd, mu))
+    ref, dmin, dsec = oracle.assign(X, mu)
+    assert (dsec == dmin).mean() > 0.05
+    assert np.array_equal(la.cpu().numpy(), ref)
+    assert np.array_equal(lb.cpu().numpy(), ref)
+    assert Jb == pytest.approx(Ja, rel=1e-12)
+
+
+def test_general_far_points_and_large_offsets(km):
+    rng = np.random.default_rng(180)
+    d, N, K = 16, 120_001, 200
+    X = (rng.normal(size=(d, N)) * 3 + 1000.0).astype(np.float32)
+    X[:, ::97] += 5000.0
+    mu = rng.normal(size=(K, d)) * 3 + 1000.0
+    Xd = torch.from_numpy(X).cuda()
+    (la, _), (lb, _) = both(km, lambda: km.assign(Xd, mu))
+    assert np.array_equal(la.cpu().numpy(), lb.cpu().numpy())
+    mism, near, _, _ = label_check(lb.cpu().numpy(), X, mu, N)
+    log(f"  general far/offset: mismatches vs oracle {mism} (near-ties {near})")
+
+
+@pytest.mark.parametrize("xs,ms", [(1e-15, 1e-15), (1e-3, 1e-3), (1e4, 1e4), (1e15, 1e15),
+                                   (1.0, 1e6), (1e6, 1.0), (1.0, 0.0)])
+def test_general_scales_identical_across_scans(km, xs, ms):
+    """Extreme magnitudes in 12-D (beyond the matrix-core scale's range every
+    point goes to the float64 re-scan; ms = 0: all keys tie)."""
+    rng = np.random.default_rng(190)
+    d, N, K = 12, 30_001, 70
+    X = (rng.normal(size=(d, N)) * xs).astype(np.float32)
+    mu = rng.normal(size=(K, d)) * ms
+    log(f"  general scales data {xs:g} centres {ms:g}")
+    Xd = torch.from_numpy(X).cuda()
+    (la, Ja), (lb, Jb) = both(km, lambda: km.assign(Xd, mu))
+    a, b = la.cpu().numpy(), lb.cpu().numpy()
+    assert np.array_equal(a, b)
+    mism, near, _, _ = label_check(b, X, mu, N)
+    log(f"    mismatches vs oracle {mism} (near-ties {near})")
+    assert Jb == pytest.approx(Ja, rel=1e-12)
+
+
+def test_general_unaligned_rows_identical_across_scans(km):
+    d, N, ld, K = 12, 50_001, 50_003, 80
+    s = datagen.spec("C2", N=N, d=d, K=K, seed=7400)
+    X, _ = datagen.generate(s)
+    buf = torch.zeros(d * ld + 1, dtype=torch.float32, device="cuda")
+    Xu = buf[1:1 + d * ld].view(d, ld)
+    Xu[:, :N] = torch.from_numpy(X).cuda()
+    mu0 = datagen.init_sample(X, N, K, 5)
+    a, b = both(km, lambda: km.fit(Xu, mu0, tol=1e-6, max_iter=20, N=N))
+    assert a.iters == b.iters
+    assert np.array_equal(a.centroids, b.centroids)
+    assert np.array_equal(a.labels.cpu().numpy(), b.labels.cpu().numpy())
