@@ -247,7 +247,7 @@ def wide_variant(d, K, keys):
     if w in (8, 12, 16) and keys != 1 and (keys == 2 or K >= 64):
         kt = (K + 31) // 32
         steps = (3 * (w // 2) + 7) // 8
-        lds = ((8 * K * (d + 1) + 63) & ~63) + kt * steps * 1024 + kt * 128 + 2224
+        lds = ((8 * K * (d + 1) + 63) & ~63) + kt * steps * 1024 + kt * 128 + 4272
         if lds <= 65536:
             return "_mfma"
     return "_tiled" if wide_tiled(d, K) else ""

@@ -19,10 +19,11 @@ SOURCES = ["lloyd_kernels.hip", "batched_kernels.hip", "initnet_kernels.hip", "k
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-result"]
-# Per-source extras.  lloyd_kernels.hip: the matrix-core key scan reads every
-# result register on the VALU, so the results must land in ordinary VGPRs
-# (the accumulation-register form would cost one copy per key).
-EXTRA = {"lloyd_kernels.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+# Per-source extras.  lloyd_kernels.hip, wide_kernels.hip: the matrix-core key
+# scans read every result register on the VALU, so the results must land in
+# ordinary VGPRs (the accumulation-register form would cost one copy per key).
+EXTRA = {"lloyd_kernels.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+         "wide_kernels.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def build(verbose: bool = False) -> str:

@@ -84,10 +84,10 @@ __host__ __device__ constexpr int wide_mfma_steps(int d) {
     return (3 * (wide_width(d) / 2) + 7) / 8;
 }
 // LDS of the reassignment-only kernel: operands, accumulator inputs, bound
-// coefficients, re-scan queues and objective sums.
+// coefficients, the two levels of re-scan queues and objective sums.
 __host__ __device__ constexpr size_t wide_mfma_table_bytes(int d, int K) {
     return (size_t)((K + 31) / 32) * wide_mfma_steps(d) * 1024 + (size_t)((K + 31) / 32) * 128 +
-           36 * 4 + (size_t)(WBLOCK / 64) * WQCAP * 4 + (WBLOCK / 64) * 8;
+           36 * 4 + (size_t)(WBLOCK / 64) * WQCAP * 4 * 2 + (WBLOCK / 64) * 8;
 }
 // LDS of the update kernel: the integer sums and counts first (rounded to 64
 // bytes), then the tables.

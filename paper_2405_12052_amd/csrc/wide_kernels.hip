@@ -295,6 +295,129 @@ struct WQueue {
     }
 };
 
+// Centre rows and key constants in device memory, read through the scalar
+// cache where every lane reads the same address (they do not change while a
+// kernel runs).
+typedef const __attribute__((address_space(4))) float* cfp;
+
+// The re-scan of the points the matrix-core scan leaves uncertified, in two
+// levels.  Its certificate is wider than the VALU scan's (it covers the
+// float32 sum of 3 D products), so most of those points are decided by the
+// VALU keys: level 1 takes 64 queued points, one per lane, keys each against
+// all K centres exactly as the VALU scan does (hh + the FMA chain over the
+// coordinates), keeps the largest key t1 (first index) and the second
+// largest t2, and applies the VALU scan's certificate to them.  The points
+// that fail it (near-ties) go to a second queue, re-scanned 64 at a time in
+// the float64 direct form (first index of the minimum).
+template <int D, typename Sink>
+struct WQueue2 {
+    const float* X;
+    int64_t ld;
+    int d, K;
+    cfp crow;  // K rows of WShape<D>::DS floats
+    cfp hrow;
+    const float* amax;
+    WBound wb;
+    int* wq;   // level 1 (WQCAP entries)
+    int* wq2;  // level 2 (WQCAP entries)
+    Sink& sink;
+    int qn = 0, qn2 = 0;  // queue lengths (the same in every lane)
+
+    __device__ __forceinline__ void load(int64_t i, float (&xr)[D]) const {
+#pragma unroll
+        for (int j = 0; j < D; ++j) xr[j] = j < d ? X[(int64_t)j * ld + i] : 0.0f;
+    }
+
+    __device__ __forceinline__ void drain2(int cnt) {
+        constexpr int NB = WShape<D>::NB;
+        const int lane = threadIdx.x & 63;
+        const float4* rows = (const float4*)crow;
+        __builtin_amdgcn_wave_barrier();
+        if (lane < cnt) {
+            const int64_t i = wq2[qn2 - cnt + lane];
+            float xr[D];
+            load(i, xr);
+            double bq = INFINITY;
+            int bk = 0;
+#pragma unroll 1
+            for (int k = 0; k < K; ++k) {
+                const double dk = wide_direct64<D>(xr, rows + k * NB);
+                if (dk < bq) { bq = dk; bk = k; }
+            }
+            sink(xr, i, bk, wide_direct<D>(xr, rows + bk * NB));
+        }
+        __builtin_amdgcn_wave_barrier();
+        qn2 -= cnt;
+    }
+
+    __device__ __forceinline__ void push2(bool f, int64_t i) {
+        const int lane = threadIdx.x & 63;
+        const uint64_t mq = __ballot(f);
+        if (mq) {
+            if (f) wq2[qn2 + __popcll(mq & ((1ull << lane) - 1ull))] = (int)i;
+            qn2 += __popcll(mq);
+            if (qn2 >= 64) drain2(64);
+        }
+    }
+
+    __device__ __forceinline__ void drain(int cnt) {
+        constexpr int NB = WShape<D>::NB;
+        const int lane = threadIdx.x & 63;
+        __builtin_amdgcn_wave_barrier();
+        bool f = false;
+        int64_t i = 0;
+        if (lane < cnt) {
+            i = wq[qn - cnt + lane];
+            float xr[D];
+            load(i, xr);
+            float t1 = -INFINITY, t2 = -INFINITY;
+            int k1 = 0;
+#pragma unroll 2
+            for (int k = 0; k < K; ++k) {
+                float v = hrow[k];
+#pragma unroll
+                for (int j = 0; j < D; ++j) v = fmaf(xr[j], crow[k * (4 * NB) + j], v);
+                t2 = fmaxf(t2, fminf(t1, v));
+                k1 = v > t1 ? k : k1;
+                t1 = fmaxf(t1, v);
+            }
+            float mag = wb.hmax, xx = 0.0f;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const float a = j < d ? amax[j] : 0.0f;
+                mag = fmaf(a, fabsf(xr[j]), mag);
+                xx = fmaf(xr[j], xr[j], xx);
+            }
+            const float gap = t1 - t2;
+            const float bound = fmaf(wb.kc, mag, wb.dc * (xx + 2.0f * fabsf(t1) + fabsf(gap)));
+            if (gap > bound) {
+                const float4* rows = (const float4*)crow;
+                sink(xr, i, k1, wide_direct<D>(xr, rows + k1 * NB));
+            } else {
+                f = true;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        qn -= cnt;
+        push2(f, i);
+    }
+
+    __device__ __forceinline__ void push(bool f, int64_t i) {
+        const int lane = threadIdx.x & 63;
+        const uint64_t mq = __ballot(f);
+        if (mq) {
+            if (f) wq[qn + __popcll(mq & ((1ull << lane) - 1ull))] = (int)i;
+            qn += __popcll(mq);
+            if (qn >= 64) drain(64);
+        }
+    }
+
+    __device__ __forceinline__ void finish() {
+        if (qn > 0) drain(qn);
+        if (qn2 > 0) drain2(qn2);
+    }
+};
+
 // Reassignment of this thread's grid-stride share of the points against the
 // K centres cm (LDS, Kpad rows of stride DS, zero padded) with the key
 // constants hh and the bound coefficients amax (see the file header).
@@ -565,7 +688,7 @@ template <int D, typename Sink>
 __device__ __forceinline__ void wide_points_mfma(const WState* __restrict__ st, const u32x4* As,
                                                  const float* Cs, const float* amax, int K,
                                                  int d, int e, bool mok, int* __restrict__ wq,
-                                                 Sink&& sink) {
+                                                 int* __restrict__ wq2, Sink&& sink) {
     using M = WMfma<D>;
     constexpr int H = M::H, S = M::S, NB = WShape<D>::NB, DS = WShape<D>::DS;
     const int lane = threadIdx.x & 63;
@@ -582,7 +705,8 @@ __device__ __forceinline__ void wide_points_mfma(const WState* __restrict__ st, 
     const float s2 = ldexpf(1.0f, 2 * e);
     const float kcm = 2.0f * (3.0f * D + 13.05f) * 0x1.004p-23f;
     const float habs = 5.0f * D;
-    WQueue<D, Sink> q{X, ld, d, K, grow, wq, sink};
+    WQueue2<D, Sink> q{X, ld, d, K, (cfp)st->mu32, (cfp)ghh,
+                       amax, wb, wq, wq2, sink};
 
     const int64_t nchunks = (N + 63) / 64;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -591,23 +715,28 @@ __device__ __forceinline__ void wide_points_mfma(const WState* __restrict__ st, 
         const int64_t i0 = ch * 64 + 2 * c;  // this lane's two points
         const int rem = N - ch * 64 < 64 ? (int)(N - ch * 64) : 64;
         // this half's coordinates h H .. h H + H - 1 of points i0, i0 + 1
+        // (one branch for all of them: 64-bit loads of both points, or
+        // guarded 32-bit loads at the end of the data or on unaligned rows)
         float x[H][2];
+        const float* xrow = X + (int64_t)(h * H) * ld + i0;
+        if (vec && i0 + 2 <= N) {
 #pragma unroll
-        for (int jj = 0; jj < H; ++jj) {
-            const int j = h * H + jj;
-            if (j < d) {
-                const float* row = X + (int64_t)j * ld + i0;
-                if (vec && i0 + 2 <= N) {
-                    const float2 v = *reinterpret_cast<const float2*>(row);
+            for (int jj = 0; jj < H; ++jj) {
+                if (h * H + jj < d) {
+                    const float2 v = *reinterpret_cast<const float2*>(xrow + (int64_t)jj * ld);
                     x[jj][0] = v.x;
                     x[jj][1] = v.y;
                 } else {
-                    x[jj][0] = i0 < N ? row[0] : 0.0f;
-                    x[jj][1] = i0 + 1 < N ? row[1] : 0.0f;
+                    x[jj][0] = 0.0f;
+                    x[jj][1] = 0.0f;
                 }
-            } else {
-                x[jj][0] = 0.0f;
-                x[jj][1] = 0.0f;
+            }
+        } else {
+#pragma unroll
+            for (int jj = 0; jj < H; ++jj) {
+                const bool in = h * H + jj < d;
+                x[jj][0] = in && i0 < N ? xrow[(int64_t)jj * ld] : 0.0f;
+                x[jj][1] = in && i0 + 1 < N ? xrow[(int64_t)jj * ld + 1] : 0.0f;
             }
         }
         float W[2] = {0.0f, 0.0f}, L[2] = {0.0f, 0.0f};
@@ -731,7 +860,7 @@ __device__ __forceinline__ void wide_points_mfma(const WState* __restrict__ st, 
         q.push(valid && !ok, i);
         (void)DS;
     }
-    if (q.qn > 0) q.drain(q.qn);
+    q.finish();
 }
 
 // Key tables of the float32 centres mu32 (K rows of stride DS): hh[k] =
@@ -954,12 +1083,13 @@ __device__ __forceinline__ void wide_update_body(WState* __restrict__ st, unsign
 
 // The same update with the matrix-core keys (widths 8 to 16, wide_mfma_lds_bytes
 // of LDS): the A operands and accumulator inputs of every tile are staged in
-// LDS in place of the float32 centre table.
-template <int D, bool TRACK>
+// LDS in place of the float32 centre table.  FULL: d equals the width D, so
+// that every per-coordinate test folds away at compile time.
+template <int D, bool TRACK, bool FULL>
 __device__ __forceinline__ void wide_update_mfma_body(WState* __restrict__ st, unsigned char* wsm) {
     using M = WMfma<D>;
     const int tid = threadIdx.x;
-    const int d = st->d, K = st->K, nacc = K * (d + 1);
+    const int d = FULL ? D : st->d, K = st->K, nacc = K * (d + 1);
     const int KT = (K + 31) / 32;
     unsigned long long* acc = reinterpret_cast<unsigned long long*>(wsm);
     u32x4* As = reinterpret_cast<u32x4*>(wsm + (((size_t)nacc * 8 + 63) & ~(size_t)63));
@@ -967,7 +1097,8 @@ __device__ __forceinline__ void wide_update_mfma_body(WState* __restrict__ st, u
     float* amax = Cs + KT * 32;
     int* q0 = reinterpret_cast<int*>(amax + 36);
     int* wq = q0 + (tid >> 6) * WQCAP;
-    double* sw = reinterpret_cast<double*>(q0 + NW * WQCAP);
+    int* wq2 = q0 + (NW + (tid >> 6)) * WQCAP;
+    double* sw = reinterpret_cast<double*>(q0 + 2 * NW * WQCAP);
     const int xe = data_exponent(st->absmax_bits);
     for (int i = tid; i < nacc; i += WBLOCK) acc[i] = 0ull;
     for (int i = tid; i <= WD_MAX; i += WBLOCK) amax[i] = st->amax[i];
@@ -977,7 +1108,7 @@ __device__ __forceinline__ void wide_update_mfma_body(WState* __restrict__ st, u
     if (mok) stage_mfma<D>(st, K, d, e, As, Cs);
     __syncthreads();
     LdsSums<D, TRACK> sums{acc, K, d, fxp_scale(xe), st->track};
-    wide_points_mfma<D>(st, As, Cs, amax, K, d, e, mok, wq,
+    wide_points_mfma<D>(st, As, Cs, amax, K, d, e, mok, wq, wq2,
                         [&](const float (&xr)[D], int64_t i, int k, float dist) { sums.add(xr, i, k, dist); });
     sums.publish(st, q0, sw);
 }
@@ -997,18 +1128,21 @@ __global__ __launch_bounds__(WBLOCK) void wide_update_track(WState* __restrict__
     wide_update_body<D, true>(st, wsm);
 }
 
-template <int D>
-__global__ __launch_bounds__(WBLOCK) void wide_update_mfma(WState* __restrict__ st) {
+// Widths 12 and 16 run 2 waves per SIMD (LDS allows no more at K = 256): the
+// compiler may then use 256 registers per lane and keeps the matrix-core
+// results out of the accumulation registers.
+template <int D, bool FULL>
+__global__ __launch_bounds__(WBLOCK) __attribute__((amdgpu_waves_per_eu(1, D >= 12 ? 2 : 4))) void wide_update_mfma(WState* __restrict__ st) {
     extern __shared__ __align__(64) unsigned char wsm[];
     if (st->done) return;
-    wide_update_mfma_body<D, false>(st, wsm);
+    wide_update_mfma_body<D, false, FULL>(st, wsm);
 }
 
-template <int D>
-__global__ __launch_bounds__(WBLOCK) void wide_update_mfma_track(WState* __restrict__ st) {
+template <int D, bool FULL>
+__global__ __launch_bounds__(WBLOCK) __attribute__((amdgpu_waves_per_eu(1, D >= 12 ? 2 : 4))) void wide_update_mfma_track(WState* __restrict__ st) {
     extern __shared__ __align__(64) unsigned char wsm[];
     if (st->done) return;
-    wide_update_mfma_body<D, true>(st, wsm);
+    wide_update_mfma_body<D, true, FULL>(st, wsm);
 }
 
 // The update for shapes beyond one block's LDS (wide_tiled): the tiled scan,
@@ -1283,20 +1417,21 @@ __global__ __launch_bounds__(WBLOCK) void wide_label_tiled(WState* __restrict__ 
 }
 
 // Reassignment only with the matrix-core keys.
-template <int D>
-__global__ __launch_bounds__(WBLOCK) void wide_label_mfma(WState* __restrict__ st,
+template <int D, bool FULL>
+__global__ __launch_bounds__(WBLOCK) __attribute__((amdgpu_waves_per_eu(1, D >= 12 ? 2 : 4))) void wide_label_mfma(WState* __restrict__ st,
                                                           int32_t* __restrict__ labels) {
     extern __shared__ __align__(64) unsigned char wsm[];
     __shared__ double sw[64];
     __shared__ int sflag;
     using M = WMfma<D>;
     const int tid = threadIdx.x;
-    const int d = st->d, K = st->K;
+    const int d = FULL ? D : st->d, K = st->K;
     const int KT = (K + 31) / 32;
     u32x4* As = reinterpret_cast<u32x4*>(wsm);
     float* Cs = reinterpret_cast<float*>(As + (size_t)KT * M::S * 64);
     float* amax = Cs + KT * 32;
     int* wq = reinterpret_cast<int*>(amax + 36) + (tid >> 6) * WQCAP;
+    int* wq2 = reinterpret_cast<int*>(amax + 36) + (NW + (tid >> 6)) * WQCAP;
     for (int i = tid; i <= WD_MAX; i += WBLOCK) amax[i] = st->amax[i];
     __syncthreads();
     int e = 0;
@@ -1304,7 +1439,7 @@ __global__ __launch_bounds__(WBLOCK) void wide_label_mfma(WState* __restrict__ s
     if (mok) stage_mfma<D>(st, K, d, e, As, Cs);
     __syncthreads();
     double jl = 0.0;
-    wide_points_mfma<D>(st, As, Cs, amax, K, d, e, mok, wq,
+    wide_points_mfma<D>(st, As, Cs, amax, K, d, e, mok, wq, wq2,
                         [&](const float (&)[D], int64_t i, int k, float dist) {
         jl += (double)dist;
         if (labels) labels[i] = k;
@@ -1329,11 +1464,16 @@ __global__ __launch_bounds__(WBLOCK) void wide_label_mfma(WState* __restrict__ s
 }
 
 // The matrix-core kernels exist for widths 8, 12 and 16.
+// The matrix-core kernels exist for widths 8, 12 and 16, each for d equal to
+// the width (FULL) and for narrower d.
 #define KM_WIDE_MFMA_DISPATCH(KERN, d, grid, lds, s, ...)                                      \
-    switch (wide_width(d)) {                                                                 \
-        case 8: hipLaunchKernelGGL(KERN<8>, dim3(grid), dim3(WBLOCK), lds, s, __VA_ARGS__); break;   \
-        case 12: hipLaunchKernelGGL(KERN<12>, dim3(grid), dim3(WBLOCK), lds, s, __VA_ARGS__); break; \
-        case 16: hipLaunchKernelGGL(KERN<16>, dim3(grid), dim3(WBLOCK), lds, s, __VA_ARGS__); break; \
+    switch (2 * wide_width(d) + (wide_width(d) == (d) ? 1 : 0)) {                             \
+        case 16: hipLaunchKernelGGL((KERN<8, false>), dim3(grid), dim3(WBLOCK), lds, s, __VA_ARGS__); break;  \
+        case 17: hipLaunchKernelGGL((KERN<8, true>), dim3(grid), dim3(WBLOCK), lds, s, __VA_ARGS__); break;   \
+        case 24: hipLaunchKernelGGL((KERN<12, false>), dim3(grid), dim3(WBLOCK), lds, s, __VA_ARGS__); break; \
+        case 25: hipLaunchKernelGGL((KERN<12, true>), dim3(grid), dim3(WBLOCK), lds, s, __VA_ARGS__); break;  \
+        case 32: hipLaunchKernelGGL((KERN<16, false>), dim3(grid), dim3(WBLOCK), lds, s, __VA_ARGS__); break; \
+        case 33: hipLaunchKernelGGL((KERN<16, true>), dim3(grid), dim3(WBLOCK), lds, s, __VA_ARGS__); break;  \
         default: return hipErrorInvalidValue;                                                \
     }
 
@@ -1448,9 +1588,9 @@ int wide_blocks_per_cu(int d, int K, bool mfma) {
         int n = 0;
         hipError_t e = hipErrorInvalidValue;
         switch (w) {
-            case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(wide_update_mfma<8>), WBLOCK, lds); break;
-            case 12: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(wide_update_mfma<12>), WBLOCK, lds); break;
-            case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(wide_update_mfma<16>), WBLOCK, lds); break;
+            case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(wide_update_mfma<8, false>), WBLOCK, lds); break;
+            case 12: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(wide_update_mfma<12, false>), WBLOCK, lds); break;
+            case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(wide_update_mfma<16, false>), WBLOCK, lds); break;
             default: break;
         }
         return e == hipSuccess ? n : 0;
