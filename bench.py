@@ -22,6 +22,7 @@ sys.path.insert(0, ROOT)
 
 # Published MI355X peaks used for the roofline.
 PEAK_FP32_TFLOPS = 157.3   # FP32 vector (packed FMA = 2 flop per lane)
+PEAK_FP16_MFMA_TFLOPS = 2500.0  # dense fp16 matrix cores
 PEAK_HBM_GBS = 8000.0
 
 
@@ -177,7 +178,7 @@ def bench_wide(args):
     import datagen
     from paper_2405_12052_amd import KM_OPT_KEYS, KM_OPT_TIMING, KMeans
 
-    over = {k: v for k, v in (("N", args.N), ("K", args.K)) if v is not None}
+    over = {k: v for k, v in (("N", args.N), ("K", args.K), ("d", args.d)) if v is not None}
     s = datagen.spec("W1", **over)
     iters = s.max_iter
     t0 = time.time()
@@ -210,10 +211,15 @@ def bench_wide(args):
     achieved = flops / per_update_s / 1e12
     peaks = km.measure_peaks()
     fma_peak = 2.0 * peaks["fma_lane_ops_per_s"] / 1e12
-    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-            "kernel": f"wide_update{wide_variant(s.d, s.K, args.keys)}<{s.d}> + "
-                      f"wide_reduce (one update)",
+    variant = wide_variant(s.d, s.K, args.keys)
+    # the contraction on the matrix cores is priced at their fp16 peak (the
+    # algorithmic flops count each of the d K multiply-adds once, the kernel
+    # performs three fp16 products for each); otherwise the FP32 vector peak
+    peak = PEAK_FP16_MFMA_TFLOPS if variant == "_mfma" else PEAK_FP32_TFLOPS
+    roof = {"bound": "mfma" if variant == "_mfma" else "alu", "achieved": achieved, "peak": peak,
+            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+            "frac_of_fp32_vector_peak": achieved / PEAK_FP32_TFLOPS,
+            "kernel": f"wide_update{variant}<{s.d}> + wide_reduce (one update)",
             "avg_update_us": per_update_s * 1e6, "alg_flops_per_update": flops,
             "alg_bytes_per_update": alg_bytes_per_point(s.d) * s.N,
             "frac_of_measured_nonpacked_fma_peak": achieved / fma_peak}
@@ -524,6 +530,8 @@ def main():
     ap.add_argument("--K", type=int, default=None,
                     help="default workload only: K centres seeded from the same K=64 mixture "
                          "(testing only)")
+    ap.add_argument("--d", type=int, default=None,
+                    help="--workload wide only: dimension of the points (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-converge", action="store_true",
                     help="default workload: skip the run to E < 1e-6 and the learned-vs-plain "

@@ -115,14 +115,19 @@ enum km_option {
     KM_OPT_TIMING = 4,    /* 1: time the iteration launches with HIP events
                              (see kmeans_get_timing)                           */
     KM_OPT_KEYS = 5,      /* how the reassignment scan forms its keys
-                             |m|^2 - 2 m.x: 0 (default) automatic (matrix
-                             cores for 24 < K <= 32 and K > 44, the vector
-                             ALUs otherwise), 1 vector ALUs, 2 matrix cores
-                             (one fp16 MFMA per 32 x 32 keys on hi/lo pieces
-                             of the operands; data or centres beyond about
-                             2^36 or below 2^-48 in magnitude take the vector
-                             ALUs).  Labels, centres, E and T do not depend
-                             on it.                                             */
+                             |m|^2 - 2 m.x: 0 (default) automatic, 1 vector
+                             ALUs, 2 matrix cores (fp16 MFMA on hi/lo pieces
+                             of the operands).  Automatic: in the 2-D/3-D
+                             kernels the matrix cores for 24 < K <= 32 and
+                             K > 44 (data or centres beyond about 2^36 or
+                             below 2^-48 in magnitude take the vector ALUs);
+                             in the general-shape kernels the matrix cores for
+                             padded widths 8, 12 and 16 (7 <= d <= 16) with
+                             K >= 64 whose operand tables fit in 64 KB of LDS
+                             (at d = 16: K <= 256), with 2 the same shapes at
+                             any K (beyond the scale range every point takes
+                             the float64 re-scan).  Labels, centres, E and T
+                             do not depend on it.                               */
     KM_OPT_PERSIST = 6,   /* how kmeans_fit runs its updates: 0 (default)
                              and 1: graph replays of one launch per update
                              (measured as fast or faster at every size); 2:
