@@ -128,9 +128,17 @@ def bench_batched(args):
         inst.append((dev[off:off + s.d * ld].view(s.d, ld), s.N, ini))
     km = KMeans(0)
     t0 = time.time()
-    sched = km.tune_batched(inst, tol=1e-6, max_iter=300,
-                            cache_path=os.environ.get("KMEANS_TUNE_CACHE"))
-    log(f"tuned on the {len(inst)} instances in {time.time() - t0:.1f}s: {sched}")
+    if args.schedule:
+        # a fixed schedule (A/B timing of kernel changes): team size, blocks per
+        # compute unit, work threshold of the teams
+        ts, bpc, bw = args.schedule.split(",")
+        km.set_batched_schedule(int(ts), int(bpc), float(bw))
+        sched = km.batched_schedule()
+        log(f"fixed schedule: {sched}")
+    else:
+        sched = km.tune_batched(inst, tol=1e-6, max_iter=300,
+                                cache_path=os.environ.get("KMEANS_TUNE_CACHE"))
+        log(f"tuned on the {len(inst)} instances in {time.time() - t0:.1f}s: {sched}")
     for i in range(args.warmup):
         km.fit_batched(inst, tol=1e-6, max_iter=300)
     torch.cuda.synchronize()
@@ -550,6 +558,8 @@ def main():
     ap.add_argument("--instances", type=int, default=None,
                     help="instances (batched: 4096, learned: 100)")
     ap.add_argument("--repeats", type=int, default=3)
+    ap.add_argument("--schedule", default=None, metavar="TEAM,BLOCKS_PER_CU,BIG_WORK",
+                    help="--workload batched: use this schedule instead of the autotuner's")
     ap.add_argument("--weights", default=None, help="learned initialiser weights (.npy)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="before the workload, copy a device buffer of BYTES twice (a plain "
