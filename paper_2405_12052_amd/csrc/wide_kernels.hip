@@ -578,6 +578,9 @@ __device__ __forceinline__ void wide_points_tiled(const WState* __restrict__ st,
 // first-index float64 direct-form argmin.  Other points go to the float64
 // re-scan.  Scales outside e in [-24, 60] (data or centres beyond about
 // 2^36 or below 2^-48) send every point to the re-scan.
+// Points per lane of the matrix-core scan's wave iteration.
+constexpr int WMFMA_PL = 4;
+
 template <int D>
 struct WMfma {
     static constexpr int H = D / 2;            // coordinates per lane half
@@ -681,16 +684,22 @@ __device__ __forceinline__ f32x16 tile_keys(const f16x8 (&A)[S], const f16x8 (&B
 }
 
 // Reassignment with the matrix-core keys (see above) of this wave's share of
-// the grid, 64 points at a time; same contract as wide_points.  As, Cs: the
-// staged operands (stage_mfma); amax: the bound coefficients (LDS); e, mok:
-// the scale and whether it is in range.
-template <int D, typename Sink>
+// the grid, 32 PL points at a time (PL = 2 or 4 per lane: more independent
+// matrix-core chains and loads in flight per wave); same contract as
+// wide_points.  As, Cs: the staged operands (stage_mfma); amax: the bound
+// coefficients (LDS); e, mok: the scale and whether it is in range.  Lane
+// (c, h) loads the coordinates h H .. h H + H - 1 of points PL c .. PL c +
+// PL - 1 of the iteration; chunk p is the 32 points {PL c + p}.  Chunks are
+// merged in pairs (2 q, 2 q + 1), lane half h finishing chunk 2 q + h.
+template <int D, int PL, typename Sink>
 __device__ __forceinline__ void wide_points_mfma(const WState* __restrict__ st, const u32x4* As,
                                                  const float* Cs, const float* amax, int K,
                                                  int d, int e, bool mok, int* __restrict__ wq,
                                                  int* __restrict__ wq2, Sink&& sink) {
+    static_assert(PL == 2 || PL == 4, "2 or 4 points per lane");
     using M = WMfma<D>;
-    constexpr int H = M::H, S = M::S, NB = WShape<D>::NB, DS = WShape<D>::DS;
+    constexpr int H = M::H, S = M::S, NB = WShape<D>::NB;
+    constexpr int PTS = 32 * PL;  // points per wave iteration
     const int lane = threadIdx.x & 63;
     const int c = lane & 31, h = lane >> 5;
     const int64_t N = st->N, ld = st->ld;
@@ -708,57 +717,69 @@ __device__ __forceinline__ void wide_points_mfma(const WState* __restrict__ st, 
     WQueue2<D, Sink> q{X, ld, d, K, (cfp)st->mu32, (cfp)ghh,
                        amax, wb, wq, wq2, sink};
 
-    const int64_t nchunks = (N + 63) / 64;
+    const int64_t nchunks = (N + PTS - 1) / PTS;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int64_t ch = (int64_t)blockIdx.x * NW + wid; ch < nchunks;
          ch += (int64_t)gridDim.x * NW) {
-        const int64_t i0 = ch * 64 + 2 * c;  // this lane's two points
-        const int rem = N - ch * 64 < 64 ? (int)(N - ch * 64) : 64;
-        // this half's coordinates h H .. h H + H - 1 of points i0, i0 + 1
-        // (one branch for all of them: 64-bit loads of both points, or
-        // guarded 32-bit loads at the end of the data or on unaligned rows)
-        float x[H][2];
+        const int64_t i0 = ch * PTS + PL * c;  // this lane's PL points
+        const int rem = N - ch * PTS < PTS ? (int)(N - ch * PTS) : PTS;
+        // this half's coordinates of the lane's points (one branch for all of
+        // them: vector loads, or guarded 32-bit loads at the end of the data
+        // or on unaligned rows)
+        float x[H][PL];
         const float* xrow = X + (int64_t)(h * H) * ld + i0;
-        if (vec && i0 + 2 <= N) {
+        if (vec && i0 + PL <= N) {
 #pragma unroll
             for (int jj = 0; jj < H; ++jj) {
                 if (h * H + jj < d) {
-                    const float2 v = *reinterpret_cast<const float2*>(xrow + (int64_t)jj * ld);
-                    x[jj][0] = v.x;
-                    x[jj][1] = v.y;
+                    if constexpr (PL == 4) {
+                        const float4 v = *reinterpret_cast<const float4*>(xrow + (int64_t)jj * ld);
+                        x[jj][0] = v.x;
+                        x[jj][1] = v.y;
+                        x[jj][2] = v.z;
+                        x[jj][3] = v.w;
+                    } else {
+                        const float2 v = *reinterpret_cast<const float2*>(xrow + (int64_t)jj * ld);
+                        x[jj][0] = v.x;
+                        x[jj][1] = v.y;
+                    }
                 } else {
-                    x[jj][0] = 0.0f;
-                    x[jj][1] = 0.0f;
+#pragma unroll
+                    for (int p = 0; p < PL; ++p) x[jj][p] = 0.0f;
                 }
             }
         } else {
 #pragma unroll
             for (int jj = 0; jj < H; ++jj) {
                 const bool in = h * H + jj < d;
-                x[jj][0] = in && i0 < N ? xrow[(int64_t)jj * ld] : 0.0f;
-                x[jj][1] = in && i0 + 1 < N ? xrow[(int64_t)jj * ld + 1] : 0.0f;
+#pragma unroll
+                for (int p = 0; p < PL; ++p)
+                    x[jj][p] = in && i0 + p < N ? xrow[(int64_t)jj * ld + p] : 0.0f;
             }
         }
-        float W[2] = {0.0f, 0.0f}, L[2] = {0.0f, 0.0f};
-        int G[2] = {0, 0};
-        if (mok) {
-            f16x8 B[2][S];
+        float W[PL], L[PL];
+        int G[PL];
 #pragma unroll
-            for (int p = 0; p < 2; ++p) {
+        for (int p = 0; p < PL; ++p) { W[p] = 0.0f; L[p] = 0.0f; G[p] = 0; }
+        if (mok) {
+            f16x8 B[PL][S];
+#pragma unroll
+            for (int p = 0; p < PL; ++p) {
                 float u[H];
 #pragma unroll
                 for (int jj = 0; jj < H; ++jj) u[jj] = x[jj][p] * sc;
                 point_operand_w<D>(u, B[p]);
+                W[p] = INFINITY;
+                L[p] = INFINITY;
             }
-            W[0] = W[1] = L[0] = L[1] = INFINITY;
             for (int g = 0; g < KT; g += 2) {
-                float pm[2][8];
+                float pm[PL][8];
 #pragma unroll
                 for (int tt = 0; tt < 2; ++tt) {
                     const int t = g + tt;
                     if (tt == 1 && t >= KT) {
 #pragma unroll
-                        for (int p = 0; p < 2; ++p)
+                        for (int p = 0; p < PL; ++p)
 #pragma unroll
                             for (int r = 4; r < 8; ++r) pm[p][r] = INFINITY;
                         break;
@@ -769,14 +790,14 @@ __device__ __forceinline__ void wide_points_mfma(const WState* __restrict__ st, 
                         A[s] = __builtin_bit_cast(f16x8, As[((t * S + s) * 2 + h) * 32 + c]);
                     const f32x16 C = *reinterpret_cast<const f32x16*>(Cs + (t * 2 + h) * 16);
 #pragma unroll
-                    for (int p = 0; p < 2; ++p) {
+                    for (int p = 0; p < PL; ++p) {
                         const f32x16 kk = tile_keys<S>(A, B[p], C);
                         if (tt == 0) tile_minima<0>(kk, ninf, reinterpret_cast<float(&)[4]>(pm[p][0]));
                         else tile_minima<1>(kk, ninf, reinterpret_cast<float(&)[4]>(pm[p][4]));
                     }
                 }
 #pragma unroll
-                for (int p = 0; p < 2; ++p) {
+                for (int p = 0; p < PL; ++p) {
                     float a1, a2, b1, b2;
                     top2_3(pm[p][0], pm[p][1], pm[p][2], a1, a2);
                     top2_3(pm[p][3], pm[p][4], pm[p][5], b1, b2);
@@ -789,76 +810,79 @@ __device__ __forceinline__ void wide_points_mfma(const WState* __restrict__ st, 
                 }
             }
         }
-        // lane half h finishes chunk h (point i0 + h): after each swap, w0
-        // is the h = 0 lane's value for that point, w1 the h = 1 lane's
-        const auto ws = __builtin_amdgcn_permlane32_swap(__float_as_uint(W[0]),
-                                                          __float_as_uint(W[1]), false, false);
-        const auto ls = __builtin_amdgcn_permlane32_swap(__float_as_uint(L[0]),
-                                                          __float_as_uint(L[1]), false, false);
-        const auto gs = __builtin_amdgcn_permlane32_swap((uint32_t)G[0], (uint32_t)G[1], false,
-                                                          false);
-        const float w0 = __uint_as_float(ws[0]), w1 = __uint_as_float(ws[1]);
-        const float l0 = __uint_as_float(ls[0]), l1 = __uint_as_float(ls[1]);
-        const float Wc = vmin2(w0, w1);
-        const float Lc = vmin3(vmax2(w0, w1), l0, l1);
-        const int hw = w1 < w0 ? 1 : 0;
-        const int gw = hw ? (int)gs[1] : (int)gs[0];
-        // the point's coordinates: this half's H and the other half's
-        float xp[D];
 #pragma unroll
-        for (int jj = 0; jj < H; ++jj) {
-            const auto xs = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[jj][0]),
-                                                              __float_as_uint(x[jj][1]), false,
-                                                              false);
-            xp[jj] = __uint_as_float(xs[0]);
-            xp[H + jj] = __uint_as_float(xs[1]);
-        }
-        // the winning quad: centres 32 (gw + tile) + 8 quad + 4 hw + 0..3,
-        // keyed as the VALU scan keys them (rows past K: -2^127, never chosen)
-        const uint32_t bits = __float_as_uint(Wc) & 7u;
-        const int base = 32 * (gw + (int)(bits >> 2)) + 8 * (int)(bits & 3u) + 4 * hw;
-        float s4[4];
+        for (int qq = 0; qq < PL / 2; ++qq) {
+            const int p0 = 2 * qq;
+            // lane half h finishes chunk p0 + h (point i0 + p0 + h): after each
+            // swap, w0 is the h = 0 lane's value for that point, w1 the h = 1 lane's
+            const auto ws = __builtin_amdgcn_permlane32_swap(__float_as_uint(W[p0]),
+                                                              __float_as_uint(W[p0 + 1]), false, false);
+            const auto ls = __builtin_amdgcn_permlane32_swap(__float_as_uint(L[p0]),
+                                                              __float_as_uint(L[p0 + 1]), false, false);
+            const auto gs = __builtin_amdgcn_permlane32_swap((uint32_t)G[p0], (uint32_t)G[p0 + 1],
+                                                              false, false);
+            const float w0 = __uint_as_float(ws[0]), w1 = __uint_as_float(ws[1]);
+            const float l0 = __uint_as_float(ls[0]), l1 = __uint_as_float(ls[1]);
+            const float Wc = vmin2(w0, w1);
+            const float Lc = vmin3(vmax2(w0, w1), l0, l1);
+            const int hw = w1 < w0 ? 1 : 0;
+            const int gw = hw ? (int)gs[1] : (int)gs[0];
+            // the point's coordinates: this half's H and the other half's
+            float xp[D];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int k = base + u;
-            const int kk = k < K ? k : K - 1;
-            float v = ghh[kk];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const float4 m = grow[kk * NB + b];
-                const float mv[4] = {m.x, m.y, m.z, m.w};
-#pragma unroll
-                for (int w2 = 0; w2 < 4; ++w2) {
-                    const int j = 4 * b + w2;
-                    if (j < D) v = fmaf(xp[j], mv[w2], v);
-                }
+            for (int jj = 0; jj < H; ++jj) {
+                const auto xs = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[jj][p0]),
+                                                                  __float_as_uint(x[jj][p0 + 1]),
+                                                                  false, false);
+                xp[jj] = __uint_as_float(xs[0]);
+                xp[H + jj] = __uint_as_float(xs[1]);
             }
-            s4[u] = k < K ? v : -0x1p127f;
-        }
-        const float a3 = fmaxf(fmaxf(s4[0], s4[1]), s4[2]);
-        const float t1 = fmaxf(a3, s4[3]);
-        const float t2 = fmaxf(__builtin_amdgcn_fmed3f(s4[0], s4[1], s4[2]), fminf(a3, s4[3]));
-        int kq = 3;
-        kq = s4[2] == t1 ? 2 : kq;
-        kq = s4[1] == t1 ? 1 : kq;
-        kq = s4[0] == t1 ? 0 : kq;
-        const int k = base + kq;
-        float mag = wb.hmax, xx = 0.0f;
+            // the winning quad: centres 32 (gw + tile) + 8 quad + 4 hw + 0..3,
+            // keyed as the VALU scan keys them (rows past K: -2^127, never chosen)
+            const uint32_t bits = __float_as_uint(Wc) & 7u;
+            const int base = 32 * (gw + (int)(bits >> 2)) + 8 * (int)(bits & 3u) + 4 * hw;
+            float s4[4];
 #pragma unroll
-        for (int j = 0; j < D; ++j) {
-            const float a = j < d ? amax[j] : 0.0f;
-            mag = fmaf(a, fabsf(xp[j]), mag);
-            xx = fmaf(xp[j], xp[j], xx);
+            for (int u = 0; u < 4; ++u) {
+                const int k = base + u;
+                const int kk = k < K ? k : K - 1;
+                float v = ghh[kk];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const float4 m = grow[kk * NB + b];
+                    const float mv[4] = {m.x, m.y, m.z, m.w};
+#pragma unroll
+                    for (int w2 = 0; w2 < 4; ++w2) {
+                        const int j = 4 * b + w2;
+                        if (j < D) v = fmaf(xp[j], mv[w2], v);
+                    }
+                }
+                s4[u] = k < K ? v : -0x1p127f;
+            }
+            const float a3 = fmaxf(fmaxf(s4[0], s4[1]), s4[2]);
+            const float t1 = fmaxf(a3, s4[3]);
+            const float t2 = fmaxf(__builtin_amdgcn_fmed3f(s4[0], s4[1], s4[2]), fminf(a3, s4[3]));
+            int kq = 3;
+            kq = s4[2] == t1 ? 2 : kq;
+            kq = s4[1] == t1 ? 1 : kq;
+            kq = s4[0] == t1 ? 0 : kq;
+            const int k = base + kq;
+            float mag = wb.hmax, xx = 0.0f;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const float a = j < d ? amax[j] : 0.0f;
+                mag = fmaf(a, fabsf(xp[j]), mag);
+                xx = fmaf(xp[j], xp[j], xx);
+            }
+            const float gap = t1 - t2;
+            const float bound = fmaf(wb.kc, mag, wb.dc * (xx + 2.0f * fabsf(t1) + fabsf(gap)));
+            const float thr = fmaf(fmaf(kcm, mag, wb.dc * (xx + 2.0f * fabsf(t1))), s2, habs);
+            const int64_t i = i0 + p0 + h;
+            const bool valid = PL * c + p0 + h < rem;
+            const bool ok = mok && Lc - Wc > thr && gap > bound && k < K;
+            if (valid && ok) sink(xp, i, k, wide_direct<D>(xp, grow + k * NB));
+            q.push(valid && !ok, i);
         }
-        const float gap = t1 - t2;
-        const float bound = fmaf(wb.kc, mag, wb.dc * (xx + 2.0f * fabsf(t1) + fabsf(gap)));
-        const float thr = fmaf(fmaf(kcm, mag, wb.dc * (xx + 2.0f * fabsf(t1))), s2, habs);
-        const int64_t i = i0 + h;
-        const bool valid = 2 * c + h < rem;
-        const bool ok = mok && Lc - Wc > thr && gap > bound && k < K;
-        if (valid && ok) sink(xp, i, k, wide_direct<D>(xp, grow + k * NB));
-        q.push(valid && !ok, i);
-        (void)DS;
     }
     q.finish();
 }
@@ -1108,7 +1132,7 @@ __device__ __forceinline__ void wide_update_mfma_body(WState* __restrict__ st, u
     if (mok) stage_mfma<D>(st, K, d, e, As, Cs);
     __syncthreads();
     LdsSums<D, TRACK> sums{acc, K, d, fxp_scale(xe), st->track};
-    wide_points_mfma<D>(st, As, Cs, amax, K, d, e, mok, wq, wq2,
+    wide_points_mfma<D, WMFMA_PL>(st, As, Cs, amax, K, d, e, mok, wq, wq2,
                         [&](const float (&xr)[D], int64_t i, int k, float dist) { sums.add(xr, i, k, dist); });
     sums.publish(st, q0, sw);
 }
@@ -1439,7 +1463,7 @@ __global__ __launch_bounds__(WBLOCK) __attribute__((amdgpu_waves_per_eu(1, D >= 
     if (mok) stage_mfma<D>(st, K, d, e, As, Cs);
     __syncthreads();
     double jl = 0.0;
-    wide_points_mfma<D>(st, As, Cs, amax, K, d, e, mok, wq, wq2,
+    wide_points_mfma<D, WMFMA_PL>(st, As, Cs, amax, K, d, e, mok, wq, wq2,
                         [&](const float (&)[D], int64_t i, int k, float dist) {
         jl += (double)dist;
         if (labels) labels[i] = k;
