@@ -268,7 +268,7 @@ def test_error_paths(km):
     X = np.random.default_rng(0).normal(size=(3, 1000)).astype(np.float32)
     Xd = torch.from_numpy(X).cuda()
     mu = X[:, :4].T.astype(np.float64)
-    for bad_mu, n, code in [(np.zeros((1025, 3)), 1000, KM_EUNSUPPORTED),
+    for bad_mu, n, code in [(np.zeros((4097, 3)), 1000, KM_EUNSUPPORTED),
                             (np.zeros((11, 3)), 10, KM_EINVAL)]:
         with pytest.raises(KMeansError) as e:
             km.fit(Xd, bad_mu, N=n)
