@@ -79,7 +79,7 @@
 extern "C" {
 #endif
 
-#define KMEANS_ABI_VERSION 1
+#define KMEANS_ABI_VERSION 2
 
 typedef struct kmeans_ctx kmeans_ctx;
 
@@ -296,7 +296,12 @@ typedef struct km_schedule {
     int32_t team_size;          /* blocks that share one large instance (1..16; 1 = no teams) */
     int32_t blocks_per_cu;      /* persistent grid = blocks_per_cu x compute units (capped by
                                    occupancy)                                       */
-    double big_work;            /* instances with N*K*n_restarts >= big_work go to teams */
+    double big_work;            /* work items with N*K*restarts >= big_work go to teams */
+    int32_t restart_group;      /* restart fusion: an instance's restarts run as work items of
+                                   at most restart_group restarts each, every item scanning its
+                                   restarts in one pass over the points (1..8; 0 = all of
+                                   them in one item).  Results do not depend on it.      */
+    int32_t reserved;           /* must be 0                                          */
 } km_schedule;
 
 /*
@@ -323,8 +328,10 @@ int kmeans_get_batched_schedule(kmeans_ctx *ctx, km_schedule *s);
  * (the workload itself, or a sample of it: the end of a launch, when the last
  * large instances run on single blocks, depends on the number of instances
  * per block, so a small sample can mislead) for each candidate schedule (team
- * size 1, 4, 8, 16; teams for the top 30/50/70/90 % of instances by N*K*R;
- * 2-4 blocks per compute unit), keeps the fastest on the context and
+ * size 1, 4, 8, 16; teams for the top 90/70/50/30 % of work items by N*K*R;
+ * 2-4 blocks per compute unit; all restarts fused), then, from the fastest,
+ * restart groups of 4, 2 and 1 where the batch has more restarts per
+ * instance, and keeps the fastest on the context and
  * writes it to *best (may be NULL).  If cache_path is not NULL the result is
  * looked up first and stored afterwards in that JSON file, keyed by a coarse
  * signature of the batch (restarts, d mix, K and N ranges).  Results of the

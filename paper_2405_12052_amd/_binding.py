@@ -48,7 +48,8 @@ class km_instance(C.Structure):
 
 
 class km_schedule(C.Structure):
-    _fields_ = [("team_size", C.c_int32), ("blocks_per_cu", C.c_int32), ("big_work", C.c_double)]
+    _fields_ = [("team_size", C.c_int32), ("blocks_per_cu", C.c_int32), ("big_work", C.c_double),
+                ("restart_group", C.c_int32), ("reserved", C.c_int32)]
 
 
 _lib = None
@@ -279,14 +280,15 @@ class KMeans:
                         "empty_events": r.empty_events})
         return res
 
-    def set_batched_schedule(self, team_size=0, blocks_per_cu=0, big_work=0.0):
-        s = km_schedule(int(team_size), int(blocks_per_cu), float(big_work))
+    def set_batched_schedule(self, team_size=0, blocks_per_cu=0, big_work=0.0, restart_group=0):
+        s = km_schedule(int(team_size), int(blocks_per_cu), float(big_work), int(restart_group), 0)
         self._check(self._lib.kmeans_set_batched_schedule(self._ctx, C.byref(s)))
 
     def batched_schedule(self):
         s = km_schedule()
         self._check(self._lib.kmeans_get_batched_schedule(self._ctx, C.byref(s)))
-        return {"team_size": s.team_size, "blocks_per_cu": s.blocks_per_cu, "big_work": s.big_work}
+        return {"team_size": s.team_size, "blocks_per_cu": s.blocks_per_cu, "big_work": s.big_work,
+                "restart_group": s.restart_group}
 
     def tune_batched(self, instances, tol=1e-6, max_iter=300, cache_path=None):
         """Search the batched schedule on `instances`; keeps the fastest."""
@@ -295,7 +297,8 @@ class KMeans:
         cp = cache_path.encode() if cache_path else None
         self._check(self._lib.kmeans_tune_batched(self._ctx, len(instances), arr, float(tol),
                                                   int(max_iter), cp, C.byref(s)))
-        return {"team_size": s.team_size, "blocks_per_cu": s.blocks_per_cu, "big_work": s.big_work}
+        return {"team_size": s.team_size, "blocks_per_cu": s.blocks_per_cu, "big_work": s.big_work,
+                "restart_group": s.restart_group}
 
     # ------------------------------------------------ learned initialiser
     def _net_args(self, pts, K, params):

@@ -5,6 +5,7 @@
 // cooperative kernel in a capture), result read-back, and the schedule search
 // with its JSON cache.
 #include "ctx.h"
+#include "batched_copy.h"
 
 #include <math.h>
 #include <stdio.h>
@@ -47,6 +48,12 @@ struct BatchedWS {
     double* tjpart = nullptr;
     BTeam* teams = nullptr;
     int32_t* error_h = nullptr;  // pinned copy of BatchState::error
+    // restart groups: labels of the work items after an instance's first
+    // (device), and the table of the copies of kept restarts' labels
+    int32_t* tmp_labels = nullptr;
+    size_t cap_tmp = 0;            // int32 entries of tmp_labels
+    BCopy* copies = nullptr;       // device [cap_inst]
+    BCopy* copies_h = nullptr;     // pinned [cap_inst]
     // graph of {scan, fit} for the current (grid, team size, n_inst) key
     hipGraphExec_t graph = nullptr;
     int g_grid = -1, g_S = -1, g_n = -1;
@@ -59,11 +66,11 @@ void batched_ws_free(BatchedWS* w) {
     if (!w) return;
     if (w->graph) (void)hipGraphExecDestroy(w->graph);
     void* dev[] = {w->bs, w->inst, w->order, w->init, w->absmax, w->out, w->best, w->best_mu,
-                   w->tpart, w->fold, w->tjpart, w->teams};
+                   w->tpart, w->fold, w->tjpart, w->teams, w->tmp_labels, w->copies};
     for (void* p : dev)
         if (p) (void)hipFree(p);
     void* host[] = {w->bs_h, w->inst_h, w->order_h, w->init_h, w->out_h, w->best_h,
-                    w->best_mu_h, w->error_h};
+                    w->best_mu_h, w->error_h, w->copies_h};
     for (void* p : host)
         if (p) (void)hipHostFree(p);
     if (w->ev0) (void)hipEventDestroy(w->ev0);
@@ -100,7 +107,7 @@ void drop_graph(km::BatchedWS* w) {
     w->g_grid = w->g_S = w->g_n = -1;
 }
 
-int ensure_ws(kmeans_ctx* c, int n_inst, size_t n_init, int blocks) {
+int ensure_ws(kmeans_ctx* c, int n_inst, size_t n_init, int blocks, size_t n_tmp) {
     (void)hipSetDevice(c->device);
     if (!c->bws) {
         c->bws = new km::BatchedWS();
@@ -130,6 +137,8 @@ int ensure_ws(kmeans_ctx* c, int n_inst, size_t n_init, int blocks) {
         if (!rc) rc = host_alloc(c, &w->best_h, n);
         if (!rc) rc = dev_alloc(c, &w->best_mu, (size_t)n * km::BK_KMAX * km::DMAX);
         if (!rc) rc = host_alloc(c, &w->best_mu_h, (size_t)n * km::BK_KMAX * km::DMAX);
+        if (!rc) rc = dev_alloc(c, &w->copies, n);
+        if (!rc) rc = host_alloc(c, &w->copies_h, n);
         if (rc) {
             w->cap_inst = 0;
             return rc;
@@ -147,6 +156,16 @@ int ensure_ws(kmeans_ctx* c, int n_inst, size_t n_init, int blocks) {
             return rc;
         }
         w->cap_init = n;
+    }
+    if (n_tmp > w->cap_tmp) {
+        (void)hipStreamSynchronize(c->stream);
+        const size_t n = std::max(n_tmp, (size_t)1 << 20);
+        int rc = dev_alloc(c, &w->tmp_labels, n);
+        if (rc) {
+            w->cap_tmp = 0;
+            return rc;
+        }
+        w->cap_tmp = n;
     }
     if (blocks > w->cap_blocks) {
         (void)hipStreamSynchronize(c->stream);
@@ -206,6 +225,23 @@ km_schedule resolve(kmeans_ctx* c, const km_schedule& s, const std::vector<doubl
     return r;
 }
 
+// One work item of a batched call: restarts [r0, r0 + nr) of instance inst.
+struct Item {
+    int inst, r0, nr;
+};
+
+// The work items of a batch under restart groups of g (0: all of an
+// instance's restarts in one item), instance by instance, restarts in order.
+std::vector<Item> work_items(int32_t n_inst, const km_instance* inst, int g) {
+    std::vector<Item> items;
+    for (int i = 0; i < n_inst; ++i) {
+        const int R = inst[i].n_restarts;
+        const int G = g > 0 ? g : R;
+        for (int r0 = 0; r0 < R; r0 += G) items.push_back({i, r0, std::min(G, R - r0)});
+    }
+    return items;
+}
+
 int run_batched(kmeans_ctx* c, int32_t n_inst, km_instance* inst, double tol, int32_t max_iter,
                 const km_schedule& sched_in, float* ms_out) {
     if (!c) return KM_EINVAL;
@@ -213,13 +249,30 @@ int run_batched(kmeans_ctx* c, int32_t n_inst, km_instance* inst, double tol, in
     if (!inst) return fail(c, KM_EINVAL, "inst is NULL");
     if (!(tol >= 0.0) || !isfinite(tol)) return fail(c, KM_EINVAL, "tol must be finite and >= 0");
     if (max_iter < 1) return fail(c, KM_EINVAL, "max_iter=%d < 1", max_iter);
+    if (sched_in.restart_group < 0 || sched_in.restart_group > km::BK_RMAX)
+        return fail(c, KM_EINVAL, "restart_group out of [0, %d]", km::BK_RMAX);
     size_t n_init = 0;
-    std::vector<double> work(n_inst);
+    std::vector<size_t> init_off(n_inst);
     for (int i = 0; i < n_inst; ++i) {
         int rc = validate_instance(c, i, inst[i]);
         if (rc) return rc;
+        init_off[i] = n_init;
         n_init += (size_t)inst[i].n_restarts * inst[i].K * inst[i].d;
-        work[i] = (double)inst[i].N * inst[i].K * inst[i].n_restarts;
+    }
+    // the work items: every restart group of every instance is scheduled as
+    // an instance of its own by the kernel (same X, its own restarts)
+    const std::vector<Item> items = work_items(n_inst, inst, sched_in.restart_group);
+    const int n_items = (int)items.size();
+    std::vector<double> work(n_items);
+    size_t n_tmp = 0;
+    std::vector<size_t> tmp_off(n_items, 0);
+    for (int j = 0; j < n_items; ++j) {
+        const km_instance& in = inst[items[j].inst];
+        work[j] = (double)in.N * in.K * items[j].nr;
+        if (items[j].r0 > 0 && in.labels_out) {
+            tmp_off[j] = n_tmp;
+            n_tmp += (size_t)in.N;
+        }
     }
     KM_HIP(c, hipSetDevice(c->device));
     const km_schedule sch = resolve(c, sched_in, work);
@@ -228,30 +281,31 @@ int run_batched(kmeans_ctx* c, int32_t n_inst, km_instance* inst, double tol, in
     const int bpc = std::min(sch.blocks_per_cu, occ);
     const int grid = bpc * c->n_cu;
     const int S = sch.team_size;
-    int rc = ensure_ws(c, n_inst, n_init, grid);
+    int rc = ensure_ws(c, n_items, n_init, grid, n_tmp);
     if (rc) return rc;
     km::BatchedWS* w = c->bws;
 
-    // descriptors, initial centres, and the two work lists (largest first)
-    size_t off = 0;
+    // initial centres, item descriptors, and the two work lists (largest first)
+    for (int i = 0; i < n_inst; ++i)
+        memcpy(w->init_h + init_off[i], inst[i].init,
+               sizeof(double) * (size_t)inst[i].n_restarts * inst[i].K * inst[i].d);
     std::vector<int32_t> big, small;
-    for (int i = 0; i < n_inst; ++i) {
-        const km_instance& in = inst[i];
-        BInst& b = w->inst_h[i];
+    for (int j = 0; j < n_items; ++j) {
+        const km_instance& in = inst[items[j].inst];
+        BInst& b = w->inst_h[j];
         b.X = in.X;
         b.N = in.N;
         b.ld = in.ld;
         b.d = in.d;
         b.K = in.K;
-        b.R = in.n_restarts;
+        b.R = items[j].nr;
         b.vec = ((reinterpret_cast<uintptr_t>(in.X) & 15u) == 0 && (in.ld & 3) == 0) ? 1 : 0;
-        b.labels = in.labels_out;
-        const size_t n = (size_t)in.n_restarts * in.K * in.d;
-        memcpy(w->init_h + off, in.init, sizeof(double) * n);
-        b.init = w->init + off;
-        off += n;
-        (S > 1 && work[i] >= sch.big_work ? big : small).push_back(i);
+        b.labels = !in.labels_out ? nullptr
+                                  : (items[j].r0 == 0 ? in.labels_out : w->tmp_labels + tmp_off[j]);
+        b.init = w->init + init_off[items[j].inst] + (size_t)items[j].r0 * in.K * in.d;
+        (S > 1 && work[j] >= sch.big_work ? big : small).push_back(j);
     }
+    const size_t off = n_init;
     auto larger = [&](int32_t a, int32_t b) { return work[a] > work[b] || (work[a] == work[b] && a < b); };
     std::sort(big.begin(), big.end(), larger);
     std::sort(small.begin(), small.end(), larger);
@@ -264,17 +318,17 @@ int run_batched(kmeans_ctx* c, int32_t n_inst, km_instance* inst, double tol, in
     h->inst = w->inst;
     h->order_big = w->order;
     h->order_small = w->order + big.size();
-    h->n_inst = n_inst;
+    h->n_inst = n_items;
     h->n_big = n_teams ? (int32_t)big.size() : 0;
     h->n_small = (int32_t)small.size();
     if (!n_teams && !big.empty()) {
-        // no teams: every instance goes through the single-block list
-        std::vector<int32_t> all(n_inst);
+        // no teams: every item goes through the single-block list
+        std::vector<int32_t> all(n_items);
         std::iota(all.begin(), all.end(), 0);
         std::sort(all.begin(), all.end(), larger);
         std::copy(all.begin(), all.end(), w->order_h);
         h->order_small = w->order;
-        h->n_small = n_inst;
+        h->n_small = n_items;
     }
     h->team_size = n_teams ? S : 1;
     h->n_teams = n_teams;
@@ -290,21 +344,21 @@ int run_batched(kmeans_ctx* c, int32_t n_inst, km_instance* inst, double tol, in
     h->tjpart = w->tjpart;
     h->teams = w->teams;
 
-    KM_HIP(c, hipMemcpyAsync(w->inst, w->inst_h, sizeof(BInst) * n_inst, hipMemcpyHostToDevice, c->stream));
-    KM_HIP(c, hipMemcpyAsync(w->order, w->order_h, sizeof(int32_t) * n_inst, hipMemcpyHostToDevice, c->stream));
+    KM_HIP(c, hipMemcpyAsync(w->inst, w->inst_h, sizeof(BInst) * n_items, hipMemcpyHostToDevice, c->stream));
+    KM_HIP(c, hipMemcpyAsync(w->order, w->order_h, sizeof(int32_t) * n_items, hipMemcpyHostToDevice, c->stream));
     KM_HIP(c, hipMemcpyAsync(w->init, w->init_h, sizeof(double) * off, hipMemcpyHostToDevice, c->stream));
     KM_HIP(c, hipMemcpyAsync(w->bs, h, sizeof(BatchState), hipMemcpyHostToDevice, c->stream));
 
     // {scan, persistent fit}: one graph per (grid, team size, n_inst)
-    const int scan_grid = std::min(n_inst, 4 * c->n_cu);
+    const int scan_grid = std::min(n_items, 4 * c->n_cu);
     KM_HIP(c, hipEventRecord(w->ev0, c->stream));
     bool launched = false;
     if (c->use_graph && w->coop_capture_ok) {
-        if (!w->graph || w->g_grid != grid || w->g_S != h->team_size || w->g_n != n_inst) {
+        if (!w->graph || w->g_grid != grid || w->g_S != h->team_size || w->g_n != n_items) {
             drop_graph(w);
             hipGraph_t g = nullptr;
             KM_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-            hipError_t e1 = km::launch_batched_scan(w->bs, n_inst, scan_grid, c->cap_stream);
+            hipError_t e1 = km::launch_batched_scan(w->bs, n_items, scan_grid, c->cap_stream);
             hipError_t e2 = e1 == hipSuccess ? km::launch_batched_fit(w->bs, grid, c->cap_stream, true)
                                              : e1;
             hipError_t e3 = hipStreamEndCapture(c->cap_stream, &g);
@@ -314,7 +368,7 @@ int run_batched(kmeans_ctx* c, int32_t n_inst, km_instance* inst, double tol, in
                     w->graph = ex;
                     w->g_grid = grid;
                     w->g_S = h->team_size;
-                    w->g_n = n_inst;
+                    w->g_n = n_items;
                 }
             }
             if (g) (void)hipGraphDestroy(g);
@@ -329,13 +383,13 @@ int run_batched(kmeans_ctx* c, int32_t n_inst, km_instance* inst, double tol, in
         }
     }
     if (!launched) {
-        KM_HIP(c, km::launch_batched_scan(w->bs, n_inst, scan_grid, c->stream));
+        KM_HIP(c, km::launch_batched_scan(w->bs, n_items, scan_grid, c->stream));
         KM_HIP(c, km::launch_batched_fit(w->bs, grid, c->stream, true));
     }
     KM_HIP(c, hipEventRecord(w->ev1, c->stream));
-    KM_HIP(c, hipMemcpyAsync(w->out_h, w->out, sizeof(BOut) * n_inst * km::BK_RMAX, hipMemcpyDeviceToHost, c->stream));
-    KM_HIP(c, hipMemcpyAsync(w->best_h, w->best, sizeof(int32_t) * n_inst, hipMemcpyDeviceToHost, c->stream));
-    KM_HIP(c, hipMemcpyAsync(w->best_mu_h, w->best_mu, sizeof(double) * n_inst * km::BK_KMAX * km::DMAX,
+    KM_HIP(c, hipMemcpyAsync(w->out_h, w->out, sizeof(BOut) * n_items * km::BK_RMAX, hipMemcpyDeviceToHost, c->stream));
+    KM_HIP(c, hipMemcpyAsync(w->best_h, w->best, sizeof(int32_t) * n_items, hipMemcpyDeviceToHost, c->stream));
+    KM_HIP(c, hipMemcpyAsync(w->best_mu_h, w->best_mu, sizeof(double) * n_items * km::BK_KMAX * km::DMAX,
                              hipMemcpyDeviceToHost, c->stream));
     KM_HIP(c, hipMemcpyAsync(w->error_h, &w->bs->error, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     KM_HIP(c, hipStreamSynchronize(c->stream));
@@ -343,29 +397,62 @@ int run_batched(kmeans_ctx* c, int32_t n_inst, km_instance* inst, double tol, in
     if (ms_out) *ms_out = w->last_ms;
     if (*w->error_h) return fail(c, KM_EHIP, "a team barrier of the batched kernel timed out");
 
+    // per instance: the kept restart over all of its items (smallest
+    // objective, lowest restart index on ties: items and their restarts come
+    // in restart order), its outcome and centres, and the copy of its labels
+    // when they were written by a later item
     int nonfinite = -1, range = -1;
-    for (int i = 0; i < n_inst; ++i) {
+    int n_copies = 0;
+    for (int j0 = 0; j0 < n_items;) {
+        const int i = items[j0].inst;
+        int j1 = j0;
+        while (j1 < n_items && items[j1].inst == i) ++j1;
         km_instance& in = inst[i];
-        const BOut* o = w->out_h + (size_t)i * km::BK_RMAX;
-        if (o[0].iters < 0) {
-            if (o[0].iters == -1 && nonfinite < 0) nonfinite = i;
-            if (o[0].iters == -2 && range < 0) range = i;
+        const BOut* o0 = w->out_h + (size_t)j0 * km::BK_RMAX;
+        if (o0[0].iters < 0) {
+            if (o0[0].iters == -1 && nonfinite < 0) nonfinite = i;
+            if (o0[0].iters == -2 && range < 0) range = i;
+            j0 = j1;
             continue;
         }
-        const int b = w->best_h[i];
-        in.best_restart = b;
-        memcpy(in.centroids_out, w->best_mu_h + (size_t)i * km::BK_KMAX * km::DMAX,
+        int bj = j0, br = 0;
+        double bJ = 0.0;
+        bool have = false;
+        for (int j = j0; j < j1; ++j) {
+            const BOut* o = w->out_h + (size_t)j * km::BK_RMAX;
+            for (int r = 0; r < items[j].nr; ++r) {
+                const int rr = items[j].r0 + r;
+                if (in.restart_objective) in.restart_objective[rr] = o[r].J;
+                if (in.restart_iters) in.restart_iters[rr] = o[r].iters;
+                if (!have || o[r].J < bJ) {
+                    have = true;
+                    bJ = o[r].J;
+                    bj = j;
+                    br = r;
+                }
+            }
+        }
+        // the item's own kept restart is the instance's (its objective is the
+        // smallest, and the first such within the item)
+        const BOut& ob = w->out_h[(size_t)bj * km::BK_RMAX + br];
+        in.best_restart = items[bj].r0 + br;
+        memcpy(in.centroids_out, w->best_mu_h + (size_t)bj * km::BK_KMAX * km::DMAX,
                sizeof(double) * in.K * in.d);
-        in.res.iters = o[b].iters;
-        in.res.converged = o[b].converged;
-        in.res.E = o[b].E;
-        in.res.shift_l2 = sqrt(o[b].E);
-        in.res.objective = o[b].J;
-        in.res.empty_events = o[b].empty_events;
-        if (in.restart_objective)
-            for (int r = 0; r < in.n_restarts; ++r) in.restart_objective[r] = o[r].J;
-        if (in.restart_iters)
-            for (int r = 0; r < in.n_restarts; ++r) in.restart_iters[r] = o[r].iters;
+        in.res.iters = ob.iters;
+        in.res.converged = ob.converged;
+        in.res.E = ob.E;
+        in.res.shift_l2 = sqrt(ob.E);
+        in.res.objective = ob.J;
+        in.res.empty_events = ob.empty_events;
+        if (in.labels_out && items[bj].r0 > 0)
+            w->copies_h[n_copies++] = km::BCopy{w->tmp_labels + tmp_off[bj], in.labels_out, in.N};
+        j0 = j1;
+    }
+    if (n_copies > 0) {
+        KM_HIP(c, hipMemcpyAsync(w->copies, w->copies_h, sizeof(km::BCopy) * n_copies,
+                                 hipMemcpyHostToDevice, c->stream));
+        KM_HIP(c, km::launch_batched_copy_labels(w->copies, n_copies, c->stream));
+        KM_HIP(c, hipStreamSynchronize(c->stream));
     }
     if (nonfinite >= 0)
         return fail(c, KM_EINVAL, "instance %d holds a NaN or an infinity", nonfinite);
@@ -402,16 +489,19 @@ bool cache_lookup(const char* path, const std::string& key, km_schedule* s) {
     bool found = false;
     while (fgets(line, sizeof line, f)) {
         char k[200];
-        int S = 0, b = 0;
+        int S = 0, b = 0, g = 0;
         double w = 0.0;
-        // one entry per line: {"key": "...", "team_size": S, "blocks_per_cu": b, "big_work": w}
-        if (sscanf(line, " {\"key\": \"%199[^\"]\", \"team_size\": %d, \"blocks_per_cu\": %d, "
-                         "\"big_work\": %lf",
-                   k, &S, &b, &w) == 4 &&
-            key == k) {
+        // one entry per line: {"key": "...", "team_size": S, "blocks_per_cu": b, "big_work": w,
+        // "restart_group": g, ...}
+        const int n = sscanf(line, " {\"key\": \"%199[^\"]\", \"team_size\": %d, \"blocks_per_cu\": %d, "
+                                   "\"big_work\": %lf, \"restart_group\": %d",
+                             k, &S, &b, &w, &g);
+        if (n >= 4 && key == k) {
             s->team_size = S;
             s->blocks_per_cu = b;
             s->big_work = w;
+            s->restart_group = n == 5 ? g : 0;
+            s->reserved = 0;
             found = true;
         }
     }
@@ -423,8 +513,8 @@ void cache_store(const char* path, const std::string& key, const km_schedule& s,
     FILE* f = fopen(path, "a");
     if (!f) return;
     fprintf(f, "{\"key\": \"%s\", \"team_size\": %d, \"blocks_per_cu\": %d, \"big_work\": %.17g, "
-               "\"ms\": %.4f}\n",
-            key.c_str(), s.team_size, s.blocks_per_cu, s.big_work, ms);
+               "\"restart_group\": %d, \"ms\": %.4f}\n",
+            key.c_str(), s.team_size, s.blocks_per_cu, s.big_work, s.restart_group, ms);
     fclose(f);
 }
 
@@ -446,6 +536,9 @@ int kmeans_set_batched_schedule(kmeans_ctx* c, const km_schedule* s) {
     if (s->blocks_per_cu < 0 || s->blocks_per_cu > 16)
         return fail(c, KM_EINVAL, "blocks_per_cu out of [0, 16]");
     if (!(s->big_work >= 0.0)) return fail(c, KM_EINVAL, "big_work must be >= 0");
+    if (s->restart_group < 0 || s->restart_group > km::BK_RMAX)
+        return fail(c, KM_EINVAL, "restart_group out of [0, %d]", km::BK_RMAX);
+    if (s->reserved != 0) return fail(c, KM_EINVAL, "reserved must be 0");
     c->sched = *s;
     return KM_OK;
 }
@@ -468,38 +561,66 @@ int kmeans_tune_batched(kmeans_ctx* c, int32_t n_inst, km_instance* inst, double
         if (best) *best = s;
         return KM_OK;
     }
-    // candidates: no teams, or teams of 4/8/16 blocks for the top 30/50/70/90 %
-    // of the instances by work; two to four resident blocks per compute unit
-    // (as many as fit).  Tune on the whole batch where possible: the tail of
-    // the launch (the last large instances on single blocks) depends on the
-    // number of instances per block.
-    std::vector<double> work(n_inst);
-    for (int i = 0; i < n_inst; ++i)
-        work[i] = (double)inst[i].N * inst[i].K * inst[i].n_restarts;
-    std::sort(work.begin(), work.end());
-    auto q = [&](double f) { return work[(size_t)(f * (double)(n_inst - 1))]; };
+    // candidates: no teams, or teams of 4/8/16 blocks for the top 90/70/50/30 %
+    // of the work items by work; two to four resident blocks per compute unit
+    // (as many as fit); every restart of an instance in one item.  Tune on
+    // the whole batch where possible: the tail of the launch (the last large
+    // items on single blocks) depends on the number of items per block.  Then,
+    // from the fastest, restart groups of 4, 2 and 1 (with the same team
+    // threshold as a share of the items).
+    int rmax = 1;
+    for (int i = 0; i < n_inst; ++i) rmax = std::max(rmax, (int)inst[i].n_restarts);
+    auto threshold = [&](int g, double f) {
+        const std::vector<Item> items = work_items(n_inst, inst, g);
+        std::vector<double> work(items.size());
+        for (size_t j = 0; j < items.size(); ++j) {
+            const km_instance& in = inst[items[j].inst];
+            work[j] = (double)in.N * in.K * items[j].nr;
+        }
+        std::sort(work.begin(), work.end());
+        return std::max(1.0, work[(size_t)(f * (double)(work.size() - 1))]);
+    };
     const int occ = km::batched_max_blocks_per_cu();
-    std::vector<km_schedule> cand;
+    struct Cand {
+        km_schedule s;
+        double f;  // team threshold as a quantile of the items' work (< 0: no teams)
+    };
+    std::vector<Cand> cand;
     for (int bpc : {2, 3, 4}) {
         if (bpc > occ && bpc > 2) break;
-        cand.push_back({1, bpc, 0.0});
+        cand.push_back({{1, bpc, 0.0, 0, 0}, -1.0});
         for (int S : {4, 8, 16})
-            for (double f : {0.10, 0.30, 0.50, 0.70}) cand.push_back({S, bpc, std::max(1.0, q(f))});
+            for (double f : {0.10, 0.30, 0.50, 0.70})
+                cand.push_back({{S, bpc, threshold(0, f), 0, 0}, f});
     }
     float best_ms = 1e30f;
-    km_schedule best_s = cand[0];
+    Cand best_c = cand[0];
     // one warm-up run (allocations, code load), then one timed run per candidate
-    int rc = run_batched(c, n_inst, inst, tol, max_iter, cand[0], nullptr);
+    int rc = run_batched(c, n_inst, inst, tol, max_iter, cand[0].s, nullptr);
     if (rc) return rc;
-    for (const km_schedule& cs : cand) {
+    for (const Cand& cs : cand) {
         float ms = 0.f;
-        rc = run_batched(c, n_inst, inst, tol, max_iter, cs, &ms);
+        rc = run_batched(c, n_inst, inst, tol, max_iter, cs.s, &ms);
         if (rc) return rc;
         if (ms < best_ms) {
             best_ms = ms;
-            best_s = cs;
+            best_c = cs;
         }
     }
+    for (int g : {4, 2, 1}) {
+        if (g >= rmax) continue;
+        Cand cs = best_c;
+        cs.s.restart_group = g;
+        cs.s.big_work = cs.f < 0.0 ? 0.0 : threshold(g, cs.f);
+        float ms = 0.f;
+        rc = run_batched(c, n_inst, inst, tol, max_iter, cs.s, &ms);
+        if (rc) return rc;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best_c = cs;
+        }
+    }
+    const km_schedule best_s = best_c.s;
     c->sched = best_s;
     if (best) *best = best_s;
     if (cache_path) cache_store(cache_path, key, best_s, best_ms);

@@ -27,6 +27,7 @@
 // points takes it in chunks of at most that many, adding each chunk's sums
 // into a block-private 128-bit area in device memory (fold), so that no
 // int64 slot overflows under any schedule.
+#include "batched_copy.h"
 #include "lloyd_device.h"
 
 namespace km {
@@ -544,6 +545,21 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 8))) v
 }
 
 }  // namespace
+
+// Label copies (batched_copy.h): block b takes entries b, b + grid, ...
+__global__ __launch_bounds__(BLOCK) void batched_copy_labels(const BCopy* __restrict__ tab, int n) {
+    for (int t = blockIdx.x; t < n; t += gridDim.x) {
+        const BCopy c = tab[t];
+        for (int64_t i = threadIdx.x; i < c.n; i += BLOCK) c.dst[i] = c.src[i];
+    }
+}
+
+hipError_t launch_batched_copy_labels(const BCopy* tab, int n, hipStream_t s) {
+    if (n < 1) return hipSuccess;
+    const int grid = n < 1024 ? n : 1024;
+    hipLaunchKernelGGL(batched_copy_labels, dim3(grid), dim3(BLOCK), 0, s, tab, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_batched_scan(BatchState* bs, int n_inst, int grid, hipStream_t s) {
     if (grid < 1) return hipErrorInvalidValue;

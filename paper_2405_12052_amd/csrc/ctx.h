@@ -67,7 +67,7 @@ struct kmeans_ctx {
     int last_T = 0;
     // batched fits
     km::BatchedWS* bws = nullptr;
-    km_schedule sched = {0, 0, 0.0};   // zeros: automatic
+    km_schedule sched = {0, 0, 0.0, 0, 0};  // zeros: automatic
     // learned initialiser
     km::NetWS* nws = nullptr;
     // k-means++ seeding

@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_abi_version():
-    assert km.load_library().kmeans_abi_version() == 1
+    assert km.load_library().kmeans_abi_version() == 2
 
 
 @pytest.mark.parametrize("args,code", [

@@ -99,6 +99,33 @@ def test_schedule_independence(km, batch):
             assert np.array_equal(a["labels"].cpu().numpy(), b["labels"].cpu().numpy())
 
 
+@pytest.mark.parametrize("group", [4, 3, 2, 1])
+def test_restart_groups_give_the_same_results(km, batch, group):
+    """Restart fusion (km_schedule.restart_group): an instance's restarts run
+    as work items of at most `group` restarts, the kept restart chosen across
+    them and its labels copied from a later item when it ran there.  Every
+    output equals the one-item run's, on a batch of 1 to 8 restarts per
+    instance, with and without teams."""
+    specs, inst, host, _ = batch
+    for team in (8, 1):
+        # The objective's float64 summation order follows the team layout, so
+        # each grouping is compared with the one-item run on the same teams.
+        km.set_batched_schedule(team, 2, 0.0, 0)
+        base = km.fit_batched(inst, tol=1e-6, max_iter=300)
+        sch = (team, 2, 0.0, group)
+        km.set_batched_schedule(*sch)
+        out = km.fit_batched(inst, tol=1e-6, max_iter=300)
+        for s, a, b in zip(specs, base, out):
+            assert a["best_restart"] == b["best_restart"], (sch, s.name)
+            assert np.array_equal(a["centroids"], b["centroids"]), sch
+            assert a["iters"] == b["iters"] and a["E"] == b["E"], sch
+            assert a["objective"] == b["objective"], sch
+            assert np.array_equal(a["restart_objective"], b["restart_objective"]), sch
+            assert np.array_equal(a["restart_iters"], b["restart_iters"]), sch
+            assert np.array_equal(a["labels"].cpu().numpy(), b["labels"].cpu().numpy()), sch
+    km.set_batched_schedule(0, 0, 0.0, 0)
+
+
 def test_batched_errors(km, batch):
     from paper_2405_12052_amd import KM_EINVAL, KM_EUNSUPPORTED, KMeansError
     specs, inst, host, dev = batch
@@ -126,6 +153,7 @@ def test_tuner_and_cache(km, tmp_path):
     log(f"tuned schedule {best}")
     lines = open(cache).read().strip().splitlines()
     assert len(lines) == 1 and json.loads(lines[0])["team_size"] == best["team_size"]
+    assert json.loads(lines[0])["restart_group"] == best["restart_group"]
     again = km.tune_batched(inst, tol=1e-6, max_iter=300, cache_path=cache)
     assert again == best and len(open(cache).read().strip().splitlines()) == 1
     assert km.batched_schedule() == best
