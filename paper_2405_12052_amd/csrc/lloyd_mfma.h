@@ -51,8 +51,10 @@
 // flushed f16 subnormal pieces to zero, each dropped product would add < 2
 // (scaled units), < 8 in all.  Packing 3 bits moves a quad minimum by at
 // most 7 units in its last place, <= 0.875 2^-20 mag'.  When L - W exceeds
-// 2 (pack + e_m), below 16 b(x) 2^(2e) + 16 with b(x) the VALU scan's bound
-// (b >= 2^-21 mag), every key outside the winning quad
+// 2 (pack + e_m) <= 6.01 2^-20 mag' + 16.008, below 12.5 b(x) 2^(2e) + 17
+// with b(x) the VALU scan's bound (b >= 2^-21 mag; the margin also covers
+// the float32 rounding of L - W and of the bound), every key outside the
+// winning quad
 // exceeds, in exact arithmetic, the exact key of the quad's smallest member;
 // when in addition t2 - t1 > b(x), the re-keying orders the quad exactly.
 // The winner is then the exact argmin over all centres, and its margin is far
@@ -143,6 +145,20 @@ __device__ __forceinline__ void top2_merge(float& m1, float& m2, float u1, float
     m1 = vmin2(m1, u1);
 }
 
+// W, the smallest of 8 distinct values, and L, the second smallest, in 10
+// instructions: groups of 3, 3 and 2 give their smallest (a1, b1, c1) and
+// second smallest (a2, b2, c2); W is the smallest group minimum, and L the
+// smaller of the middle group minimum (the best of the other groups) and the
+// smallest second (the winning group's own runner-up, or a larger value).
+__device__ __forceinline__ void top2_of_8(const float (&p)[8], float& W, float& L) {
+    float a1, a2, b1, b2;
+    top2_3(p[0], p[1], p[2], a1, a2);
+    top2_3(p[3], p[4], p[5], b1, b2);
+    const float c1 = vmin2(p[6], p[7]), c2 = vmax2(p[6], p[7]);
+    W = vmin3(a1, b1, c1);
+    L = vmin2(__builtin_amdgcn_fmed3f(a1, b1, c1), vmin3(a2, b2, c2));
+}
+
 // The keys of one chunk (B: its points' operand) against the KT tiles of
 // centres A: W, the smallest packed quad minimum, and L, the second smallest
 // (a small tournament over the 4 KT packed minima).
@@ -156,13 +172,7 @@ __device__ __forceinline__ void chunk_keys(const f16x8 (&A)[KT], f16x8 B, float 
     if constexpr (KT == 2) {
         const f32x16 k1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[1], B, zero16, 0, 0, 0);
         tile_minima<1>(k1, ninf, reinterpret_cast<float(&)[4]>(p[4]));
-        float a1, a2, b1, b2;
-        top2_3(p[0], p[1], p[2], a1, a2);
-        top2_3(p[3], p[4], p[5], b1, b2);
-        top2_merge(a1, a2, b1, b2);
-        top2_merge(a1, a2, vmin2(p[6], p[7]), vmax2(p[6], p[7]));
-        W = a1;
-        L = a2;
+        top2_of_8(p, W, L);
     } else {
         float a1, a2;
         top2_3(p[0], p[1], p[2], a1, a2);
@@ -197,7 +207,12 @@ __device__ __forceinline__ f16x8 point_operand(float u, float v, uint32_t q3) {
     _Float16 uh, ul, vh, vl;
     split_f16(u, uh, ul);
     split_f16(v, vh, vl);
-    const u32x4 r = {pack2(uh, ul), pack2(vh, vl), pack2(uh, vh), q3};
+    const uint32_t r0 = pack2(uh, ul), r1 = pack2(vh, vl);
+    // (uh, vh): the low halves of r0 and r1, one byte permute (left to
+    // itself the compiler converts uh and vh a second time)
+    uint32_t r2;
+    asm("v_perm_b32 %0, %1, %2, %3" : "=v"(r2) : "v"(r1), "v"(r0), "s"(0x05040100u));
+    const u32x4 r = {r0, r1, r2, q3};
     return __builtin_bit_cast(f16x8, r);
 }
 
@@ -274,10 +289,10 @@ __device__ __forceinline__ void assign_points_mfma(const float* __restrict__ X, 
     const uint32_t hm = h ? ~0u : 0u;  // lane half as a bit mask
     const uint32_t q3 = h == 0 ? pack2((_Float16)T, (_Float16)T) : pack2((_Float16)T, (_Float16)P);
     const float s = ldexpf(1.0f, e);
-    // matrix-key bound in scaled units: 16 b(x) 2^(2e) + 16 (the absolute
+    // matrix-key bound in scaled units: 12.5 b(x) 2^(2e) + 17 (the absolute
     // part covers f16 subnormal pieces even if the matrix core flushed them);
     // the scale 2^(2e+4) <= 2^124 stays finite
-    const float bms = ldexpf(16.0f, 2 * e);
+    const float bms = ldexpf(12.5f, 2 * e);
 
     int qn = 0;
     auto drain = [&](int cnt) {
@@ -293,19 +308,40 @@ __device__ __forceinline__ void assign_points_mfma(const float* __restrict__ X, 
         qn -= cnt;
     };
 
-    const int64_t nchunks = (N + 63) / 64;
+    // chunk numbers in 32 bits (N < 2^31), so the loop test is a scalar one
+    const int nchunks = (int)((N + 63) / 64);
+    // the points as global memory: loads from a wave-uniform base in scalar
+    // registers plus the lane's 32-bit offset
+    typedef const float __attribute__((address_space(1)))* gfp;
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    typedef const f32x2 __attribute__((address_space(1)))* gf2p;
+    const gfp Xg = (gfp)X;
     // the wave's index, known to the compiler as uniform (scalar registers)
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (int64_t ch = (int64_t)blockIdx.x * NW + wid; ch < nchunks;
-         ch += (int64_t)gridDim.x * NW) {
-        const int64_t i0 = ch * 64 + 2 * c;  // first of this lane's 2 points
-        // points of this chunk pair that exist (wave-uniform)
-        const int rem = N - ch * 64 < 64 ? (int)(N - ch * 64) : 64;
+    // the grid stride, kept in a scalar register (reloaded from the dispatch
+    // packet it would cost a wait on every outstanding LDS atomic per chunk)
+    int stride = (int)gridDim.x * NW;
+    asm("" : "+s"(stride));
+    for (int ch = (int)blockIdx.x * NW + wid; ch < nchunks; ch += stride) {
+        const int64_t c0 = (int64_t)ch * 64;
+        const int64_t i0 = c0 + 2 * c;  // first of this lane's 2 points
+        // points of this chunk pair that exist (wave-uniform; left > 0).  The
+        // empty asm statements keep these values in scalar registers as
+        // written: the compiler would otherwise turn the test into a 64-bit
+        // comparison on the VALU, and fold the row base into per-lane 64-bit
+        // addresses.
+        const int64_t left = N - c0;
+        int64_t lhi = left >> 6;
+        asm("" : "+s"(lhi));
+        const bool full = lhi != 0;
+        const int rem = full ? 64 : (int)left;
         float x[3][2];
-        if (VEC && i0 + 2 <= N) {
+        if (VEC && full) {
 #pragma unroll
             for (int j = 0; j < D; ++j) {
-                const float2 v = *reinterpret_cast<const float2*>(X + j * ld + i0);
+                gfp row = Xg + (j * ld + c0);
+                asm("" : "+s"(row));
+                const f32x2 v = *(gf2p)(row + (uint32_t)(2 * c));
                 x[j][0] = v.x; x[j][1] = v.y;
             }
         } else {
@@ -365,15 +401,20 @@ __device__ __forceinline__ void assign_points_mfma(const float* __restrict__ X, 
         float b = fmaf(bnd.y, fabsf(x0), bnd.x);
         b = fmaf(bnd.z, fabsf(x1), b);
         if constexpr (D == 3) b = fmaf(bnd.w, fabsf(x2), b);
-        const float bm = fmaf(b, bms, 16.0f);
+        const float bm = fmaf(b, bms, 17.0f);
         const int64_t i = i0 + h;
         const bool valid = 2 * c + h < rem;
         const bool ok = Lc - Wc > bm && t2 - t1 > b && k < K;
-        if (valid && ok) sink(i, x0, x1, x2, k, direct_dist<D>(x0, x1, x2, smu[k]));
+        // the queue's lanes, taken before the sink's branch (the mask is then
+        // still the comparison's, with no copy through a vector register)
         const bool f = valid && !ok;
-        const uint64_t m = __ballot(f);
+        const uint64_t m = __builtin_amdgcn_ballot_w64(f);
+        if (valid && ok) sink(i, x0, x1, x2, k, direct_dist<D>(x0, x1, x2, smu[k]));
         if (m) {
-            if (f) wq[qn + __popcll(m & below)] = make_float4(x0, x1, x2, __int_as_float((int)i));
+            // slot: the queued lanes below this one (mbcnt)
+            const int below_m = (int)__builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            if (f) wq[qn + below_m] = make_float4(x0, x1, x2, __int_as_float((int)i));
             qn += __popcll(m);
             if (qn >= 64) drain(64);
         }

@@ -798,11 +798,8 @@ __device__ __forceinline__ void wide_points_mfma(const WState* __restrict__ st, 
                 }
 #pragma unroll
                 for (int p = 0; p < PL; ++p) {
-                    float a1, a2, b1, b2;
-                    top2_3(pm[p][0], pm[p][1], pm[p][2], a1, a2);
-                    top2_3(pm[p][3], pm[p][4], pm[p][5], b1, b2);
-                    top2_merge(a1, a2, b1, b2);
-                    top2_merge(a1, a2, vmin2(pm[p][6], pm[p][7]), vmax2(pm[p][6], pm[p][7]));
+                    float a1, a2;
+                    top2_of_8(pm[p], a1, a2);
                     // into the running pair
                     L[p] = vmin3(vmax2(W[p], a1), L[p], a2);
                     G[p] = a1 < W[p] ? g : G[p];
