@@ -403,18 +403,26 @@ __device__ __forceinline__ void assign_points_mfma(const float* __restrict__ X, 
         if constexpr (D == 3) b = fmaf(bnd.w, fabsf(x2), b);
         const float bm = fmaf(b, bms, 17.0f);
         const int64_t i = i0 + h;
-        const bool valid = 2 * c + h < rem;
-        const bool ok = Lc - Wc > bm && t2 - t1 > b && k < K;
-        // the queue's lanes, taken before the sink's branch (the mask is then
-        // still the comparison's, with no copy through a vector register)
-        const bool f = valid && !ok;
-        const uint64_t m = __builtin_amdgcn_ballot_w64(f);
-        if (valid && ok) sink(i, x0, x1, x2, k, direct_dist<D>(x0, x1, x2, smu[k]));
+        // The certificate as lane masks, one ballot per comparison, combined
+        // on the scalar unit (a ballot of a combined condition costs a copy
+        // through a vector register).  No k < K test: a pad's matrix key,
+        // 2^30, is above every real one (< 2^29.2), so the winning quad
+        // holds a real centre, and a pad's record keys at 2^127, above
+        // every real key, so t1 is a real centre's.
+        const uint64_t mv = __builtin_amdgcn_ballot_w64(2 * c + h < rem);
+        const uint64_t mok = __builtin_amdgcn_ballot_w64(Lc - Wc > bm) &
+                             __builtin_amdgcn_ballot_w64(t2 - t1 > b);
+        // the queue's lanes: valid and not certified
+        const uint64_t m = mv & ~mok;
+        if (__builtin_amdgcn_inverse_ballot_w64(mv & mok))
+            sink(i, x0, x1, x2, k, direct_dist<D>(x0, x1, x2, smu[k]));
         if (m) {
             // slot: the queued lanes below this one (mbcnt)
             const int below_m = (int)__builtin_amdgcn_mbcnt_hi(
                 (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-            if (f) wq[qn + below_m] = make_float4(x0, x1, x2, __int_as_float((int)i));
+            // this lane is queued: its bit of m, as a lane mask (no vector copy)
+            if (__builtin_amdgcn_inverse_ballot_w64(m))
+                wq[qn + below_m] = make_float4(x0, x1, x2, __int_as_float((int)i));
             qn += __popcll(m);
             if (qn >= 64) drain(64);
         }
