@@ -132,7 +132,8 @@ def bench_batched(args):
         # a fixed schedule (A/B timing of kernel changes): team size, blocks per
         # compute unit, work threshold of the teams
         f = args.schedule.split(",")
-        km.set_batched_schedule(int(f[0]), int(f[1]), float(f[2]), int(f[3]) if len(f) > 3 else 0)
+        km.set_batched_schedule(int(f[0]), int(f[1]), float(f[2]), int(f[3]) if len(f) > 3 else 0,
+                                int(f[4]) if len(f) > 4 else 0)
         sched = km.batched_schedule()
         log(f"fixed schedule: {sched}")
     else:
@@ -558,7 +559,7 @@ def main():
     ap.add_argument("--instances", type=int, default=None,
                     help="instances (batched: 4096, learned: 100)")
     ap.add_argument("--repeats", type=int, default=3)
-    ap.add_argument("--schedule", default=None, metavar="TEAM,BLOCKS_PER_CU,BIG_WORK[,RESTART_GROUP]",
+    ap.add_argument("--schedule", default=None, metavar="TEAM,BLOCKS_PER_CU,BIG_WORK[,RESTART_GROUP[,MFMA_MIN_K]]",
                     help="--workload batched: use this schedule instead of the autotuner's")
     ap.add_argument("--weights", default=None, help="learned initialiser weights (.npy)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",

@@ -301,8 +301,17 @@ typedef struct km_schedule {
                                    at most restart_group restarts each, every item scanning its
                                    restarts in one pass over the points (1..8; 0 = all of
                                    them in one item).  Results do not depend on it.      */
-    int32_t reserved;           /* must be 0                                          */
+    int32_t mfma_min_k;         /* 3-D instances with K >= mfma_min_k reassign with the
+                                   matrix-core keys (all their restarts' centres as rows of
+                                   32-row tiles), the others with the VALU keys (1..33;
+                                   33 = never; 0 = the default, KM_BATCHED_MFMA_MIN_K).
+                                   Results do not depend on it.                          */
 } km_schedule;
+
+/* Default of km_schedule.mfma_min_k: the VALU keys everywhere (on the mixed
+   4096-instance batch the matrix-core keys from K = 16 measured 2.6 % slower;
+   on uniform batches of 3-D instances at K = 32, 15 % faster). */
+#define KM_BATCHED_MFMA_MIN_K 33
 
 /*
  * Many independent fits in one persistent launch (the points of every
@@ -331,7 +340,8 @@ int kmeans_get_batched_schedule(kmeans_ctx *ctx, km_schedule *s);
  * size 1, 4, 8, 16; teams for the top 90/70/50/30 % of work items by N*K*R;
  * 2-4 blocks per compute unit; all restarts fused), then, from the fastest,
  * restart groups of 4, 2 and 1 where the batch has more restarts per
- * instance, and keeps the fastest on the context and
+ * instance, then the matrix-core keys for 3-D instances from K = 24 and 16
+ * (km_schedule.mfma_min_k), and keeps the fastest on the context and
  * writes it to *best (may be NULL).  If cache_path is not NULL the result is
  * looked up first and stored afterwards in that JSON file, keyed by a coarse
  * signature of the batch (restarts, d mix, K and N ranges).  Results of the

@@ -49,7 +49,7 @@ class km_instance(C.Structure):
 
 class km_schedule(C.Structure):
     _fields_ = [("team_size", C.c_int32), ("blocks_per_cu", C.c_int32), ("big_work", C.c_double),
-                ("restart_group", C.c_int32), ("reserved", C.c_int32)]
+                ("restart_group", C.c_int32), ("mfma_min_k", C.c_int32)]
 
 
 _lib = None
@@ -280,15 +280,17 @@ class KMeans:
                         "empty_events": r.empty_events})
         return res
 
-    def set_batched_schedule(self, team_size=0, blocks_per_cu=0, big_work=0.0, restart_group=0):
-        s = km_schedule(int(team_size), int(blocks_per_cu), float(big_work), int(restart_group), 0)
+    def set_batched_schedule(self, team_size=0, blocks_per_cu=0, big_work=0.0, restart_group=0,
+                             mfma_min_k=0):
+        s = km_schedule(int(team_size), int(blocks_per_cu), float(big_work), int(restart_group),
+                        int(mfma_min_k))
         self._check(self._lib.kmeans_set_batched_schedule(self._ctx, C.byref(s)))
 
     def batched_schedule(self):
         s = km_schedule()
         self._check(self._lib.kmeans_get_batched_schedule(self._ctx, C.byref(s)))
         return {"team_size": s.team_size, "blocks_per_cu": s.blocks_per_cu, "big_work": s.big_work,
-                "restart_group": s.restart_group}
+                "restart_group": s.restart_group, "mfma_min_k": s.mfma_min_k}
 
     def tune_batched(self, instances, tol=1e-6, max_iter=300, cache_path=None):
         """Search the batched schedule on `instances`; keeps the fastest."""
@@ -298,7 +300,7 @@ class KMeans:
         self._check(self._lib.kmeans_tune_batched(self._ctx, len(instances), arr, float(tol),
                                                   int(max_iter), cp, C.byref(s)))
         return {"team_size": s.team_size, "blocks_per_cu": s.blocks_per_cu, "big_work": s.big_work,
-                "restart_group": s.restart_group}
+                "restart_group": s.restart_group, "mfma_min_k": s.mfma_min_k}
 
     # ------------------------------------------------ learned initialiser
     def _net_args(self, pts, K, params):

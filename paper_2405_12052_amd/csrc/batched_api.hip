@@ -209,6 +209,7 @@ km_schedule resolve(kmeans_ctx* c, const km_schedule& s, const std::vector<doubl
     if (r.team_size <= 0) r.team_size = 8;
     if (r.team_size > km::BK_TEAM_MAX) r.team_size = km::BK_TEAM_MAX;
     if (r.blocks_per_cu <= 0) r.blocks_per_cu = 3;
+    if (r.mfma_min_k <= 0) r.mfma_min_k = KM_BATCHED_MFMA_MIN_K;
     if (r.big_work <= 0.0) {
         // default: instances above the 30th percentile of work go to teams.
         // Single blocks take the rest once the teams' list is empty; a
@@ -331,6 +332,7 @@ int run_batched(kmeans_ctx* c, int32_t n_inst, km_instance* inst, double tol, in
         h->n_small = n_items;
     }
     h->team_size = n_teams ? S : 1;
+    h->mfma_min_k = sch.mfma_min_k;
     h->n_teams = n_teams;
     h->max_iter = max_iter;
     h->tol = tol;
@@ -489,19 +491,19 @@ bool cache_lookup(const char* path, const std::string& key, km_schedule* s) {
     bool found = false;
     while (fgets(line, sizeof line, f)) {
         char k[200];
-        int S = 0, b = 0, g = 0;
+        int S = 0, b = 0, g = 0, mk = 0;
         double w = 0.0;
         // one entry per line: {"key": "...", "team_size": S, "blocks_per_cu": b, "big_work": w,
-        // "restart_group": g, ...}
+        // "restart_group": g, "mfma_min_k": mk, ...}
         const int n = sscanf(line, " {\"key\": \"%199[^\"]\", \"team_size\": %d, \"blocks_per_cu\": %d, "
-                                   "\"big_work\": %lf, \"restart_group\": %d",
-                             k, &S, &b, &w, &g);
+                                   "\"big_work\": %lf, \"restart_group\": %d, \"mfma_min_k\": %d",
+                             k, &S, &b, &w, &g, &mk);
         if (n >= 4 && key == k) {
             s->team_size = S;
             s->blocks_per_cu = b;
             s->big_work = w;
-            s->restart_group = n == 5 ? g : 0;
-            s->reserved = 0;
+            s->restart_group = n >= 5 ? g : 0;
+            s->mfma_min_k = n >= 6 ? mk : 0;
             found = true;
         }
     }
@@ -513,8 +515,8 @@ void cache_store(const char* path, const std::string& key, const km_schedule& s,
     FILE* f = fopen(path, "a");
     if (!f) return;
     fprintf(f, "{\"key\": \"%s\", \"team_size\": %d, \"blocks_per_cu\": %d, \"big_work\": %.17g, "
-               "\"restart_group\": %d, \"ms\": %.4f}\n",
-            key.c_str(), s.team_size, s.blocks_per_cu, s.big_work, s.restart_group, ms);
+               "\"restart_group\": %d, \"mfma_min_k\": %d, \"ms\": %.4f}\n",
+            key.c_str(), s.team_size, s.blocks_per_cu, s.big_work, s.restart_group, s.mfma_min_k, ms);
     fclose(f);
 }
 
@@ -538,7 +540,8 @@ int kmeans_set_batched_schedule(kmeans_ctx* c, const km_schedule* s) {
     if (!(s->big_work >= 0.0)) return fail(c, KM_EINVAL, "big_work must be >= 0");
     if (s->restart_group < 0 || s->restart_group > km::BK_RMAX)
         return fail(c, KM_EINVAL, "restart_group out of [0, %d]", km::BK_RMAX);
-    if (s->reserved != 0) return fail(c, KM_EINVAL, "reserved must be 0");
+    if (s->mfma_min_k < 0 || s->mfma_min_k > km::BK_KMAX + 1)
+        return fail(c, KM_EINVAL, "mfma_min_k out of [0, %d]", km::BK_KMAX + 1);
     c->sched = *s;
     return KM_OK;
 }
@@ -567,7 +570,7 @@ int kmeans_tune_batched(kmeans_ctx* c, int32_t n_inst, km_instance* inst, double
     // the whole batch where possible: the tail of the launch (the last large
     // items on single blocks) depends on the number of items per block.  Then,
     // from the fastest, restart groups of 4, 2 and 1 (with the same team
-    // threshold as a share of the items).
+    // threshold as a share of the items), then the matrix-core keys.
     int rmax = 1;
     for (int i = 0; i < n_inst; ++i) rmax = std::max(rmax, (int)inst[i].n_restarts);
     auto threshold = [&](int g, double f) {
@@ -612,6 +615,23 @@ int kmeans_tune_batched(kmeans_ctx* c, int32_t n_inst, km_instance* inst, double
         Cand cs = best_c;
         cs.s.restart_group = g;
         cs.s.big_work = cs.f < 0.0 ? 0.0 : threshold(g, cs.f);
+        float ms = 0.f;
+        rc = run_batched(c, n_inst, inst, tol, max_iter, cs.s, &ms);
+        if (rc) return rc;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best_c = cs;
+        }
+    }
+    // then the matrix-core keys for the 3-D instances from K = 16 or 24
+    // (they pay only at the larger K: fewer instructions per point, but a
+    // longer dependent chain per restart)
+    for (int mk : {24, 16}) {
+        bool any = false;
+        for (int i = 0; i < n_inst; ++i) any = any || (inst[i].d == 3 && inst[i].K >= mk);
+        if (!any) continue;
+        Cand cs = best_c;
+        cs.s.mfma_min_k = mk;
         float ms = 0.f;
         rc = run_batched(c, n_inst, inst, tol, max_iter, cs.s, &ms);
         if (rc) return rc;

@@ -29,6 +29,7 @@
 // int64 slot overflows under any schedule.
 #include "batched_copy.h"
 #include "lloyd_device.h"
+#include "lloyd_mfma.h"
 
 namespace km {
 namespace {
@@ -204,6 +205,256 @@ __device__ void points_pass(const BInst& in, int rank, int S, int mask, double f
     if (qn > 0) drain(qn);
 }
 
+// The update pass (MODE_ACC) with matrix-core keys for all active restarts of
+// the instance at once: the single fit's split-fp16 keys, packed quad minima,
+// VALU re-key of the winning quad and certificate (lloyd_mfma.h), so the
+// labels equal the VALU pass's.  Rows of the 32-row tiles are (restart,
+// centre) slots: each restart owns SW consecutive rows (SW = 8, 16 or 32 >=
+// K; slots past K are pads), so a tile holds RT = 32 / SW restarts and the
+// restart of every result register is known at compile time.  A wave takes 64
+// points at a time (lane (c, h): points 2c and 2c + 1, "chunks" 0 and 1);
+// after the two chunks' keys, lane half h finishes chunk h's point for every
+// restart.  e: the common scale exponent (mfma_scale of every active
+// restart).  Points [4 g_lo, min(4 g_hi, N)) in units of 64, strided over
+// the team's waves.
+template <int D, int SW>
+__device__ void points_pass_mfma(const BInst& in, int rank, int S, int mask, double fscale,
+                                 float ninf, int e, BSmem& sm, int64_t g_lo, int64_t g_hi) {
+    constexpr int RT = 32 / SW;        // restarts per tile
+    constexpr int NT = BK_RMAX / RT;   // tiles at most
+    constexpr int QPR = SW / 8;        // quads of result registers per restart (4, 2, 1)
+    constexpr float T = 16384.0f, P = 32768.0f;
+    const int K = in.K, R = in.R;
+    const int64_t N = in.N, ld = in.ld;
+    const float* __restrict__ X = in.X;
+    const bool vec = in.vec != 0;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int c = lane & 31, h = lane >> 5;
+    float4* __restrict__ wq = sm.queue[w];
+    int qn = 0;
+    const int nacc = R * K * (D + 1);
+    unsigned long long* const myacc = &sm.acc[(lane % acc_copies(nacc)) * nacc];
+    const int ntiles = (R + RT - 1) / RT;
+
+    // A operands: row c of tile t is centre c % SW of restart t RT + c / SW
+    f16x8 A[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int r = t * RT + c / SW, k = c % SW;
+        const bool real = r < R && ((mask >> r) & 1) && k < K;
+        A[t] = centre_operand<D>(real, real ? sm.scand[r][k] : make_float4(0.f, 0.f, 0.f, 0.f),
+                                 e, h);
+    }
+    const uint32_t hm = h ? ~0u : 0u;
+    const uint32_t q3 = h == 0 ? pack2((_Float16)T, (_Float16)T) : pack2((_Float16)T, (_Float16)P);
+    const float sc = ldexpf(1.0f, e);
+    const float bms = ldexpf(12.5f, 2 * e);  // matrix-key bound, as in the single fit
+
+    auto drain = [&](int cnt) {
+        __builtin_amdgcn_wave_barrier();
+        if (lane < cnt) {
+            const float4 q = wq[qn - cnt + lane];
+            const int tag = __float_as_int(q.w);
+            const int r = tag >> 27;
+            float bd;
+            int bk;
+            direct_scan<D>(sm.smu[r], K, q.x, q.y, q.z, bd, bk);
+            unsigned long long* a = &myacc[r * (D + 1) * K + bk];
+            const float xs[3] = {q.x, q.y, q.z};
+#pragma unroll
+            for (int j = 0; j < D; ++j)
+                __hip_atomic_fetch_add(&a[j * K], fxp_bits(xs[j], fscale), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(&a[D * K], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        __builtin_amdgcn_wave_barrier();
+        qn -= cnt;
+    };
+
+    const int64_t p_lo = 4 * g_lo;
+    const int64_t p_hi = 4 * g_hi < N ? 4 * g_hi : N;
+    // PU units of 64 points per wave and iteration: independent chains of
+    // matrix products, re-keying and certificates for the scheduler to
+    // interleave (few waves are resident beside this kernel's registers)
+    constexpr int PU = 2;
+    const int64_t nunits = (p_hi - p_lo + 63) / 64;
+    const int64_t npairs = (nunits + PU - 1) / PU;
+    const int wid = __builtin_amdgcn_readfirstlane(w);
+    for (int64_t v = (int64_t)rank * NW + wid; v < npairs; v += (int64_t)S * NW) {
+        float x0[PU], x1[PU], x2[PU];
+        int64_t i[PU];
+        uint64_t mv[PU];
+        unsigned long long fb[PU][3];
+        f16x8 B[PU][2];
+#pragma unroll
+        for (int pu = 0; pu < PU; ++pu) {
+            const int64_t c0 = p_lo + (v * PU + pu) * 64;
+            const int64_t left = p_hi - c0;
+            const int rem = left <= 0 ? 0 : (left < 64 ? (int)left : 64);
+            const int64_t i0 = c0 + 2 * c;  // this lane's first point of the unit
+            float x[3][2];
+            if (vec && rem == 64) {
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    const float2 q = *reinterpret_cast<const float2*>(X + j * ld + i0);
+                    x[j][0] = q.x; x[j][1] = q.y;
+                }
+            } else {
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    const bool inr = 2 * c + p < rem;
+#pragma unroll
+                    for (int j = 0; j < D; ++j) x[j][p] = inr ? X[j * ld + i0 + p] : 0.0f;
+                }
+            }
+            if constexpr (D == 2) {
+                x[2][0] = 0.0f;
+                x[2][1] = 0.0f;
+            }
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+                B[pu][q] = point_operand(sel_half(hm, x[0][q], x[2][q]) * sc, x[1][q] * sc, q3);
+            // this lane's point (chunk h), its fixed-point bits (one
+            // conversion for every restart)
+            x0[pu] = sel_half(hm, x[0][0], x[0][1]);
+            x1[pu] = sel_half(hm, x[1][0], x[1][1]);
+            x2[pu] = sel_half(hm, x[2][0], x[2][1]);
+            i[pu] = i0 + h;
+            mv[pu] = __builtin_amdgcn_ballot_w64(2 * c + h < rem);
+            fb[pu][0] = fxp_bits(x0[pu], fscale);
+            fb[pu][1] = fxp_bits(x1[pu], fscale);
+            fb[pu][2] = D == 3 ? fxp_bits(x2[pu], fscale) : 0ull;
+        }
+
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            if (t >= ntiles) break;
+            if (!((mask >> (t * RT)) & ((1 << RT) - 1))) continue;
+            // per unit, restart of the tile and chunk: the smallest packed
+            // quad minimum W and the second smallest L
+            float W[PU][RT][2], L[PU][RT][2];
+#pragma unroll
+            for (int pu = 0; pu < PU; ++pu)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const f32x16 zero16 = {};
+                const f32x16 kk = __builtin_amdgcn_mfma_f32_32x32x16_f16(A[t], B[pu][q], zero16, 0, 0, 0);
+                float pm[4];
+                const uint32_t qmask = ~7u;
+                pm[0] = quad_min<0, true>(kk[0], kk[1], kk[2], kk[3], qmask, ninf);
+                pm[1] = quad_min<QPR == 1 ? 0 : 1, false>(kk[4], kk[5], kk[6], kk[7], qmask, ninf);
+                pm[2] = quad_min<QPR == 4 ? 2 : 0, false>(kk[8], kk[9], kk[10], kk[11], qmask, ninf);
+                pm[3] = quad_min<QPR == 4 ? 3 : (QPR == 2 ? 1 : 0), false>(kk[12], kk[13], kk[14],
+                                                                           kk[15], qmask, ninf);
+                if constexpr (QPR == 4) {
+                    float a1, a2;
+                    top2_3(pm[0], pm[1], pm[2], a1, a2);
+                    W[pu][0][q] = vmin2(a1, pm[3]);
+                    L[pu][0][q] = vmin2(a2, vmax2(a1, pm[3]));
+                } else if constexpr (QPR == 2) {
+                    W[pu][0][q] = vmin2(pm[0], pm[1]);
+                    L[pu][0][q] = vmax2(pm[0], pm[1]);
+                    W[pu][1][q] = vmin2(pm[2], pm[3]);
+                    L[pu][1][q] = vmax2(pm[2], pm[3]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        W[pu][j][q] = pm[j];
+                        L[pu][j][q] = INFINITY;
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < RT; ++j) {
+                const int r = t * RT + j;
+                if (r >= R || !((mask >> r) & 1)) continue;
+                const float4* rec = sm.scand[r];
+                const float4 bnd = sm.sbnd[r];
+                // both units' winners and certificates first (independent
+                // work), then their sums and queue entries
+                int base[PU], kk4[PU];
+                uint64_t mok[PU];
+#pragma unroll
+                for (int pu = 0; pu < PU; ++pu) {
+                    // halves merged as in the single fit: after the swaps,
+                    // w0 / l0 come from the h = 0 lane of the point, w1 / l1
+                    // from h = 1
+                    const auto ws = __builtin_amdgcn_permlane32_swap(
+                        __float_as_uint(W[pu][j][0]), __float_as_uint(W[pu][j][1]), false, false);
+                    const auto ls = __builtin_amdgcn_permlane32_swap(
+                        __float_as_uint(L[pu][j][0]), __float_as_uint(L[pu][j][1]), false, false);
+                    const float w0 = __uint_as_float(ws[0]), w1 = __uint_as_float(ws[1]);
+                    const float l0 = __uint_as_float(ls[0]), l1 = __uint_as_float(ls[1]);
+                    const float Wc = vmin2(w0, w1);
+                    const float Lc = vmin3(vmax2(w0, w1), l0, l1);
+                    const int hw = w1 < w0 ? 1 : 0;
+                    // the winning quad: centres 8 g + 4 hw + 0..3 of restart r
+                    const int g = QPR == 1 ? 0 : (int)(__float_as_uint(Wc) & 7u);
+                    base[pu] = (g << 3) | (hw << 2);
+                    const float s0 = expanded_key<D>(x0[pu], x1[pu], x2[pu], rec[base[pu]]);
+                    const float s1 = expanded_key<D>(x0[pu], x1[pu], x2[pu], rec[base[pu] + 1]);
+                    const float s2 = expanded_key<D>(x0[pu], x1[pu], x2[pu], rec[base[pu] + 2]);
+                    const float s3 = expanded_key<D>(x0[pu], x1[pu], x2[pu], rec[base[pu] + 3]);
+                    const float a3 = fminf(fminf(s0, s1), s2);
+                    const float t1 = fminf(a3, s3);
+                    const float t2 = fminf(__builtin_amdgcn_fmed3f(s0, s1, s2), fmaxf(a3, s3));
+                    int kq = 3;
+                    kq = s2 == t1 ? 2 : kq;
+                    kq = s1 == t1 ? 1 : kq;
+                    kq = s0 == t1 ? 0 : kq;
+                    kk4[pu] = kq;
+                    float b = fmaf(bnd.y, fabsf(x0[pu]), bnd.x);
+                    b = fmaf(bnd.z, fabsf(x1[pu]), b);
+                    if constexpr (D == 3) b = fmaf(bnd.w, fabsf(x2[pu]), b);
+                    const float bm = fmaf(b, bms, 17.0f);
+                    // the certificate as lane masks (no k < K test: pads key
+                    // above every real centre, in the matrix keys and in the
+                    // records)
+                    mok[pu] = __builtin_amdgcn_ballot_w64(Lc - Wc > bm) &
+                              __builtin_amdgcn_ballot_w64(t2 - t1 > b);
+                }
+#pragma unroll
+                for (int pu = 0; pu < PU; ++pu) {
+                    if (__builtin_amdgcn_inverse_ballot_w64(mv[pu] & mok[pu])) {
+                        unsigned long long* a = &myacc[r * (D + 1) * K + base[pu] + kk4[pu]];
+#pragma unroll
+                        for (int jj = 0; jj < D; ++jj)
+                            __hip_atomic_fetch_add(&a[jj * K], fb[pu][jj], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                        __hip_atomic_fetch_add(&a[D * K], 1ull, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                    const uint64_t m = mv[pu] & ~mok[pu];
+                    if (m) {
+                        const int below_m = (int)__builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                        if (__builtin_amdgcn_inverse_ballot_w64(m))
+                            wq[qn + below_m] = make_float4(x0[pu], x1[pu], x2[pu],
+                                                           __int_as_float((r << 27) | (int)i[pu]));
+                        qn += __popcll(m);
+                        if (qn >= 64) drain(64);
+                    }
+                }
+            }
+        }
+    }
+    if (qn > 0) drain(qn);
+}
+
+// The common scale exponent of the matrix-core keys for the active restarts
+// (mfma_scale of each), or false when one falls outside its range.
+__device__ __forceinline__ bool batched_mfma_scale(const BSmem& sm, int mask, int R, int xe,
+                                                   int& e) {
+    e = 1 << 20;
+    for (int r = 0; r < R; ++r) {
+        if (!((mask >> r) & 1)) continue;
+        int er;
+        if (!mfma_scale(xe, sm.sbnd[r], er)) return false;
+        e = er < e ? er : e;
+    }
+    return true;
+}
+
 // Objective partial of the block for restart r, summed over the waves in
 // order, into sm.J[r].
 __device__ void block_objective(BSmem& sm, int r, double jl) {
@@ -223,7 +474,7 @@ __device__ void block_objective(BSmem& sm, int r, double jl) {
 // Run instance `inst` to completion.  rank/S: this block's place in its team
 // (S = 1: alone).  Returns false when a team barrier timed out.
 template <int D>
-__device__ bool run_instance(BatchState* __restrict__ bs, int inst, int rank, int S, BTeam* tm,
+__device__ __attribute__((always_inline)) bool run_instance(BatchState* __restrict__ bs, int inst, int rank, int S, BTeam* tm,
                              unsigned long long* tpart, double* tjpart, uint32_t& nbar,
                              BSmem& sm) {
     const BInst in = bs->inst[inst];
@@ -262,7 +513,7 @@ __device__ bool run_instance(BatchState* __restrict__ bs, int inst, int rank, in
     }
     if (tid == 0) sm.active = bad ? 0 : (1 << R) - 1;
     __syncthreads();
-    for (int r = 0; r < R; ++r) prep_centres(sm.smu[r], K, 3 * ((K + 2) / 3), sm.scand[r], &sm.sbnd[r], sm.sc, sm.sa, am);
+    for (int r = 0; r < R; ++r) prep_centres(sm.smu[r], K, BK_KPAD, sm.scand[r], &sm.sbnd[r], sm.sc, sm.sa, am);
 
     double jl = 0.0;
     // ---- Lloyd updates of all active restarts
@@ -270,11 +521,22 @@ __device__ bool run_instance(BatchState* __restrict__ bs, int inst, int rank, in
         const int active = __builtin_amdgcn_readfirstlane(sm.active);
         if (!active) break;
         const int copies = acc_copies(nacc);
+        // the matrix-core keys for this update (labels are the same either way)
+        int e_mfma = 0;
+        const bool use_mfma = D == 3 && K >= bs->mfma_min_k &&
+                              batched_mfma_scale(sm, active, R, xe, e_mfma);
         for (int64_t g0 = 0; g0 < ngroups; g0 += chunk) {
             const int64_t g1 = g0 + chunk < ngroups ? g0 + chunk : ngroups;
             for (int i = tid; i < copies * nacc; i += BLOCK) sm.acc[i] = 0ull;
             __syncthreads();
-            points_pass<D, MODE_ACC>(in, rank, S, active, fscale, ninf, sm, jl, g0, g1);
+            if (!use_mfma)
+                points_pass<D, MODE_ACC>(in, rank, S, active, fscale, ninf, sm, jl, g0, g1);
+            else if (K <= 8)
+                points_pass_mfma<D, 8>(in, rank, S, active, fscale, ninf, e_mfma, sm, g0, g1);
+            else if (K <= 16)
+                points_pass_mfma<D, 16>(in, rank, S, active, fscale, ninf, e_mfma, sm, g0, g1);
+            else
+                points_pass_mfma<D, 32>(in, rank, S, active, fscale, ninf, e_mfma, sm, g0, g1);
             __syncthreads();
             // the chunk's sums: copies added, FXP_MAGIC_BITS removed once per
             // point (the count slot of the same restart and cluster), added to
@@ -379,12 +641,12 @@ __device__ bool run_instance(BatchState* __restrict__ bs, int inst, int rank, in
         const int still = __builtin_amdgcn_readfirstlane(sm.active);
         for (int r = 0; r < R; ++r)
             if ((still >> r) & 1)
-                prep_centres(sm.smu[r], K, 3 * ((K + 2) / 3), sm.scand[r], &sm.sbnd[r], sm.sc, sm.sa, am);
+                prep_centres(sm.smu[r], K, BK_KPAD, sm.scand[r], &sm.sbnd[r], sm.sc, sm.sa, am);
         __syncthreads();
     }
     if (!bad) {
         // ---- objective of every restart at its final centres
-        for (int r = 0; r < R; ++r) prep_centres(sm.smu[r], K, 3 * ((K + 2) / 3), sm.scand[r], &sm.sbnd[r], sm.sc, sm.sa, am);
+        for (int r = 0; r < R; ++r) prep_centres(sm.smu[r], K, BK_KPAD, sm.scand[r], &sm.sbnd[r], sm.sc, sm.sa, am);
         for (int r = 0; r < R; ++r) {
             jl = 0.0;
             points_pass<D, MODE_OBJ>(in, rank, S, 1 << r, fscale, ninf, sm, jl, 0, ngroups);

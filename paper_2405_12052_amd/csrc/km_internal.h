@@ -127,6 +127,7 @@ struct BatchState {
     const int32_t* order_small;// instances processed by single blocks, largest first
     int32_t n_inst, n_big, n_small;
     int32_t team_size;         // blocks per team (1 = no teams)
+    int32_t mfma_min_k;        // instances with K >= this take the matrix-core keys
     int32_t n_teams;
     int32_t max_iter;
     double tol;

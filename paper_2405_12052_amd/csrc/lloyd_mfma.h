@@ -221,6 +221,35 @@ __device__ __forceinline__ f16x8 zero_operand() {
     return __builtin_bit_cast(f16x8, r);
 }
 
+// The A operand of one centre row for lane half h (see the file header):
+// the record r = (a0, a1, a2, c) of a real centre at scale 2^e, or a pad's
+// single term P (with the half-1 constant P of the B operand: 2^30).
+template <int D>
+__device__ __forceinline__ f16x8 centre_operand(bool real, float4 r, int e, int h) {
+    const _Float16 z = 0;
+    if (real) {
+        _Float16 h0, l0, h1, l1, h2, l2;
+        split_f16(ldexpf(r.x, e), h0, l0);
+        split_f16(ldexpf(r.y, e), h1, l1);
+        split_f16(D == 3 ? ldexpf(r.z, e) : 0.0f, h2, l2);
+        // c' 2^-14 in three pieces
+        const float cs = ldexpf(r.w, 2 * e - 14);
+        const _Float16 c1 = (_Float16)cs;
+        const float r1 = cs - (float)c1;
+        const _Float16 c2 = (_Float16)r1;
+        const _Float16 c3 = (_Float16)(r1 - (float)c2);
+        if (h == 0) {
+            const f16x8 a = {h0, h0, h1, h1, l0, l1, c1, c2};
+            return a;
+        }
+        const f16x8 a = {h2, h2, z, z, l2, z, c3, z};
+        return a;
+    }
+    if (h == 0) return zero_operand();
+    const f16x8 a = {z, z, z, z, z, z, z, (_Float16)32768.0f};
+    return a;
+}
+
 // Scale exponent e of the matrix-core keys for data of exponent xe
 // (max|x| < 2^(xe+1)) and centres with bnd (the VALU bound coefficients:
 // bnd.y..w >= 2^-20 max_k |m_kj|); false when e falls outside [-24, 96].
@@ -248,7 +277,6 @@ __device__ __forceinline__ void assign_points_mfma(const float* __restrict__ X, 
                                                    float4* __restrict__ wq, Sink&& sink) {
     const int lane = threadIdx.x & 63;
     const int c = lane & 31, h = lane >> 5;
-    const uint64_t below = (1ull << lane) - 1ull;
     constexpr float T = 16384.0f, P = 32768.0f;
 
     // A operands (centre 32 t + c), fixed for the whole pass
@@ -256,35 +284,7 @@ __device__ __forceinline__ void assign_points_mfma(const float* __restrict__ X, 
 #pragma unroll
     for (int t = 0; t < KT; ++t) {
         const int k = 32 * t + c;
-        const _Float16 z = 0;
-        if (k < K) {
-            const float4 r = scand[k];
-            _Float16 h0, l0, h1, l1, h2, l2;
-            split_f16(ldexpf(r.x, e), h0, l0);
-            split_f16(ldexpf(r.y, e), h1, l1);
-            split_f16(D == 3 ? ldexpf(r.z, e) : 0.0f, h2, l2);
-            // c' 2^-14 in three pieces
-            const float cs = ldexpf(r.w, 2 * e - 14);
-            const _Float16 c1 = (_Float16)cs;
-            const float r1 = cs - (float)c1;
-            const _Float16 c2 = (_Float16)r1;
-            const _Float16 c3 = (_Float16)(r1 - (float)c2);
-            if (h == 0) {
-                const f16x8 a = {h0, h0, h1, h1, l0, l1, c1, c2};
-                A[t] = a;
-            } else {
-                const f16x8 a = {h2, h2, z, z, l2, z, c3, z};
-                A[t] = a;
-            }
-        } else {
-            const _Float16 p = (_Float16)P;
-            if (h == 0) {
-                A[t] = zero_operand();
-            } else {
-                const f16x8 a = {z, z, z, z, z, z, z, p};
-                A[t] = a;
-            }
-        }
+        A[t] = centre_operand<D>(k < K, k < K ? scand[k] : make_float4(0.f, 0.f, 0.f, 0.f), e, h);
     }
     const uint32_t hm = h ? ~0u : 0u;  // lane half as a bit mask
     const uint32_t q3 = h == 0 ? pack2((_Float16)T, (_Float16)T) : pack2((_Float16)T, (_Float16)P);

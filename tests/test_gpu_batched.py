@@ -126,6 +126,29 @@ def test_restart_groups_give_the_same_results(km, batch, group):
     km.set_batched_schedule(0, 0, 0.0, 0)
 
 
+@pytest.mark.parametrize("team", [8, 1])
+def test_matrix_core_pass_gives_the_same_results(km, batch, team):
+    """km_schedule.mfma_min_k: the update pass with matrix-core keys for the
+    3-D instances (all restarts' centres as rows of 32-row tiles, 8 / 16 / 32
+    rows per restart by K) against the VALU pass, on the same team layout:
+    every output is identical, the objectives included."""
+    specs, inst, host, _ = batch
+    km.set_batched_schedule(team, 2, 0.0, 0, 33)  # VALU keys only
+    base = km.fit_batched(inst, tol=1e-6, max_iter=300)
+    km.set_batched_schedule(team, 2, 0.0, 0, 1)   # matrix-core keys for every K
+    out = km.fit_batched(inst, tol=1e-6, max_iter=300)
+    km.set_batched_schedule(0, 0, 0.0, 0, 0)
+    ks = sorted({s.K for s in specs if s.d == 3})
+    assert ks[0] <= 8 and ks[-1] > 16, ks          # all three row widths are exercised
+    for s, a, b in zip(specs, base, out):
+        assert a["best_restart"] == b["best_restart"], s.name
+        assert np.array_equal(a["centroids"], b["centroids"]), s.name
+        assert a["iters"] == b["iters"] and a["E"] == b["E"], s.name
+        assert np.array_equal(a["restart_objective"], b["restart_objective"]), s.name
+        assert np.array_equal(a["restart_iters"], b["restart_iters"]), s.name
+        assert np.array_equal(a["labels"].cpu().numpy(), b["labels"].cpu().numpy()), s.name
+
+
 def test_batched_errors(km, batch):
     from paper_2405_12052_amd import KM_EINVAL, KM_EUNSUPPORTED, KMeansError
     specs, inst, host, dev = batch
@@ -142,6 +165,10 @@ def test_batched_errors(km, batch):
     with pytest.raises(KMeansError, match="NaN") as e:
         km.fit_batched([inst[1], (Xn, N, ini)])
     assert e.value.code == KM_EINVAL
+    for bad in ({"mfma_min_k": 34}, {"mfma_min_k": -1}, {"restart_group": 9}):
+        with pytest.raises(KMeansError) as e:
+            km.set_batched_schedule(8, 2, 0.0, **bad)
+        assert e.value.code == KM_EINVAL
     out = km.fit_batched(inst[:3])          # the context still works
     assert len(out) == 3
 
@@ -154,6 +181,7 @@ def test_tuner_and_cache(km, tmp_path):
     lines = open(cache).read().strip().splitlines()
     assert len(lines) == 1 and json.loads(lines[0])["team_size"] == best["team_size"]
     assert json.loads(lines[0])["restart_group"] == best["restart_group"]
+    assert json.loads(lines[0])["mfma_min_k"] == best["mfma_min_k"]
     again = km.tune_batched(inst, tol=1e-6, max_iter=300, cache_path=cache)
     assert again == best and len(open(cache).read().strip().splitlines()) == 1
     assert km.batched_schedule() == best
