@@ -4,16 +4,18 @@ TEST/TRAINING INFRASTRUCTURE: this script calls only the oracle and the input
 generators.  For each training instance (the C5 recipe -- 16 axis-aligned
 Gaussian components in [-50, 50]^3, Dirichlet weights, 1% uniform noise --
 drawn with N = 4096 points from seed base + i) it runs Lloyd's algorithm in
-the oracle from 4 seeded samples of K = 16 points (E < 1e-6 or 300 updates),
-keeps the restart with the smallest final objective, and stores its centres
+the oracle from 4 seeded samples of K = 16 points (E < 1e-6 or 300 updates)
+and, with --means-start, also from the generator's 16 component means (an
+informed start that usually reaches the best basin), keeps the run with the
+smallest final objective, and stores its centres
 normalised by the instance's point mean and scalar standard deviation
 (x - mean) / s with s^2 = mean over points and coordinates of (x - mean)^2,
 the same normalisation the network's input uses.
 
 Output: an .npz with seeds [n] int64, targets [n, 16, 3] float32, J [n]
 float64 (objective of the kept restart) and T [n, 4] int32 (updates per
-restart).  Usage:
-    python oracle/make_initnet_targets.py OUT.npz --n 200000 --base 1000000 --procs 8
+restart; with --means-start a fifth column for the informed start).  Usage:
+    python oracle/make_initnet_targets.py OUT.npz --n 200000 --base 1000000 --procs 8 [--means-start]
 """
 from __future__ import annotations
 
@@ -45,16 +47,21 @@ def normalise(X):
     return m, s
 
 
+MEANS_START = False
+
+
 def one(seed: int):
     import datagen
     import oracle
     oracle.threads(1)
     s = instance_spec(seed)
-    X, _ = datagen.generate(s, threads=1)
+    X, meta = datagen.generate(s, threads=1)
+    starts = [datagen.init_sample(X, s.N, K, seed * 16 + r) for r in range(RESTARTS)]
+    if MEANS_START:
+        starts.append(np.asarray(meta["centres"], np.float64))
     best = None
     Ts = []
-    for r in range(RESTARTS):
-        mu0 = datagen.init_sample(X, s.N, K, seed * 16 + r)
+    for mu0 in starts:
         f = oracle.fit(X, mu0, tol=1e-6, max_iter=300, labels=False)
         Ts.append(f["T"])
         if best is None or f["J"] < best["J"]:
@@ -70,7 +77,10 @@ def main():
     ap.add_argument("--n", type=int, default=200_000)
     ap.add_argument("--base", type=int, default=1_000_000)
     ap.add_argument("--procs", type=int, default=os.cpu_count() or 1)
+    ap.add_argument("--means-start", action="store_true")
     args = ap.parse_args()
+    global MEANS_START
+    MEANS_START = args.means_start
     seeds = list(range(args.base, args.base + args.n))
     t0 = time.time()
     res = []
