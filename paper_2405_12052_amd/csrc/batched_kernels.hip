@@ -110,33 +110,6 @@ __device__ bool team_barrier(BatchState* __restrict__ bs, BTeam* tm, uint32_t& n
     return *sflag != 0;
 }
 
-// load_group for the batched passes, through global-address-space loads:
-// flat loads also count against the LDS counter, so each wait for the
-// points would wait for the block's outstanding LDS atomics too.
-template <int D>
-__device__ __forceinline__ int load_group_g(bool vec, const float* __restrict__ X, int64_t ld,
-                                            int64_t N, int64_t g, float (&x)[D][4]) {
-    typedef const float __attribute__((address_space(1)))* gfp;
-    typedef float f32x4 __attribute__((ext_vector_type(4)));
-    typedef const f32x4 __attribute__((address_space(1)))* gf4p;
-    const gfp Xg = (gfp)X;
-    const int64_t i0 = g * 4;
-    if (vec && i0 + 4 <= N) {
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            const f32x4 v = *(gf4p)(Xg + j * ld + i0);
-            x[j][0] = v.x; x[j][1] = v.y; x[j][2] = v.z; x[j][3] = v.w;
-        }
-        return 4;
-    }
-    const int n = (int)((N - i0) < 4 ? (N - i0) : 4);
-#pragma unroll
-    for (int j = 0; j < D; ++j)
-#pragma unroll
-        for (int p = 0; p < 4; ++p) x[j][p] = p < n ? Xg[j * ld + i0 + p] : 0.0f;
-    return n;
-}
-
 // One pass over this block's share of the instance's points for the restarts
 // in `mask`: MODE_ACC adds the points to their clusters' integer sums,
 // MODE_OBJ adds the distances to jl, MODE_LABEL writes the labels.  MODE_OBJ
@@ -198,7 +171,7 @@ __device__ void points_pass(const BInst& in, int rank, int S, int mask, double f
         float x[D][4];
         int n = 0;
         if (g < g_hi) {
-            n = load_group_g<D>(vec, X, ld, N, g, x);
+            n = load_group_rt<D>(vec, X, ld, N, g, x);
         } else {
 #pragma unroll
             for (int j = 0; j < D; ++j)

@@ -140,11 +140,18 @@ __device__ __forceinline__ double fxp_mean(const i128& S, int xe, unsigned long 
 template <int D, bool VEC>
 __device__ __forceinline__ int load_group(const float* __restrict__ X, int64_t ld,
                                           int64_t N, int64_t g, float (&x)[D][4]) {
+    // global-address-space loads: flat loads also count against the LDS
+    // counter, so each wait for the points would wait for the block's
+    // outstanding LDS atomics too
+    typedef const float __attribute__((address_space(1)))* gfp;
+    typedef float f32x4 __attribute__((ext_vector_type(4)));
+    typedef const f32x4 __attribute__((address_space(1)))* gf4p;
+    const gfp Xg = (gfp)X;
     const int64_t i0 = g * 4;
     if (VEC && i0 + 4 <= N) {
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-            const float4 v = *reinterpret_cast<const float4*>(X + j * ld + i0);
+            const f32x4 v = *(gf4p)(Xg + j * ld + i0);
             x[j][0] = v.x; x[j][1] = v.y; x[j][2] = v.z; x[j][3] = v.w;
         }
         return 4;
@@ -153,7 +160,7 @@ __device__ __forceinline__ int load_group(const float* __restrict__ X, int64_t l
 #pragma unroll
     for (int j = 0; j < D; ++j)
 #pragma unroll
-        for (int p = 0; p < 4; ++p) x[j][p] = p < n ? X[j * ld + i0 + p] : 0.0f;
+        for (int p = 0; p < 4; ++p) x[j][p] = p < n ? Xg[j * ld + i0 + p] : 0.0f;
     return n;
 }
 

@@ -2,7 +2,8 @@
 device header (lloyd_device.h: nearest4 and its centre tables) is compiled
 for the host with g++ (tests/host_scan: a stand-in for the HIP runtime
 header; the one inline-assembly bitfield insert is replaced by the same bit
-operation in C), and run on adversarial inputs.  Every point the scan
+operation in C, and the clang vector type of the loads by a plain struct),
+and run on adversarial inputs.  Every point the scan
 certifies must carry the exact label -- the first index of the minimum of
 the float64 direct-form distance to the float32 centres, as the oracle
 computes it -- whatever the data: offsets far from the origin, outliers,
@@ -22,6 +23,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(os.path.dirname(HERE), "paper_2405_12052_amd", "csrc")
 BFI_ASM = 'asm("v_bfi_b32 %0, 31, %1, %2" : "=v"(r) : "s"(g), "v"(v));'
 BFI_C = "r = __uint_as_float((__float_as_uint(v) & ~31u) | ((uint32_t)g & 31u));"
+# the clang vector type of the global loads, as a plain struct for g++ (which
+# ignores the address-space attribute of the pointer typedefs)
+VEC4 = "typedef float f32x4 __attribute__((ext_vector_type(4)));"
+VEC4_C = "struct f32x4 { float x, y, z, w; };"
 
 
 @pytest.fixture(scope="module")
@@ -29,10 +34,11 @@ def scan(tmp_path_factory):
     d = tmp_path_factory.mktemp("host_scan")
     src = open(os.path.join(CSRC, "lloyd_device.h")).read()
     assert src.count(BFI_ASM) == 1, "the bitfield insert of with_index moved"
-    open(d / "lloyd_device_host.h", "w").write(src.replace(BFI_ASM, BFI_C))
+    assert src.count(VEC4) == 1, "the vector type of load_group moved"
+    open(d / "lloyd_device_host.h", "w").write(src.replace(BFI_ASM, BFI_C).replace(VEC4, VEC4_C))
     lib = d / "scan_host.so"
     cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-Wno-unknown-pragmas", "-I", str(d), "-I", os.path.join(HERE, "host_scan"),
+           "-fno-fast-math", "-Wno-unknown-pragmas", "-Wno-attributes", "-I", str(d), "-I", os.path.join(HERE, "host_scan"),
            "-I", CSRC, "-o", str(lib), os.path.join(HERE, "host_scan", "scan_host.cpp")]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-4000:]
