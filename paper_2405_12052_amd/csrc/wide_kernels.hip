@@ -42,6 +42,15 @@ struct WShape {
     static constexpr int P = D <= 16 ? 4 : 2;  // points per lane
 };
 
+// The points are read through global-address-space pointers: flat loads
+// also count against the LDS counter, so a wait for the points would wait
+// for outstanding LDS operations too.
+typedef const float __attribute__((address_space(1))) gfloat;
+typedef float f32x4g __attribute__((ext_vector_type(4)));
+typedef float f32x2g __attribute__((ext_vector_type(2)));
+typedef const f32x4g __attribute__((address_space(1))) gvec4;
+typedef const f32x2g __attribute__((address_space(1))) gvec2;
+
 // Load the P consecutive points starting at i0 (n of them exist) into
 // x[p][j]; coordinates j >= d are zero.
 template <int D, int P>
@@ -50,13 +59,13 @@ __device__ __forceinline__ void wide_load(const float* __restrict__ X, int64_t l
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         if (j < d) {
-            const float* row = X + (int64_t)j * ld + i0;
+            const gfloat* row = (const gfloat*)X + (int64_t)j * ld + i0;
             if (vec && n == P) {
                 if constexpr (P == 4) {
-                    const float4 v = *reinterpret_cast<const float4*>(row);
+                    const f32x4g v = *(const gvec4*)row;
                     x[0][j] = v.x; x[1][j] = v.y; x[2][j] = v.z; x[3][j] = v.w;
                 } else {
-                    const float2 v = *reinterpret_cast<const float2*>(row);
+                    const f32x2g v = *(const gvec2*)row;
                     x[0][j] = v.x; x[1][j] = v.y;
                 }
             } else {
@@ -727,19 +736,19 @@ __device__ __forceinline__ void wide_points_mfma(const WState* __restrict__ st, 
         // them: vector loads, or guarded 32-bit loads at the end of the data
         // or on unaligned rows)
         float x[H][PL];
-        const float* xrow = X + (int64_t)(h * H) * ld + i0;
+        const gfloat* xrow = (const gfloat*)X + (int64_t)(h * H) * ld + i0;
         if (vec && i0 + PL <= N) {
 #pragma unroll
             for (int jj = 0; jj < H; ++jj) {
                 if (h * H + jj < d) {
                     if constexpr (PL == 4) {
-                        const float4 v = *reinterpret_cast<const float4*>(xrow + (int64_t)jj * ld);
+                        const f32x4g v = *(const gvec4*)(xrow + (int64_t)jj * ld);
                         x[jj][0] = v.x;
                         x[jj][1] = v.y;
                         x[jj][2] = v.z;
                         x[jj][3] = v.w;
                     } else {
-                        const float2 v = *reinterpret_cast<const float2*>(xrow + (int64_t)jj * ld);
+                        const f32x2g v = *(const gvec2*)(xrow + (int64_t)jj * ld);
                         x[jj][0] = v.x;
                         x[jj][1] = v.y;
                     }
