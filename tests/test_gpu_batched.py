@@ -149,6 +149,43 @@ def test_matrix_core_pass_gives_the_same_results(km, batch, team):
         assert np.array_equal(a["labels"].cpu().numpy(), b["labels"].cpu().numpy()), s.name
 
 
+def test_matrix_core_pass_unaligned_rows(km):
+    """The matrix-core pass on rows that are not 16-byte aligned (offset by
+    one float, odd row stride) and N not a multiple of 64: the guarded
+    32-bit loads of every unit.  Identical to the VALU pass; the kept
+    restart of one instance matches the oracle."""
+    import dataclasses
+    specs = [s for s in datagen.batched_specs(40, seed=4242, n_range=(3.0, 4.3)) if s.d == 3][:6]
+    specs = [dataclasses.replace(s, K=min(k, s.N)) for s, k in zip(specs, (5, 12, 20, 32, 9, 27))]
+    flat, offs, inits = datagen.batched_generate(specs)
+    inst, host = [], []
+    for s, off, ini in zip(specs, offs, inits):
+        ld = s.N + 1                                  # odd stride
+        buf = torch.zeros(1 + s.d * ld, dtype=torch.float32, device="cuda")
+        Xh = flat[off:off + s.d * datagen.round_up(s.N, 4)].reshape(s.d, -1)[:, :s.N]
+        view = buf[1:].view(s.d, ld)                  # offset by one float
+        view[:, :s.N] = torch.from_numpy(np.ascontiguousarray(Xh)).cuda()
+        inst.append((view, s.N, ini))
+        host.append(np.ascontiguousarray(Xh))
+    assert any(s.N % 64 for s in specs)
+    km.set_batched_schedule(1, 2, 0.0, 0, 33)
+    base = km.fit_batched(inst, tol=1e-6, max_iter=300)
+    km.set_batched_schedule(1, 2, 0.0, 0, 1)
+    out = km.fit_batched(inst, tol=1e-6, max_iter=300)
+    km.set_batched_schedule(0, 0, 0.0, 0, 0)
+    for s, a, b in zip(specs, base, out):
+        assert a["best_restart"] == b["best_restart"], s.name
+        assert np.array_equal(a["centroids"], b["centroids"]), s.name
+        assert a["iters"] == b["iters"] and a["E"] == b["E"], s.name
+        assert np.array_equal(a["restart_objective"], b["restart_objective"]), s.name
+        assert np.array_equal(a["labels"].cpu().numpy(), b["labels"].cpu().numpy()), s.name
+    s, (X, N, ini), r = specs[3], inst[3], out[3]
+    ref = oracle.fit(host[3], ini[r["best_restart"]], tol=1e-6, max_iter=300)
+    assert r["iters"] == ref["T"], s.name
+    centre_check(r["centroids"], ref["mu"])
+    label_check(r["labels"].cpu().numpy(), host[3], r["centroids"])
+
+
 def test_batched_errors(km, batch):
     from paper_2405_12052_amd import KM_EINVAL, KM_EUNSUPPORTED, KMeansError
     specs, inst, host, dev = batch
