@@ -33,7 +33,7 @@
 // registers (four consecutive centres; group number g = 4 t + r / 4 in the 3
 // low mantissa bits: three instructions per quad), and a small tournament
 // over those packed minima gives W, the smallest, and L, the second smallest
-// (12 instructions for the 8 of K > 32).  The halves are merged
+// (10 instructions for the 8 of K > 32).  The halves are merged
 // with one lane swap per value (v_permlane32_swap), two chunks at a time, so
 // that lane half h then finishes chunk h.  The winning quad's four
 // centres (8 g + 4 hw + 0..3, hw the half that held it) are re-keyed on the
