@@ -501,12 +501,21 @@ __device__ __forceinline__ void finalize_update(State* __restrict__ st, IterSmem
     __syncthreads();
 }
 
+static_assert(KPAD <= BLOCK && KMAX <= BLOCK, "one table entry per thread");
+
 // One update per launch (replayed from a graph): the update's pass, then the
 // final block's update of the centres.
 template <int D, bool VEC, int KT, bool TRACK>
 __device__ __forceinline__ void iter_body(State* __restrict__ st, IterSmem& sm) {
     const int K = st->K;
-    stage_centres(st, K, sm.scand, sm.smu);
+    // the centre tables' loads go out before the done test (one round trip at
+    // the start of an update instead of two); KPAD and K are at most BLOCK
+    const int tid = threadIdx.x;
+    const float4 rc = tid < KPAD ? st->cand[tid] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 rm = tid < K ? st->mu32[tid] : make_float4(0.f, 0.f, 0.f, 0.f);
+    if (st->done) return;
+    if (tid < KPAD) sm.scand[tid] = rc;
+    if (tid < K) sm.smu[tid] = rm;
     __syncthreads();
     if (!update_pass<D, VEC, KT, TRACK>(st, sm, K, st->xe, st->bnd, st->minus_inf)) return;
     finalize_update<D, false, TRACK>(st, sm, K, st->xe);
@@ -514,7 +523,6 @@ __device__ __forceinline__ void iter_body(State* __restrict__ st, IterSmem& sm) 
 
 template <int D, bool VEC, int KT>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) void lloyd_iter(State* __restrict__ st) {
-    if (st->done) return;
     __shared__ IterSmem sm;
     iter_body<D, VEC, KT, false>(st, sm);
 }
@@ -522,7 +530,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
 // The same with indicator tracking (KM_OPT_TRACK).
 template <int D, bool VEC, int KT>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) void lloyd_iter_track(State* __restrict__ st) {
-    if (st->done) return;
     __shared__ IterSmem sm;
     iter_body<D, VEC, KT, true>(st, sm);
 }
