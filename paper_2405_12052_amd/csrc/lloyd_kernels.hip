@@ -452,6 +452,18 @@ __device__ __forceinline__ void finalize_update(State* __restrict__ st, IterSmem
     constexpr int R = D + 1;
     const int tid = threadIdx.x;
     const i128* tot = reinterpret_cast<const i128*>(sm.sacc);
+    // the state read at the end, loaded first: its round trip overlaps the
+    // centres' (only this block writes these fields during the update)
+    int t0 = 0, hcap = 0, max_iter = 0;
+    int64_t emp0 = 0;
+    double tol = 0.0;
+    if (tid == 0) {
+        t0 = rd<COH>(&st->t);
+        emp0 = rd<COH>(&st->empty_events);
+        hcap = st->hist_cap;
+        max_iter = st->max_iter;
+        tol = st->tol;
+    }
     if (tid < K) {
         const int k = tid;
         // the count's low 32 bits (cluster 0's carries the changed labels
@@ -482,19 +494,19 @@ __device__ __forceinline__ void finalize_update(State* __restrict__ st, IterSmem
         double E = 0.0;
         int emp = 0;
         for (int k = 0; k < K; ++k) { E += sm.u.fin.sE[k]; emp += sm.u.fin.sEmpty[k]; }
-        const int t = rd<COH>(&st->t);
-        if (t < st->hist_cap) { st->E_hist[t] = E; st->J_hist[t] = sm.sJ; }
-        int done = (E < st->tol || t + 1 >= st->max_iter) ? 1 : 0;
+        const int t = t0;
+        if (t < hcap) { st->E_hist[t] = E; st->J_hist[t] = sm.sJ; }
+        int done = (E < tol || t + 1 >= max_iter) ? 1 : 0;
         if constexpr (TRACK) {
             // the paper's other criterion: no indicator changed
             const long long chg = (long long)(tot[D].lo >> 32);
-            if (t < st->hist_cap) st->C_hist[t] = chg;
+            if (t < hcap) st->C_hist[t] = chg;
             st->changed = chg;
             if (chg == 0) done = 1;
         }
         wr<COH>(&st->t, t + 1);
         wr<COH>(&st->E, E);
-        wr<COH>(&st->empty_events, rd<COH>(&st->empty_events) + emp);
+        wr<COH>(&st->empty_events, emp0 + emp);
         wr<COH>(&st->done, done);
         sm.sdone = done;
     }
