@@ -902,18 +902,35 @@ __device__ void key_tables(const float* __restrict__ mu32, int K, int d, int DS,
                            float* __restrict__ hh, float* __restrict__ amax, uint32_t* sred) {
     const int tid = threadIdx.x, w = tid >> 6;
     const int kp = wide_kpad(K);
+    // Every wave runs the same number of passes over the rows (the wave
+    // maxima need all its lanes); a thread reads its row 8 coordinates per
+    // round trip, and each wave keeps its per-coordinate maxima in sred.
     uint32_t cmx = 0;
-    for (int k = tid; k < kp; k += WBLOCK) {
-        if (k < K) {
-            double q = 0.0;
-            for (int j = 0; j < d; ++j) {
-                const double m = mu32[k * DS + j];
-                q = fma(m, m, q);
+    for (int k0 = 0; k0 < kp; k0 += WBLOCK) {
+        const int k = k0 + tid;
+        const bool in = k < K;
+        double q = 0.0;
+        for (int j0 = 0; j0 < d; j0 += 8) {
+            float m[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) m[u] = in && j0 + u < d ? mu32[k * DS + j0 + u] : 0.0f;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (j0 + u < d) {
+                    q = fma((double)m[u], (double)m[u], q);
+                    const uint32_t b = wave_max(__float_as_uint(m[u]) & 0x7fffffffu);
+                    if ((tid & 63) == 0) {
+                        uint32_t& r = sred[w * (WD_MAX + 1) + j0 + u];
+                        r = k0 == 0 || b > r ? b : r;
+                    }
+                }
             }
+        }
+        if (in) {
             const float c = (float)q;
             hh[k] = -0.5f * c;
             cmx = __float_as_uint(c) > cmx ? __float_as_uint(c) : cmx;
-        } else {
+        } else if (k < kp) {
             hh[k] = -0x1p127f;
         }
     }
@@ -921,15 +938,6 @@ __device__ void key_tables(const float* __restrict__ mu32, int K, int d, int DS,
     // the waves: one barrier
     cmx = wave_max(cmx);
     if ((tid & 63) == 0) sred[w * (WD_MAX + 1) + WD_MAX] = cmx;
-    for (int j = 0; j < d; ++j) {
-        uint32_t m = 0;
-        for (int k = tid; k < K; k += WBLOCK) {
-            const uint32_t b = __float_as_uint(mu32[k * DS + j]) & 0x7fffffffu;
-            m = b > m ? b : m;
-        }
-        m = wave_max(m);
-        if ((tid & 63) == 0) sred[w * (WD_MAX + 1) + j] = m;
-    }
     __syncthreads();
     if (tid <= WD_MAX && (tid < d || tid == WD_MAX)) {
         uint32_t r = 0;
@@ -971,8 +979,16 @@ __device__ __forceinline__ double ordered_sum(int n, F v, double* sw) {
     if (tid < 64) {
         const int per = (n + 63) / 64;
         const int a = tid * per, b = a + per < n ? a + per : n;
+        // the terms are fetched 8 at a time, then added one by one
         double s = 0.0;
-        for (int i = a; i < b; ++i) s += v(i);
+        for (int i0 = a; i0 < b; i0 += 8) {
+            double t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t[u] = i0 + u < b ? v(i0 + u) : 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (i0 + u < b) s += t[u];
+        }
         sw[tid] = s;
     }
     __syncthreads();
@@ -1301,11 +1317,9 @@ __global__ __launch_bounds__(WBLOCK) void wide_reduce(WState* __restrict__ st) {
 
     // ---- last block: the mean step from the totals (device-coherent loads),
     // each slot cleared for the next update by the thread that read it
-    auto total = [&](int i) {
-        const unsigned long long l0 = ld_agent(&tot[i]);
-        const long long l1 = (long long)ld_agent(&tot[nacc + i]);
-        st_agent(&tot[i], 0ull);
-        st_agent(&tot[nacc + i], 0ull);
+    // a total from its two limbs: l1 2^32 + l0
+    auto limbs = [](unsigned long long l0, unsigned long long hi) {
+        const long long l1 = (long long)hi;
         i128 v = {(unsigned long long)l1 << 32, l1 >> 32};
         i128_add(v, i128{l0, 0ll});
         return v;
@@ -1316,20 +1330,55 @@ __global__ __launch_bounds__(WBLOCK) void wide_reduce(WState* __restrict__ st) {
     int emp = 0;
     long long chg = 0;
     for (int k = tid; k < K; k += WBLOCK) {
-        // slots [j * K + k]; the count in the low 32 bits (cluster 0's
-        // carries the changed labels above them, see wide_update_body)
-        const unsigned long long ct = total(d * K + k).lo;
+        // slots [j * K + k], j = d the count (low 32 bits; cluster 0's
+        // carries the changed labels above them, see wide_update_body).  The
+        // limbs go out in batches of 8 slots (the count with the first), each
+        // batch one round trip of device-coherent loads instead of one per
+        // slot, and every slot is cleared for the next update.
+        constexpr int BT = 8;
+        unsigned long long cl0 = 0ull, chi = 0ull, lo[BT], hi[BT];
+        auto load_batch = [&](int j0) {
+#pragma unroll
+            for (int u = 0; u < BT; ++u) {
+                lo[u] = 0ull;
+                hi[u] = 0ull;
+                if (j0 + u < d) {
+                    lo[u] = ld_agent(&tot[(j0 + u) * K + k]);
+                    hi[u] = ld_agent(&tot[nacc + (j0 + u) * K + k]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < BT; ++u) {
+                if (j0 + u < d) {
+                    st_agent(&tot[(j0 + u) * K + k], 0ull);
+                    st_agent(&tot[nacc + (j0 + u) * K + k], 0ull);
+                }
+            }
+        };
+        cl0 = ld_agent(&tot[d * K + k]);
+        chi = ld_agent(&tot[nacc + d * K + k]);
+        load_batch(0);
+        st_agent(&tot[d * K + k], 0ull);
+        st_agent(&tot[nacc + d * K + k], 0ull);
+        const unsigned long long ct = limbs(cl0, chi).lo;
         const unsigned long long cnt = ct & 0xffffffffull;
         if (k == 0) chg = (long long)(ct >> 32);
         double e = 0.0;
-        for (int j = 0; j < d; ++j) {
-            const i128 sj = total(j * K + k);
-            const double old = st->mu64[k * d + j];
-            const double v = cnt ? fxp_mean(sj, xe, cnt) : old;
-            const double sh = v - old;
-            e = fma(sh, sh, e);
-            st->mu64[k * d + j] = v;
-            st->mu32[k * DS + j] = (float)v;
+        for (int j0 = 0; j0 < d; j0 += BT) {
+            if (j0 > 0) load_batch(j0);
+#pragma unroll
+            for (int u = 0; u < BT; ++u) {
+                const int j = j0 + u;
+                if (j < d) {
+                    const i128 sj = limbs(lo[u], hi[u]);
+                    const double old = st->mu64[k * d + j];
+                    const double v = cnt ? fxp_mean(sj, xe, cnt) : old;
+                    const double sh = v - old;
+                    e = fma(sh, sh, e);
+                    st->mu64[k * d + j] = v;
+                    st->mu32[k * DS + j] = (float)v;
+                }
+            }
         }
         se[k] = e;
         emp += cnt == 0ull;
