@@ -1005,6 +1005,7 @@ __device__ __forceinline__ double ordered_sum(int n, F v, double* sw) {
 // centres.
 __global__ __launch_bounds__(WBLOCK) void wide_scan(WState* __restrict__ st) {
     __shared__ uint32_t sred[NW * (WD_MAX + 1)];
+    __shared__ uint32_t smx[NW];
     const int tid = threadIdx.x;
     if (blockIdx.x == 0)
         key_tables(st->mu32, st->K, st->d, wide_stride(wide_width(st->d)), st->hh, st->amax, sred);
@@ -1014,17 +1015,52 @@ __global__ __launch_bounds__(WBLOCK) void wide_scan(WState* __restrict__ st) {
     const int64_t stride = (int64_t)gridDim.x * WBLOCK;
     const int64_t t0 = (int64_t)blockIdx.x * WBLOCK + tid;
     for (int64_t i = t0; i < 2 * nacc; i += stride) st->tot[i] = 0ull;
+    // Each thread keeps 8 loads in flight (one at a time left the scan bound
+    // by memory latency): of 16 bytes where the rows allow, from the first
+    // whole group of 4, else of one float.
     uint32_t m = 0;
+    const int64_t ng = st->vec ? N >> 2 : 0;
     for (int j = 0; j < d; ++j) {
         const float* __restrict__ row = st->X + (int64_t)j * ld;
-        for (int64_t i = t0; i < N; i += stride) {
-            const uint32_t b = __float_as_uint(row[i]) & 0x7fffffffu;
-            m = b > m ? b : m;
+        const float4* __restrict__ row4 = reinterpret_cast<const float4*>(row);
+        for (int64_t g = t0; g < ng; g += 8 * stride) {
+            float4 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t p = g + u * stride;
+                v[u] = p < ng ? row4[p] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const uint32_t b0 = __float_as_uint(v[u].x) & 0x7fffffffu;
+                const uint32_t b1 = __float_as_uint(v[u].y) & 0x7fffffffu;
+                const uint32_t b2 = __float_as_uint(v[u].z) & 0x7fffffffu;
+                const uint32_t b3 = __float_as_uint(v[u].w) & 0x7fffffffu;
+                const uint32_t a = b0 > b1 ? b0 : b1, c = b2 > b3 ? b2 : b3;
+                const uint32_t e = a > c ? a : c;
+                m = e > m ? e : m;
+            }
+        }
+        for (int64_t i = 4 * ng + t0; i < N; i += 8 * stride) {
+            uint32_t b[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t p = i + u * stride;
+                b[u] = p < N ? __float_as_uint(row[p]) & 0x7fffffffu : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) m = b[u] > m ? b[u] : m;
         }
     }
     m = wave_max(m);
-    if ((tid & 63) == 0 && m) {
-        __hip_atomic_fetch_max(&st->absmax_bits, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((tid & 63) == 0) smx[tid >> 6] = m;
+    __syncthreads();
+    if (tid == 0) {
+        // one atomic per block, and only where it raises the stored maximum
+        m = 0;
+        for (int v = 0; v < NW; ++v) m = smx[v] > m ? smx[v] : m;
+        if (m > ld_agent(&st->absmax_bits))
+            __hip_atomic_fetch_max(&st->absmax_bits, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (m >= FXP_RANGE_BITS) {
             // NaN or infinity, or beyond the range of the fixed-point sums
             __hip_atomic_fetch_or(&st->flags,

@@ -347,6 +347,31 @@ def test_error_paths(km):
     centre_check(r.centroids, ref["mu"])
 
 
+
+@pytest.mark.parametrize("col, val, off", [(2001, np.nan, 0), (17, np.inf, 0), (1500, -np.inf, 1),
+                                           (2002, np.nan, 1)])
+def test_scan_stops_on_non_finite_coordinates(km, col, val, off):
+    """The data scan reads rows 16 bytes at a time where they are aligned and
+    one float at a time for the N % 4 tail and for unaligned rows; a NaN or
+    infinity in either part stops the fit and the assignment with an error."""
+    from paper_2405_12052_amd import KM_EINVAL, KMeansError
+    N = 2003
+    X = np.random.default_rng(2).normal(size=(16, N)).astype(np.float32)
+    X[11, col] = val
+    big = np.zeros((16, 2008), np.float32)            # ld % 4 == 0
+    big[:, off:off + N] = X
+    Xd = torch.from_numpy(big).cuda()[:, off:off + N]
+    assert (Xd.data_ptr() % 16 != 0) == bool(off) and Xd.stride(0) == 2008
+    mu = X[:, :40].T.astype(np.float64)
+    mu[~np.isfinite(mu)] = 0.0
+    with pytest.raises(KMeansError) as e:
+        km.fit(Xd, mu, N=N)
+    assert e.value.code == KM_EINVAL
+    with pytest.raises(KMeansError) as e:
+        km.assign(Xd, mu, N=N)
+    assert e.value.code == KM_EINVAL
+
+
 # ------------------------------------------- the benchmark's shape, sampled
 @pytest.fixture(scope="module")
 def w1():
