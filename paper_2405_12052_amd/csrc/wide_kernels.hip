@@ -51,6 +51,28 @@ typedef float f32x2g __attribute__((ext_vector_type(2)));
 typedef const f32x4g __attribute__((address_space(1))) gvec4;
 typedef const f32x2g __attribute__((address_space(1))) gvec2;
 
+// The same for loads and stores of the state's arrays where a wave also
+// exchanges values across lanes (LDS operations): device-coherent (relaxed,
+// device scope) and plain, through global-address-space pointers.
+template <typename T>
+__device__ __forceinline__ T gld_agent(const T* p) {
+    return __hip_atomic_load((const T __attribute__((address_space(1)))*)p, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void gst_agent(T* p, T v) {
+    __hip_atomic_store((T __attribute__((address_space(1)))*)p, v, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T gld(const T* p) {
+    return *(const T __attribute__((address_space(1)))*)p;
+}
+template <typename T>
+__device__ __forceinline__ void gst(T* p, T v) {
+    *(T __attribute__((address_space(1)))*)p = v;
+}
+
 // Load the P consecutive points starting at i0 (n of them exist) into
 // x[p][j]; coordinates j >= d are zero.
 template <int D, int P>
@@ -1351,8 +1373,12 @@ __global__ __launch_bounds__(WBLOCK) void wide_reduce(WState* __restrict__ st) {
     __syncthreads();
     if (!sflag) return;
 
-    // ---- last block: the mean step from the totals (device-coherent loads),
-    // each slot cleared for the next update by the thread that read it
+    // ---- last block: the mean step from the totals (device-coherent loads)
+    // and the key tables of the new float32 centres, from the values the
+    // threads hold (the arithmetic of key_tables, in its order).  A load
+    // waits for every store issued before it, so each batch's loads go out
+    // before the previous batch's stores, and the totals are cleared for
+    // the next update at the end.
     // a total from its two limbs: l1 2^32 + l0
     auto limbs = [](unsigned long long l0, unsigned long long hi) {
         const long long l1 = (long long)hi;
@@ -1363,65 +1389,95 @@ __global__ __launch_bounds__(WBLOCK) void wide_reduce(WState* __restrict__ st) {
     double* se = reinterpret_cast<double*>(wsm);
     const int xe = data_exponent(st->absmax_bits);
     const int DS = wide_stride(wide_width(d));
+    double* mu64 = st->mu64;
+    float* mu32 = st->mu32;
+    float* hh = st->hh;
+    const int w = tid >> 6;
     int emp = 0;
     long long chg = 0;
-    for (int k = tid; k < K; k += WBLOCK) {
+    uint32_t cmx = 0;
+    // every wave runs the same number of passes (the per-coordinate wave
+    // maxima need all its lanes); lanes past K hold zeros
+    for (int k0 = 0; k0 < K; k0 += WBLOCK) {
+        const int k = k0 + tid;
+        const bool in = k < K;
         // slots [j * K + k], j = d the count (low 32 bits; cluster 0's
-        // carries the changed labels above them, see wide_update_body).  The
-        // limbs go out in batches of 8 slots (the count with the first), each
-        // batch one round trip of device-coherent loads instead of one per
-        // slot, and every slot is cleared for the next update.
+        // carries the changed labels above them, see wide_update_body); the
+        // limbs and the old centre go out in batches of 8 coordinates, one
+        // round trip each
         constexpr int BT = 8;
-        unsigned long long cl0 = 0ull, chi = 0ull, lo[BT], hi[BT];
+        unsigned long long lo[BT], hi[BT];
+        double od[BT];
         auto load_batch = [&](int j0) {
 #pragma unroll
             for (int u = 0; u < BT; ++u) {
                 lo[u] = 0ull;
                 hi[u] = 0ull;
-                if (j0 + u < d) {
-                    lo[u] = ld_agent(&tot[(j0 + u) * K + k]);
-                    hi[u] = ld_agent(&tot[nacc + (j0 + u) * K + k]);
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < BT; ++u) {
-                if (j0 + u < d) {
-                    st_agent(&tot[(j0 + u) * K + k], 0ull);
-                    st_agent(&tot[nacc + (j0 + u) * K + k], 0ull);
+                od[u] = 0.0;
+                if (in && j0 + u < d) {
+                    lo[u] = gld_agent(&tot[(j0 + u) * K + k]);
+                    hi[u] = gld_agent(&tot[nacc + (j0 + u) * K + k]);
+                    od[u] = gld(&mu64[k * d + j0 + u]);
                 }
             }
         };
-        cl0 = ld_agent(&tot[d * K + k]);
-        chi = ld_agent(&tot[nacc + d * K + k]);
+        unsigned long long cl0 = 0ull, chi = 0ull;
+        if (in) {
+            cl0 = gld_agent(&tot[d * K + k]);
+            chi = gld_agent(&tot[nacc + d * K + k]);
+        }
         load_batch(0);
-        st_agent(&tot[d * K + k], 0ull);
-        st_agent(&tot[nacc + d * K + k], 0ull);
         const unsigned long long ct = limbs(cl0, chi).lo;
         const unsigned long long cnt = ct & 0xffffffffull;
         if (k == 0) chg = (long long)(ct >> 32);
-        double e = 0.0;
+        double e = 0.0, q = 0.0;
         for (int j0 = 0; j0 < d; j0 += BT) {
-            if (j0 > 0) load_batch(j0);
+            double nv[BT];
 #pragma unroll
             for (int u = 0; u < BT; ++u) {
                 const int j = j0 + u;
+                nv[u] = 0.0;
                 if (j < d) {
-                    const i128 sj = limbs(lo[u], hi[u]);
-                    const double old = st->mu64[k * d + j];
-                    const double v = cnt ? fxp_mean(sj, xe, cnt) : old;
-                    const double sh = v - old;
+                    const double v = cnt ? fxp_mean(limbs(lo[u], hi[u]), xe, cnt) : od[u];
+                    const double sh = v - od[u];
                     e = fma(sh, sh, e);
-                    st->mu64[k * d + j] = v;
-                    st->mu32[k * DS + j] = (float)v;
+                    nv[u] = v;
+                    const float m = (float)v;
+                    q = fma((double)m, (double)m, q);
+                    const uint32_t bm = wave_max(__float_as_uint(m) & 0x7fffffffu);
+                    if ((tid & 63) == 0) {
+                        uint32_t& r = sred[w * (WD_MAX + 1) + j];
+                        r = k0 == 0 || bm > r ? bm : r;
+                    }
+                }
+            }
+            if (j0 + BT < d) load_batch(j0 + BT);
+#pragma unroll
+            for (int u = 0; u < BT; ++u) {
+                if (in && j0 + u < d) {
+                    gst(&mu64[k * d + j0 + u], nv[u]);
+                    gst(&mu32[k * DS + j0 + u], (float)nv[u]);
                 }
             }
         }
-        se[k] = e;
-        emp += cnt == 0ull;
+        if (in) {
+            se[k] = e;
+            emp += cnt == 0ull;
+            const float c = (float)q;
+            gst(&hh[k], -0.5f * c);
+            cmx = __float_as_uint(c) > cmx ? __float_as_uint(c) : cmx;
+        }
     }
+    for (int k = K + tid; k < wide_kpad(K); k += WBLOCK) gst(&hh[k], -0x1p127f);
     if (emp) atomicAdd(&sempty, emp);
+    cmx = wave_max(cmx);
+    if ((tid & 63) == 0) sred[w * (WD_MAX + 1) + WD_MAX] = cmx;
     __syncthreads();
-    key_tables(st->mu32, K, d, DS, st->hh, st->amax, sred);
+    if (tid <= WD_MAX && (tid < d || tid == WD_MAX)) {
+        uint32_t r = 0;
+        for (int v = 0; v < NW; ++v) r = sred[v * (WD_MAX + 1) + tid] > r ? sred[v * (WD_MAX + 1) + tid] : r;
+        st->amax[tid] = __uint_as_float(r);
+    }
     const double E = ordered_sum(K, [&](int k) { return se[k]; }, sw);
     __syncthreads();
     const double* jp = st->jpart;
@@ -1445,6 +1501,8 @@ __global__ __launch_bounds__(WBLOCK) void wide_reduce(WState* __restrict__ st) {
         st->done = done;
         st_agent(&st->ticket, 0u);
     }
+    // the totals, zero for the next update
+    for (int i = tid; i < 2 * nacc; i += WBLOCK) gst_agent(&tot[i], 0ull);
 }
 
 // Reassignment only: labels and the objective at the current centres.
