@@ -47,6 +47,29 @@ class km_instance(C.Structure):
                 ("res", km_result)]
 
 
+def _instance_dtype():
+    """numpy view of km_instance (same field offsets and size), so that a whole
+    batch's descriptors are filled and read column by column."""
+    f, r = km_instance, km_result
+    ro = f.res.offset
+    fields = [("X", np.uint64, f.X.offset), ("N", np.int64, f.N.offset), ("ld", np.int64, f.ld.offset),
+              ("d", np.int32, f.d.offset), ("K", np.int32, f.K.offset),
+              ("n_restarts", np.int32, f.n_restarts.offset), ("init", np.uint64, f.init.offset),
+              ("centroids_out", np.uint64, f.centroids_out.offset),
+              ("labels_out", np.uint64, f.labels_out.offset),
+              ("restart_objective", np.uint64, f.restart_objective.offset),
+              ("restart_iters", np.uint64, f.restart_iters.offset),
+              ("best_restart", np.int32, f.best_restart.offset),
+              ("iters", np.int32, ro + r.iters.offset), ("converged", np.int32, ro + r.converged.offset),
+              ("E", np.float64, ro + r.E.offset), ("objective", np.float64, ro + r.objective.offset),
+              ("empty_events", np.int64, ro + r.empty_events.offset)]
+    return np.dtype({"names": [n for n, _, _ in fields], "formats": [t for _, t, _ in fields],
+                     "offsets": [o for _, _, o in fields], "itemsize": C.sizeof(km_instance)})
+
+
+_KM_INSTANCE_DT = _instance_dtype()
+
+
 class km_schedule(C.Structure):
     _fields_ = [("team_size", C.c_int32), ("blocks_per_cu", C.c_int32), ("big_work", C.c_double),
                 ("restart_group", C.c_int32), ("mfma_min_k", C.c_int32)]
@@ -241,43 +264,71 @@ class KMeans:
     def _instances(self, instances, labels):
         """instances: sequence of (X, N, init) with X a float32 CUDA tensor of
         shape (d, >= N) (unit stride along the points) and init an array of
-        shape (R, K, d)."""
+        shape (R, K, d).  Returns the descriptor array (numpy, km_instance
+        layout) and the buffers it points into: every instance's initial
+        centres, outputs and labels are slices of one buffer each."""
+        t = self._torch
         n = len(instances)
-        arr = (km_instance * n)()
-        keep = []
+        shp = np.empty((n, 6), np.int64)  # X, N, ld, d, K, R
+        inits = []
         for i, (X, N, init) in enumerate(instances):
             ptr, n_pts, ld, d = self._points(X, N)
             mu0 = _f64(init)
             if mu0.ndim != 3 or mu0.shape[2] != d:
                 raise ValueError("init must have shape (restarts, K, d)")
-            R, K = mu0.shape[0], mu0.shape[1]
-            out = np.empty((K, d), np.float64)
-            robj = np.empty(R, np.float64)
-            rit = np.empty(R, np.int32)
-            lab = self._torch.empty(n_pts, dtype=self._torch.int32, device=X.device) if labels else None
-            a = arr[i]
-            a.X, a.N, a.ld, a.d, a.K, a.n_restarts = ptr, n_pts, ld, d, K, R
-            a.init = _dptr(mu0)
-            a.centroids_out = _dptr(out)
-            a.labels_out = lab.data_ptr() if labels else None
-            a.restart_objective = _dptr(robj)
-            a.restart_iters = rit.ctypes.data_as(C.POINTER(C.c_int32))
-            keep.append((mu0, out, robj, rit, lab))
-        return arr, keep
+            shp[i] = (ptr, n_pts, ld, d, mu0.shape[1], mu0.shape[0])
+            inits.append(mu0.ravel())
+        Ns, ds, Ks, Rs = shp[:, 1], shp[:, 3], shp[:, 4], shp[:, 5]
+
+        def offsets(sizes):
+            o = np.zeros(n + 1, np.int64)
+            np.cumsum(sizes, out=o[1:])
+            return o
+
+        io, co, ro = offsets(Rs * Ks * ds), offsets(Ks * ds), offsets(Rs)
+        ibuf = np.concatenate(inits) if n else np.empty(0)
+        cbuf = np.empty(int(co[-1]), np.float64)
+        robj = np.empty(int(ro[-1]), np.float64)
+        rit = np.empty(int(ro[-1]), np.int32)
+        a = np.zeros(n, _KM_INSTANCE_DT)
+        a["X"], a["N"], a["ld"] = shp[:, 0], Ns, shp[:, 2]
+        a["d"], a["K"], a["n_restarts"] = ds, Ks, Rs
+        a["init"] = ibuf.ctypes.data + 8 * io[:-1]
+        a["centroids_out"] = cbuf.ctypes.data + 8 * co[:-1]
+        a["restart_objective"] = robj.ctypes.data + 8 * ro[:-1]
+        a["restart_iters"] = rit.ctypes.data + 4 * ro[:-1]
+        lab = None
+        if labels and n:
+            lo = offsets(Ns)
+            lab = t.empty(int(lo[-1]), dtype=t.int32, device=instances[0][0].device)
+            a["labels_out"] = lab.data_ptr() + 4 * lo[:-1]
+        keep = {"shape": shp, "offsets": (co, ro), "bufs": (ibuf, cbuf, robj, rit), "labels": lab}
+        return a, keep
+
+    @staticmethod
+    def _instance_ptr(a):
+        return a.ctypes.data_as(C.POINTER(km_instance))
 
     def fit_batched(self, instances, tol=1e-6, max_iter=300, labels=True):
         """Independent fits of many instances with restarts in one persistent
         launch; returns one dict per instance (kept restart)."""
-        arr, keep = self._instances(instances, labels)
-        self._check(self._lib.kmeans_fit_batched(self._ctx, len(instances), arr, float(tol),
-                                                 int(max_iter)))
+        a, keep = self._instances(instances, labels)
+        self._check(self._lib.kmeans_fit_batched(self._ctx, len(instances), self._instance_ptr(a),
+                                                 float(tol), int(max_iter)))
+        shp, (co, ro), (_, cbuf, robj, rit), lab = (keep["shape"], keep["offsets"], keep["bufs"],
+                                                    keep["labels"])
+        Ns, ds, Ks = shp[:, 1].tolist(), shp[:, 3].tolist(), shp[:, 4].tolist()
+        labs = lab.split(Ns) if lab is not None else [None] * len(Ns)
+        co, ro = co.tolist(), ro.tolist()
+        best, iters, conv = a["best_restart"].tolist(), a["iters"].tolist(), a["converged"].tolist()
+        E, obj, emp = a["E"].tolist(), a["objective"].tolist(), a["empty_events"].tolist()
         res = []
-        for i, (mu0, out, robj, rit, lab) in enumerate(keep):
-            r = arr[i].res
-            res.append({"centroids": out, "labels": lab, "best_restart": arr[i].best_restart,
-                        "restart_objective": robj, "restart_iters": rit, "iters": r.iters,
-                        "converged": bool(r.converged), "E": r.E, "objective": r.objective,
-                        "empty_events": r.empty_events})
+        for i in range(len(Ns)):
+            res.append({"centroids": cbuf[co[i]:co[i + 1]].reshape(Ks[i], ds[i]), "labels": labs[i],
+                        "best_restart": best[i], "restart_objective": robj[ro[i]:ro[i + 1]],
+                        "restart_iters": rit[ro[i]:ro[i + 1]], "iters": iters[i],
+                        "converged": bool(conv[i]), "E": E[i], "objective": obj[i],
+                        "empty_events": emp[i]})
         return res
 
     def set_batched_schedule(self, team_size=0, blocks_per_cu=0, big_work=0.0, restart_group=0,
@@ -294,10 +345,11 @@ class KMeans:
 
     def tune_batched(self, instances, tol=1e-6, max_iter=300, cache_path=None):
         """Search the batched schedule on `instances`; keeps the fastest."""
-        arr, keep = self._instances(instances, False)
+        a, keep = self._instances(instances, False)
         s = km_schedule()
         cp = cache_path.encode() if cache_path else None
-        self._check(self._lib.kmeans_tune_batched(self._ctx, len(instances), arr, float(tol),
+        self._check(self._lib.kmeans_tune_batched(self._ctx, len(instances), self._instance_ptr(a),
+                                                  float(tol),
                                                   int(max_iter), cp, C.byref(s)))
         return {"team_size": s.team_size, "blocks_per_cu": s.blocks_per_cu, "big_work": s.big_work,
                 "restart_group": s.restart_group, "mfma_min_k": s.mfma_min_k}

@@ -101,3 +101,34 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_binding, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="missing"):
         _binding.load_library()
+
+
+def test_batched_descriptor_view_matches_the_struct():
+    """The binding fills a batch's km_instance descriptors as one numpy record
+    array; every field written through it reads back through the ctypes
+    structure (and the result fields the library writes read back through it)."""
+    import numpy as np
+
+    from paper_2405_12052_amd import _binding as b
+
+    dt = b._KM_INSTANCE_DT
+    assert dt.itemsize == ctypes.sizeof(b.km_instance)
+    a = np.zeros(3, dt)
+    a["X"] = [0x1000, 0x2000, 0x3000]
+    a["N"], a["ld"], a["d"], a["K"], a["n_restarts"] = [5, 6, 7], [8, 8, 12], [2, 3, 2], [4, 5, 6], [1, 8, 3]
+    a["init"], a["centroids_out"], a["labels_out"] = [16, 32, 48], [64, 80, 96], [0, 112, 128]
+    a["restart_objective"], a["restart_iters"] = [144, 160, 176], [192, 208, 224]
+    s = (b.km_instance * 3).from_buffer(a)
+    for i in range(3):
+        assert s[i].X == int(a["X"][i]) and s[i].N == a["N"][i] and s[i].ld == a["ld"][i]
+        assert (s[i].d, s[i].K, s[i].n_restarts) == (a["d"][i], a["K"][i], a["n_restarts"][i])
+        assert ctypes.cast(s[i].init, ctypes.c_void_p).value == int(a["init"][i])
+        assert ctypes.cast(s[i].centroids_out, ctypes.c_void_p).value == int(a["centroids_out"][i])
+        assert (s[i].labels_out or 0) == int(a["labels_out"][i])
+        assert ctypes.cast(s[i].restart_objective, ctypes.c_void_p).value == int(a["restart_objective"][i])
+        assert ctypes.cast(s[i].restart_iters, ctypes.c_void_p).value == int(a["restart_iters"][i])
+        s[i].best_restart, s[i].res.iters, s[i].res.converged = i + 1, 10 * i, i % 2
+        s[i].res.E, s[i].res.objective, s[i].res.empty_events = 0.5 * i, 2.0 * i, 3 * i
+    assert a["best_restart"].tolist() == [1, 2, 3] and a["iters"].tolist() == [0, 10, 20]
+    assert a["converged"].tolist() == [0, 1, 0] and a["E"].tolist() == [0.0, 0.5, 1.0]
+    assert a["objective"].tolist() == [0.0, 2.0, 4.0] and a["empty_events"].tolist() == [0, 3, 6]

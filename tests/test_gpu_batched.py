@@ -49,6 +49,29 @@ def batch():
     return make_batch(40, 777, restarts=8)
 
 
+
+def test_instances_in_separate_allocations(km, batch):
+    """The same instances with their points in separate device allocations (and
+    an unaligned copy) as in one flat tensor: identical results, labels
+    included (the descriptors carry every pointer as given)."""
+    specs, inst, host, _ = batch
+    sub = inst[:6]
+    base = km.fit_batched(sub, tol=1e-6, max_iter=300)
+    sep = []
+    for q, (X, N, ini) in enumerate(sub):
+        if q == 2:      # rows off 16-byte alignment, odd ld
+            big = torch.zeros((X.shape[0], N + 2), dtype=torch.float32, device="cuda")
+            big[:, 1:N + 1] = X[:, :N]
+            sep.append((big[:, 1:], N, ini))
+        else:
+            sep.append((X.clone(), N, ini))
+    out = km.fit_batched(sep, tol=1e-6, max_iter=300)
+    for a, b in zip(base, out):
+        assert np.array_equal(a["centroids"], b["centroids"]) and a["iters"] == b["iters"]
+        assert np.array_equal(a["restart_objective"], b["restart_objective"])
+        assert a["best_restart"] == b["best_restart"] and a["E"] == b["E"]
+        assert np.array_equal(a["labels"].cpu().numpy(), b["labels"].cpu().numpy())
+
 def test_every_restart_equals_a_single_fit(km, batch):
     specs, inst, host, _ = batch
     out = km.fit_batched(inst, tol=1e-6, max_iter=300)
