@@ -739,6 +739,11 @@ __device__ __forceinline__ void wide_points_mfma(const WState* __restrict__ st, 
     const float ninf = -st->plus_inf;
     const float4* grow = reinterpret_cast<const float4*>(st->mu32);
     const float* __restrict__ ghh = st->hh;
+    // the winning quads' rows and key constants, gathered through global-
+    // address-space pointers (a flat load would also wait for the wave's LDS
+    // operand reads)
+    const gvec4* growg = (const gvec4*)st->mu32;
+    const gfloat* hhg = (const gfloat*)st->hh;
     const WBound wb = wide_bound(d, amax);
     const int KT = (K + 31) / 32;
     const float sc = ldexpf(1.0f, e);
@@ -874,10 +879,10 @@ __device__ __forceinline__ void wide_points_mfma(const WState* __restrict__ st, 
             for (int u = 0; u < 4; ++u) {
                 const int k = base + u;
                 const int kk = k < K ? k : K - 1;
-                float v = ghh[kk];
+                float v = hhg[kk];
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
-                    const float4 m = grow[kk * NB + b];
+                    const f32x4g m = growg[kk * NB + b];
                     const float mv[4] = {m.x, m.y, m.z, m.w};
 #pragma unroll
                     for (int w2 = 0; w2 < 4; ++w2) {
